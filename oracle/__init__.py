@@ -1,0 +1,305 @@
+"""FP64 CPU oracle for the PSM hot path -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, the smoke check and the benchmark's CPU-baseline leg may import
+this package.  It wraps ``liboracle.so`` (plain C, see ``oracle.c``) with
+ctypes and numpy; it shares no code with the HIP path and never imports it.
+
+The oracle works on full distribution functions f (not deviations) in FP64,
+with a two-buffer pull streaming scheme.  PDF arrays are direction-major,
+``f[i, n]`` with n = x + nx*(y + ny*z) and the oracle's own direction order
+(:func:`lattice`).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+FACE = {"periodic": 0, "wall": 1, "inlet": 2, "outlet": 3}
+
+
+def build(force: bool = True) -> str:
+    """Compile liboracle.so with gcc (FP64, OpenMP, no FP contraction)."""
+    if force or not os.path.exists(_LIB_PATH):
+        cmd = ["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+               "-fno-fast-math", os.path.join(_HERE, "oracle.c"), "-lm", "-o", _LIB_PATH + ".tmp"]
+        subprocess.check_call(cmd)
+        os.replace(_LIB_PATH + ".tmp", _LIB_PATH)
+    return _LIB_PATH
+
+
+class Config(C.Structure):
+    _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int), ("q", C.c_int),
+                ("tau", C.c_double), ("magic", C.c_double), ("force", C.c_double * 3),
+                ("bc", C.c_int * 6), ("u_in", C.c_double * 3), ("sc", C.c_int), ("psm", C.c_int)]
+
+
+class Pose(C.Structure):
+    _fields_ = [("R", C.c_double * 9), ("X", C.c_double * 3), ("V", C.c_double * 3), ("W", C.c_double * 3)]
+
+
+class Geom(C.Structure):
+    _fields_ = [("kind", C.c_int), ("p", C.c_double * 3), ("s", C.c_int), ("mmin", C.c_int * 3),
+                ("dims", C.c_int * 3), ("inside", C.c_void_p), ("r_bound", C.c_double)]
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build()
+        L = C.CDLL(_LIB_PATH)
+        dp = C.POINTER(C.c_double)
+        L.or_lattice.argtypes = [C.c_int, C.POINTER(C.c_int), dp, C.POINTER(C.c_int)]
+        L.or_feq.argtypes = [C.c_int, C.c_double, dp, dp]
+        L.or_feq.restype = None
+        L.or_pose_at.argtypes = [dp, C.c_double, C.c_double, dp, dp, C.c_longlong, C.POINTER(Pose)]
+        L.or_pose_at.restype = None
+        L.or_collide_cell.argtypes = [C.POINTER(Config), dp, C.c_int, dp, dp, dp, dp]
+        L.or_step.argtypes = [C.POINTER(Config), dp, dp, C.c_int, dp, C.POINTER(Pose), dp]
+        L.or_macro.argtypes = [C.POINTER(Config), dp, dp, dp]
+        L.or_macro.restype = None
+        L.or_mass.argtypes = [C.POINTER(Config), dp]
+        L.or_mass.restype = C.c_double
+        L.or_geom_inside.argtypes = [C.POINTER(Geom), C.c_longlong, C.c_longlong, C.c_longlong]
+        L.or_map_cell.argtypes = [C.POINTER(Geom), C.POINTER(Pose), C.c_int, C.c_int, C.c_int]
+        L.or_map_cell.restype = C.c_double
+        L.or_map.argtypes = [C.POINTER(Config), C.POINTER(Geom), C.POINTER(Pose), C.c_int, dp]
+        L.or_b_from_eps.argtypes = [C.c_double, C.c_double, C.c_int]
+        L.or_b_from_eps.restype = C.c_float
+        L.or_winding.argtypes = [dp, C.POINTER(C.c_int), C.c_longlong, dp]
+        L.or_winding.restype = C.c_double
+        L.or_voxelize.argtypes = [dp, C.POINTER(C.c_int), C.c_longlong, C.c_int, C.POINTER(C.c_int),
+                                  C.POINTER(C.c_int), C.POINTER(C.c_ubyte)]
+        L.or_mesh_volume.argtypes = [dp, C.POINTER(C.c_int), C.c_longlong]
+        L.or_mesh_volume.restype = C.c_double
+        _lib = L
+    return _lib
+
+
+def _dp(a):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _ip(a):
+    assert a.dtype == np.int32 and a.flags.c_contiguous
+    return a.ctypes.data_as(C.POINTER(C.c_int))
+
+
+# ----------------------------------------------------------------------------
+def lattice(q: int):
+    """(c (q,3) int, w (q,) float64, opp (q,) int) in the oracle's order."""
+    c = np.zeros(q * 3, dtype=np.int32)
+    w = np.zeros(q, dtype=np.float64)
+    opp = np.zeros(q, dtype=np.int32)
+    if lib().or_lattice(q, _ip(c), _dp(w), _ip(opp)) != 0:
+        raise ValueError(q)
+    return c.reshape(q, 3), w, opp
+
+
+def feq(q: int, rho: float, u) -> np.ndarray:
+    out = np.zeros(q)
+    u = np.asarray(u, dtype=np.float64)
+    lib().or_feq(q, rho, _dp(u), _dp(out))
+    return out
+
+
+def make_config(wl=None, **kw) -> Config:
+    """or_config from a psm_inputs.Workload (or keyword overrides)."""
+    d = {}
+    if wl is not None:
+        d = dict(nx=wl.nx, ny=wl.ny, nz=wl.nz, q=wl.q, tau=wl.tau, magic=wl.magic, force=wl.force,
+                 bc=wl.bc, u_in=wl.u_in, sc=wl.sc, psm=1)
+    d.update(kw)
+    cfg = Config()
+    cfg.nx, cfg.ny, cfg.nz, cfg.q = d["nx"], d["ny"], d["nz"], d["q"]
+    cfg.tau, cfg.magic = d["tau"], d.get("magic", 3.0 / 16.0)
+    cfg.force = (C.c_double * 3)(*d.get("force", (0, 0, 0)))
+    cfg.bc = (C.c_int * 6)(*[FACE[b] if isinstance(b, str) else int(b) for b in d.get("bc", ("periodic",) * 6)])
+    cfg.u_in = (C.c_double * 3)(*d.get("u_in", (0, 0, 0)))
+    cfg.sc = d.get("sc", 1)
+    cfg.psm = d.get("psm", 1)
+    return cfg
+
+
+def pose_at(motion, t: int) -> Pose:
+    p = Pose()
+    ax = np.asarray(motion.axis, dtype=np.float64)
+    x0 = np.asarray(motion.x0, dtype=np.float64)
+    v = np.asarray(motion.v, dtype=np.float64)
+    lib().or_pose_at(_dp(ax), float(motion.theta0), float(motion.omega), _dp(x0), _dp(v), int(t), C.byref(p))
+    return p
+
+
+def pose_arrays(p: Pose):
+    return (np.array(p.R[:]).reshape(3, 3), np.array(p.X[:]), np.array(p.V[:]), np.array(p.W[:]))
+
+
+def collide_cell(cfg: Config, fin, B=(), us=()):
+    q = cfg.q
+    fin = np.ascontiguousarray(fin, dtype=np.float64)
+    ns = len(B)
+    Bv = np.ascontiguousarray(np.asarray(B, dtype=np.float64).reshape(-1) if ns else np.zeros(1))
+    uv = np.ascontiguousarray(np.asarray(us, dtype=np.float64).reshape(-1) if ns else np.zeros(3))
+    fo = np.zeros(q)
+    dF = np.zeros(6)
+    if lib().or_collide_cell(C.byref(cfg), _dp(fin), ns, _dp(Bv), _dp(uv), _dp(fo), _dp(dF)) != 0:
+        raise RuntimeError("or_collide_cell")
+    return fo, dF[: 3 * ns].reshape(ns, 3)
+
+
+def step(cfg: Config, f: np.ndarray, B: np.ndarray | None, poses) -> np.ndarray:
+    """Advance f (q, N) in place by one step; returns F/T (nb, 6) on each body."""
+    nb = 0 if B is None else B.shape[0]
+    fpost = np.empty_like(f)
+    Bv = np.ascontiguousarray(B if nb else np.zeros((1, 1)), dtype=np.float64)
+    P = (Pose * max(1, nb))(*poses) if nb else (Pose * 1)()
+    ft = np.zeros((max(1, nb), 6))
+    r = lib().or_step(C.byref(cfg), _dp(f), _dp(fpost), nb, _dp(Bv), P, _dp(ft))
+    if r != 0:
+        raise RuntimeError(f"or_step failed ({r})")
+    return ft[:nb]
+
+
+def macro(cfg: Config, f: np.ndarray):
+    N = f.shape[1]
+    rho = np.empty(N)
+    u = np.empty((N, 3))
+    lib().or_macro(C.byref(cfg), _dp(f), _dp(rho), _dp(u))
+    return rho, u
+
+
+def mass(cfg: Config, f: np.ndarray) -> float:
+    return lib().or_mass(C.byref(cfg), _dp(f))
+
+
+# ----------------------------------------------------------------------------
+# geometry
+class OracleGeometry:
+    """Geometry lattice of one body: analytic (ellipsoid/cube) or voxelised mesh."""
+
+    def __init__(self, shape, s: int):
+        self.s = s
+        self._keep = None
+        g = Geom()
+        g.s = s
+        if shape.kind == "ellipsoid":
+            g.kind = 0
+            g.p = (C.c_double * 3)(*shape.params)
+            g.r_bound = float(max(shape.params))
+        elif shape.kind == "cube":
+            g.kind = 1
+            g.p = (C.c_double * 3)(shape.params[0], 0, 0)
+            g.r_bound = float(shape.params[0]) * 3 ** 0.5
+        elif shape.kind == "mesh":
+            v = np.ascontiguousarray(shape.mesh.verts, dtype=np.float64)
+            t = np.ascontiguousarray(shape.mesh.tris, dtype=np.int32)
+            h = 2.0 ** -s
+            lo = np.floor(v.min(axis=0) / h).astype(np.int64) - 2
+            hi = np.floor(v.max(axis=0) / h).astype(np.int64) + 2
+            dims = (hi - lo + 1).astype(np.int32)
+            inside = voxelize(v, t, s, lo.astype(np.int32), dims)
+            self._keep = inside
+            g.kind = 2
+            g.mmin = (C.c_int * 3)(*[int(x) for x in lo])
+            g.dims = (C.c_int * 3)(*[int(x) for x in dims])
+            g.inside = inside.ctypes.data_as(C.c_void_p)
+            # farthest box corner from the body origin
+            g.r_bound = float(np.linalg.norm(np.maximum(np.abs(lo), np.abs(hi + 1)) * h))
+        else:
+            raise ValueError(shape.kind)
+        self.g = g
+
+    def inside(self, m):
+        m = np.asarray(m, dtype=np.int64).reshape(-1, 3)
+        return np.array([lib().or_geom_inside(C.byref(self.g), int(a), int(b), int(c)) for a, b, c in m], dtype=bool)
+
+
+def map_body(cfg: Config, geom: OracleGeometry, pose: Pose, b_form: int = 0) -> np.ndarray:
+    N = cfg.nx * cfg.ny * cfg.nz
+    out = np.zeros(N)
+    lib().or_map(C.byref(cfg), C.byref(geom.g), C.byref(pose), int(b_form), _dp(out))
+    return out
+
+
+def map_cell(geom: OracleGeometry, pose: Pose, ix: int, iy: int, iz: int) -> float:
+    return lib().or_map_cell(C.byref(geom.g), C.byref(pose), ix, iy, iz)
+
+
+def b_from_eps(eps: float, tau: float, b_form: int) -> float:
+    return float(lib().or_b_from_eps(eps, tau, b_form))
+
+
+def winding(verts, tris, p) -> float:
+    v = np.ascontiguousarray(verts, dtype=np.float64)
+    t = np.ascontiguousarray(tris, dtype=np.int32)
+    return lib().or_winding(_dp(v), _ip(t), t.shape[0], _dp(np.asarray(p, dtype=np.float64)))
+
+
+def voxelize(verts, tris, s, mmin, dims) -> np.ndarray:
+    v = np.ascontiguousarray(verts, dtype=np.float64)
+    t = np.ascontiguousarray(tris, dtype=np.int32)
+    mmin = np.ascontiguousarray(mmin, dtype=np.int32)
+    dims = np.ascontiguousarray(dims, dtype=np.int32)
+    out = np.zeros(int(np.prod(dims.astype(np.int64))), dtype=np.uint8)
+    lib().or_voxelize(_dp(v), _ip(t), t.shape[0], int(s), _ip(mmin), _ip(dims),
+                      out.ctypes.data_as(C.POINTER(C.c_ubyte)))
+    return out
+
+
+def mesh_volume(verts, tris) -> float:
+    v = np.ascontiguousarray(verts, dtype=np.float64)
+    t = np.ascontiguousarray(tris, dtype=np.int32)
+    return lib().or_mesh_volume(_dp(v), _ip(t), t.shape[0])
+
+
+# ----------------------------------------------------------------------------
+class Run:
+    """Time loop of a workload in the oracle: per step, map B(t) from the poses
+    at t, then collide/stream step t (B(t), u_s(t)); records F/T(t)."""
+
+    def __init__(self, wl, f0: np.ndarray | None = None, b_form=None):
+        self.wl = wl
+        self.cfg = make_config(wl)
+        self.b_form = wl.b_form if b_form is None else b_form
+        q = wl.q
+        c, w, opp = lattice(q)
+        self.c, self.w, self.opp = c, w, opp
+        N = wl.n_cells
+        if f0 is None:
+            self.f = np.repeat(w[:, None], N, axis=1).copy()
+        else:
+            self.f = np.ascontiguousarray(f0, dtype=np.float64)
+        self.geoms = [OracleGeometry(b.shape, b.s) for b in wl.bodies]
+        self.t = 0
+        self.B = np.zeros((len(wl.bodies), N))
+        self.ft = []
+        self._static_done = False
+
+    def map(self, t):
+        for k, (b, g) in enumerate(zip(self.wl.bodies, self.geoms)):
+            self.B[k] = map_body(self.cfg, g, pose_at(b.motion, t), self.b_form)
+
+    def advance(self, steps: int, remap: bool = True):
+        for _ in range(steps):
+            poses = [pose_at(b.motion, self.t) for b in self.wl.bodies]
+            if self.wl.bodies and (remap or not self._static_done):
+                self.map(self.t)
+                self._static_done = True
+            ft = step(self.cfg, self.f, self.B if self.wl.bodies else None, poses)
+            self.ft.append(ft)
+            self.t += 1
+        return self
+
+    def macro(self):
+        return macro(self.cfg, self.f)
+
+    def mass(self):
+        return mass(self.cfg, self.f)
