@@ -1,0 +1,259 @@
+"""Throughput of the PSM hot path on one MI355X.
+
+A step is one pass of the whole hot path over the lattice: geometry_map_step
+(B(t) from the rotated geometry field), psm_stream_collide (fused in-place
+stream + TRT/PSM collision) and body_force_torque (FP64 per-body sum).
+MLUPS = cells * steps / wall time of the timed steps (inputs resident in HBM).
+
+The dominant kernel's roofline: algorithmic bytes per cell update
+(2 * Q * sizeof(storage) PDF traffic + 4 B solid fraction) times cells,
+divided by its average launch time measured with HIP events on the launch
+stream, against 8 TB/s.  HBM traffic per launch comes from a committed
+rocprofv3 FETCH_SIZE/WRITE_SIZE record when the kernel source is unchanged
+since it was taken.
+
+The CPU baseline is the FP64 oracle timed on the host cores on a bounded
+sample (a few full-size steps) of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS + % HBM roofline, PSM vs plain LBM, FP32/FP16 vs FP64 oracle"
+PEAK_HBM_GBS = 8000.0
+KERNEL_SOURCES = ["paper_2502_20049_amd/csrc/k_stream_collide.hpp", "paper_2502_20049_amd/csrc/k_sc_launch.inc",
+                  "paper_2502_20049_amd/csrc/psm_internal.hpp"]
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def workload(name):
+    import psm_inputs as pi
+
+    if name == "ellipsoid_channel_256":
+        return pi.workload_ellipsoid_channel(256, "f32", steps=2000, s=3)
+    if name == "cror_768x384x384":
+        return pi.workload_cror(storage="f16")
+    if name == "capacity_1024":
+        return pi.workload_capacity()
+    raise SystemExit(f"unknown workload {name}")
+
+
+def bytes_per_cell(q, storage, psm=True):
+    sz = {"f64": 8, "f32": 4, "f16": 2}[storage]
+    return 2 * q * sz + (4 if psm else 0)
+
+
+def run_steps(field, t0, n, events=None, map_events=None):
+    import torch
+
+    for i in range(n):
+        t = t0 + i
+        poses = field.poses(t) if field.nb else None
+        if field.nb and (field.remap_every_step or not field._mapped_once):
+            if map_events is not None:
+                map_events[i][0].record()
+            field.map(t, poses)
+            if map_events is not None:
+                map_events[i][1].record()
+        if events is not None:
+            events[i][0].record()
+        field.collide(t, poses)
+        if events is not None:
+            events[i][1].record()
+        if field.nb:
+            field.force_torque()
+    return t0 + n
+
+
+def time_field(field, steps, warmup, t0=0):
+    import torch
+
+    t = run_steps(field, t0, warmup)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    mev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    run_steps(field, t, steps, ev, mev if field.nb and field.remap_every_step else None)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    sc_ms = sum(a.elapsed_time(b) for a, b in ev) / steps
+    map_ms = (sum(a.elapsed_time(b) for a, b in mev) / steps) if field.nb and field.remap_every_step else 0.0
+    return wall, sc_ms, map_ms
+
+
+def copy_probe(nbytes=4 << 30, reps=20):
+    import torch
+
+    from paper_2502_20049_amd import sim
+
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    for _ in range(3):
+        sim.stream_copy(a, b)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        sim.stream_copy(a, b)
+    e1.record()
+    torch.cuda.synchronize()
+    s = e0.elapsed_time(e1) / 1e3 / reps
+    del a, b
+    return 2 * nbytes / s / 1e9
+
+
+def traffic_record(kname, wname):
+    p = os.path.join(ROOT, "profiles", f"traffic_{kname}_{wname}.json")
+    if not os.path.exists(p):
+        return None
+    with open(p) as fh:
+        rec = json.load(fh)
+    if rec.get("kernel_hash") != kernel_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def accuracy_check(steps=100):
+    """FP32 / FP16 storage vs the FP64 oracle on a reduced copy of the channel."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import psm_inputs as pi
+    from paper_2502_20049_amd import sim
+
+    out = {}
+    wl = pi.workload_ellipsoid_channel(n=48, steps=steps, scale=0.25, s=3)
+    wl.bodies[0].motion.omega = 4e-3
+    run = oracle.Run(wl).advance(steps)
+    _, uo = run.macro()
+    Tz_o = np.array(run.ft)[:, 0, 5]
+    for st in ("f32", "f16"):
+        f = sim.Field(wl, storage=st)
+        ft = []
+        for t in range(steps):
+            f.step(t)
+            ft.append(f.force_torque()[0, 5].item())
+        _, ug = f.macroscopic(steps)
+        ug = ug.cpu().numpy()
+        out[st] = {"u_rel_l2": float(np.linalg.norm(ug - uo) / np.linalg.norm(uo)),
+                   "torque_rel_max": float(np.abs(np.array(ft) - Tz_o).max() / np.abs(Tz_o).max())}
+        del f
+        torch.cuda.empty_cache()
+    out["case"] = f"48^3 channel, ellipsoid (10,5,2) s=3, {steps} steps, vs FP64 oracle"
+    return out
+
+
+def cpu_baseline(wl, nsteps=2):
+    import oracle
+
+    oracle.build(force=False)
+    run = oracle.Run(wl)
+    t0 = time.perf_counter()
+    run.advance(nsteps)
+    dt = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": round(wl.n_cells * nsteps / dt / 1e6, 3), "unit": "MLUPS", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{nsteps} full-size steps (map + collide/stream + F/T) of {wl.name}, FP64, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--workload", default="ellipsoid_channel_256")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip variants, copy probe and accuracy")
+    ap.add_argument("--only-psm", action="store_true", help="time the PSM path only (for profiling)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the PSM hot path here is single-GPU (no sharding or collectives); "
+              "run with --gpus 1", file=sys.stderr)
+        raise SystemExit(2)
+
+    import torch
+
+    from paper_2502_20049_amd import sim
+
+    torch.cuda.set_device(0)
+    wl = workload(args.workload)
+    storage = wl.storage
+    f = sim.Field(wl)
+    wall, sc_ms, map_ms = time_field(f, args.steps, args.warmup)
+    N = wl.n_cells
+    mlups = N * args.steps / wall / 1e6
+    bpc = bytes_per_cell(wl.q, storage)
+    achieved = bpc * N / (sc_ms / 1e3) / 1e9
+    traffic = traffic_record("psm_stream_collide", args.workload)
+    line = {
+        "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(wall / args.steps * 1e3, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": {"f32": "f32", "f16": "f32 (f16 storage)",
+                                                            "f64": "f64"}[storage],
+        "data": "synthetic",
+        "config": {"workload": wl.name, "cells": N, "q": wl.q, "storage": storage, "bodies": len(wl.bodies),
+                   "supersampling_s": [b.s for b in wl.bodies], "bc": list(wl.bc), "parallelism": "1 GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": round(achieved / PEAK_HBM_GBS, 4),
+                     "traffic": None if traffic is None else round(traffic, 0),
+                     "kernel": "psm_stream_collide", "algorithmic_bytes_per_cell": bpc,
+                     "avg_launch_ms": round(sc_ms, 5)},
+        "kernels_ms": {"psm_stream_collide": round(sc_ms, 5), "geometry_map_step": round(map_ms, 5)},
+    }
+    del f
+    torch.cuda.empty_cache()
+    if not args.no_extras and not args.only_psm:
+        extras = {}
+        fl = sim.Field(wl, psm=False)
+        wall_l, sc_l, _ = time_field(fl, min(args.steps, 500), 20)
+        extras["plain_lbm_same_storage"] = {"mlups": round(N * min(args.steps, 500) / wall_l / 1e6, 1),
+                                            "kernel_ms": round(sc_l, 5),
+                                            "gbs": round(bytes_per_cell(wl.q, storage, False) * N / sc_l / 1e6, 1)}
+        del fl
+        torch.cuda.empty_cache()
+        fs = sim.Field(wl, remap_every_step=False)
+        wall_s, sc_s, _ = time_field(fs, min(args.steps, 500), 20)
+        extras["psm_static_geometry"] = {"mlups": round(N * min(args.steps, 500) / wall_s / 1e6, 1)}
+        del fs
+        torch.cuda.empty_cache()
+        alt = "f16" if storage != "f16" else "f32"
+        fa = sim.Field(wl, storage=alt)
+        wall_a, sc_a, _ = time_field(fa, min(args.steps, 500), 20)
+        extras[f"psm_{alt}_storage"] = {"mlups": round(N * min(args.steps, 500) / wall_a / 1e6, 1),
+                                        "kernel_ms": round(sc_a, 5),
+                                        "gbs": round(bytes_per_cell(wl.q, alt) * N / sc_a / 1e6, 1)}
+        del fa
+        torch.cuda.empty_cache()
+        bw = copy_probe()
+        extras["copy_probe_gbs"] = round(bw, 1)
+        extras["psm_frac_of_copy_bw"] = round(achieved / bw, 4)
+        extras["accuracy_vs_fp64_oracle"] = accuracy_check()
+        line["extras"] = extras
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(wl)
+    else:
+        line["cpu_baseline"] = None
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,237 @@
+/*
+ * psm.h -- C ABI of the MI355X (gfx950) PSM hot path.
+ *
+ * Method: lattice Boltzmann with the Partially Saturated Cells method (PSM)
+ * for complex moving geometries, after Suffa, Kemmler, Koestler, Ruede,
+ * "Large-Scale Simulations of Fully Resolved Complex Moving Geometries with
+ * Partially Saturated Cells" (arXiv 2502.20049).
+ *
+ * One time step of the hot path is, on the caller's HIP stream:
+ *   geometry_map_step   solid fractions B(x,t) from body-frame geometry fields
+ *                       under each body's current rotation/translation (sec. III)
+ *   psm_stream_collide  fused in-place (AA pattern) stream + TRT collision
+ *                       blended with the solid collision, eq. (4), summed over
+ *                       up to two overlapping bodies per cell; writes per-tile
+ *                       force/torque partials (eqs. (10)-(11))
+ *   body_force_torque   FP64 fixed-order sum of those partials per body
+ *
+ * Conventions shared by every entry point
+ *   - Memory ownership: every device buffer is allocated and freed by the
+ *     caller (e.g. torch tensors) and passed as pointer + byte count.  Handles
+ *     own host-side metadata only.  No per-step call allocates anything.
+ *   - Streams: `stream` is a hipStream_t (NULL = default stream).  Calls are
+ *     asynchronous on it; results are valid after the stream is synchronised.
+ *   - Errors: 0 on success, a negative PSM_E* code otherwise; psm_last_error()
+ *     returns a thread-local message for the last failure.  Kernel launch
+ *     failures are reported as PSM_EHIP.  No C++ exception crosses the ABI.
+ *   - Lattice units: dx = dt = 1, rest density 1, cell (i,j,k) has its centre
+ *     at (i+1/2, j+1/2, k+1/2).  Linear cell index n = x + nx*(y + ny*z).
+ *   - PDF layout: structure of arrays, slot (k, n) at element k*N + n (N =
+ *     nx*ny*nz cells, x fastest).  Stored values are deviations
+ *     delta f_k = f_k - w_k from the lattice weights, in the storage type.
+ *     Direction order is this library's own (psm_lattice()).  The in-place
+ *     AA pattern leaves the buffer in the standard layout (slot (k,n) holds
+ *     f_k at cell n) after every even number of steps; psm_macroscopic and
+ *     psm_mass_fp64 read either parity.
+ */
+#ifndef PSM_H
+#define PSM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes --------------------------------------------------------- */
+#define PSM_OK 0
+#define PSM_EINVAL (-1)  /* invalid argument (null handle, bad enum, bad size) */
+#define PSM_ESIZE (-2)   /* a caller buffer is smaller than required         */
+#define PSM_EUNSUP (-3)  /* valid but unsupported request                    */
+#define PSM_EHIP (-4)    /* HIP runtime / launch failure                      */
+
+/* ---- enums --------------------------------------------------------------- */
+enum { PSM_F64 = 0, PSM_F32 = 1, PSM_F16 = 2 };                 /* PDF storage */
+enum { PSM_PERIODIC = 0, PSM_WALL = 1, PSM_INLET = 2, PSM_OUTLET = 3 }; /* faces */
+enum { PSM_BUF_PDF = 0, PSM_BUF_B = 1, PSM_BUF_WORK = 2 };
+enum { PSM_SHAPE_ELLIPSOID = 0, PSM_SHAPE_CUBE = 1 };
+#define PSM_MAX_BODIES 8
+
+/* Simulation configuration (section II.A; readings of unstated details in the
+ * design notes).
+ *   q        19 (D3Q19) or 27 (D3Q27)
+ *   storage  PSM_F64 (FP64 arithmetic) / PSM_F32 / PSM_F16 (FP32 arithmetic)
+ *   psm      1: PSM blend of eq. (4); 0: plain LBM (no B access at all)
+ *   sc       solid collision operator 1, 2 or 3 (eqs. (7)-(9))
+ *   b_form   0: B = eps (eq. (5)); 1: tau-weighted B (eq. (6))
+ *   slots    body slots per cell, 1 or 2 (sum over overlapping bodies)
+ *   max_bodies  1..PSM_MAX_BODIES (sizes the force/torque partials)
+ *   bc       face kinds for -x,+x,-y,+y,-z,+z: PSM_PERIODIC (both faces of
+ *            an axis), PSM_WALL (halfway bounce-back), PSM_INLET (moving-wall
+ *            bounce-back with u_in, rest density 1), PSM_OUTLET (zero
+ *            gradient: an incoming PDF equals the cell's own post-collision
+ *            PDF of the same direction).  Precedence wall > inlet > outlet.
+ *   tau      relaxation time of the even (viscous) moments, > 1/2
+ *   magic    TRT parameter Lambda; odd rate 1/(1/2 + Lambda/(tau - 1/2))
+ *   force    body-force density (Guo forcing, part of the fluid collision)
+ */
+typedef struct psm_config {
+  int32_t nx, ny, nz;
+  int32_t q;
+  int32_t storage;
+  int32_t psm;
+  int32_t sc;
+  int32_t b_form;
+  int32_t slots;
+  int32_t max_bodies;
+  int32_t bc[6];
+  double tau;
+  double magic;
+  double force[3];
+  double u_in[3];
+} psm_config;
+
+/* Pose and velocity of one rigid body at one step: a body-frame point p is at
+ * x = R p + X in the lab; the solid velocity is u_s(x) = V + W x (x - X).
+ * R is row-major.  W is the angular-velocity vector (rate times unit axis). */
+typedef struct psm_body {
+  double R[9];
+  double X[3];
+  double V[3];
+  double W[3];
+} psm_body;
+
+/* Prescribed motion (one-way coupling, section V.A): rotation by
+ * theta(t) = theta0 + omega*t about the unit `axis` through x0 + v*t. */
+typedef struct psm_motion {
+  double axis[3];
+  double theta0;
+  double omega;
+  double x0[3];
+  double v[3];
+} psm_motion;
+
+typedef struct psm_field psm_field; /* opaque: lattice + B + partial buffers  */
+typedef struct psm_geom psm_geom;   /* opaque: body-frame geometry field      */
+
+/* ---- errors, sizes, tables ---------------------------------------------- */
+const char *psm_last_error(void);
+
+/* Bytes the caller must provide for buffer `which` (PSM_BUF_*):
+ *   PDF  q*N*sizeof(storage)
+ *   B    psm ? N*4*slots + N (FP32 fraction per slot + one body-id byte) : 0
+ *   WORK flags + force/torque partials (max_bodies*6 doubles per tile) +
+ *        reduction scratch.                                                  */
+int psm_required_bytes(const psm_config *cfg, int which, size_t *out_bytes);
+
+/* This library's lattice: velocities c[q][3], weights w[q], opposite opp[q]
+ * (host arrays of at least q entries). */
+int psm_lattice(int q, int32_t *c, double *w, int32_t *opp);
+
+/* ---- host kinematics (section III: rotation folded into the lookup) ------ */
+/* Body pose at `step`: theta = theta0 + omega*step (never accumulated), R by
+ * Rodrigues' formula evaluated entry-wise as
+ *   R_ij = ((c*delta_ij + ((1-c)*a_i)*a_j) + s*K_ij),  K = [a]_x,
+ * X = x0 + v*step, V = v, W = omega*axis.  `axis` must be a unit vector. */
+int psm_body_pose(const psm_motion *m, int64_t step, psm_body *out);
+
+/* ---- field lifetime -------------------------------------------------------- */
+/* Validates cfg and the caller buffers (sizes from psm_required_bytes; the
+ * B buffer may be NULL when cfg->psm == 0) and records them.  Does not touch
+ * device memory; call psm_field_reset before the first step. */
+int pdf_field_create(const psm_config *cfg, void *pdf_dev, size_t pdf_bytes, void *b_dev,
+                     size_t b_bytes, void *work_dev, size_t work_bytes, void *stream,
+                     psm_field **out);
+int pdf_field_destroy(psm_field *f);
+
+/* Rest equilibrium (delta f = 0, rho = 1, u = 0), B = 0, body ids 0, flags 0. */
+int psm_field_reset(psm_field *f, void *stream);
+
+/* ---- geometry field (section III; voxelised once on the host) ---------- */
+/* Body-frame geometry lattice: spacing h = 2^-s LBM cells, cell centres at
+ * (m + 1/2) h for integer m.  A bit is set when its centre is inside the
+ * object.  The field is stored only over the object's body-frame bounding box
+ * plus one LBM cell of padding, bit-packed along body x (32-bit words, row
+ * length ceil(dims[0]/32) words), followed by a coarse map of one byte per
+ * 2^s x 2^s x 2^s block (0 all outside, 1 all inside, 2 mixed).
+ *
+ * psm_geometry_box: box (mmin, dims) and device bytes for a mesh (verts != NULL)
+ * or an analytic shape (kind PSM_SHAPE_*, params: ellipsoid semi-axes a,b,c;
+ * cube half side).  Meshes: verts[nv][3] doubles (body frame), tris[nt][3]
+ * int32 indices, closed and consistently oriented; inside = nonzero winding
+ * number along +x rays. */
+int psm_geometry_box(int kind, const double *params, const double *verts, int64_t nv, int s,
+                     int32_t mmin[3], int32_t dims[3], size_t *dev_bytes);
+/* Host voxelisation into a caller host buffer of dims[2]*dims[1]*ceil(dims[0]/32)
+ * uint32 words (exported for host-side checks). */
+int psm_voxelize_host(const double *verts, int64_t nv, const int32_t *tris, int64_t nt, int s,
+                      const int32_t mmin[3], const int32_t dims[3], uint32_t *bits);
+int psm_analytic_host(int kind, const double *params, int s, const int32_t mmin[3],
+                      const int32_t dims[3], uint32_t *bits);
+/* Voxelise on the host, then copy to the caller's device buffer (async on
+ * stream; the host copy is kept by the handle until destroy). */
+int geometry_field_create(const double *verts, int64_t nv, const int32_t *tris, int64_t nt, int s,
+                          void *dev_buf, size_t bytes, void *stream, psm_geom **out);
+int geometry_field_create_analytic(int kind, const double *params, int s, void *dev_buf,
+                                   size_t bytes, void *stream, psm_geom **out);
+int geometry_field_destroy(psm_geom *g);
+
+/* ---- per-step hot path ----------------------------------------------------- */
+/* Section III mapping, reading "transform each sub-sample": for each lab cell
+ * in the swept box of each body and each of its (2^s)^3 sub-sample points at
+ * offsets delta_k = (k + 1/2) h - 1/2 from the cell centre, the body-frame
+ * point p_k = R^T (x_c - X) + R^T delta_k is looked up in the geometry lattice
+ * cell that contains it; eps = (#inside)/8^s; B = eps or eq. (6).  FP64
+ * arithmetic p_a = fma(R[0][a], d0, fma(R[1][a], d1, R[2][a]*d2)) for both
+ * terms, then signed 64-bit fixed point with 32 fraction bits in sub-cell
+ * units: m = floor((rint(p*2^(s+32)) + rint((R^T delta_k)*2^(s+32))) / 2^32).
+ * Swept box of a body: cells within its geometry's bounding sphere around X,
+ * this step and the previous mapped step (cells a body has left are reset).
+ * Bodies are assigned to the cell's slots in body order; a cell touched by
+ * more bodies than cfg->slots raises error flag bit 0 (psm_error_flags).
+ * `geoms[b]` is the geometry of body b.  n_bodies <= cfg->max_bodies. */
+int geometry_map_step(psm_field *f, const psm_body *bodies, const psm_geom *const *geoms,
+                      int n_bodies, void *stream);
+
+/* One in-place time step (eqs. (1), (3), (4), (7)-(9)) with parity step&1.
+ * Per cell: rho = 1 + sum df, u = (sum c df + F/2)/rho; TRT + Guo fluid
+ * collision Omega^F; for each body slot k with B_k > 0 the solid collision
+ * Omega^S_k with u_s = V + W x (x_c - X); f* = f + (1 - sum B)Omega^F +
+ * sum B_k Omega^S_k (B scaled to sum 1 when it exceeds 1); streaming by the
+ * AA pattern with the face rules of cfg->bc.  Writes per-tile FP64 partials of
+ * the force -B_k sum_i c_i Omega^S_{k,i} on each body and its torque about X
+ * (eqs. (10)-(11), force on the body).  `bodies` must be the poses used by
+ * the last geometry_map_step (B(t) and u_s(t) of the same step). */
+int psm_stream_collide(psm_field *f, const psm_body *bodies, int n_bodies, int64_t step,
+                       void *stream);
+
+/* Sum the partials of the last psm_stream_collide in fixed order: ft_dev is a
+ * device array double[n_bodies][6] = (Fx,Fy,Fz,Tx,Ty,Tz) on each body, lattice
+ * units. */
+int body_force_torque(psm_field *f, int n_bodies, double *ft_dev, void *stream);
+
+/* ---- diagnostics ------------------------------------------------------------ */
+/* Total mass sum_x rho(x) in FP64 (fixed-order tree) into out_dev[0];
+ * `step` is the number of steps taken (selects the AA parity). */
+int psm_mass_fp64(psm_field *f, int64_t step, double *out_dev, void *stream);
+/* rho[N] and u[N][3] (u = (sum c f + F/2)/rho) in FP64 after `step` steps. */
+int psm_macroscopic(psm_field *f, int64_t step, double *rho_dev, double *u_dev, void *stream);
+/* Copy the field's int32 error flags (bit 0: too many bodies in a cell). */
+int psm_error_flags(psm_field *f, int32_t *out_dev, void *stream);
+/* Per-field options (defaults in brackets):
+ *   PSM_OPT_GENERAL_PATH [0]  1: every row of psm_stream_collide takes the
+ *                             general (face-row) addressing path; results are
+ *                             bitwise identical, used to cross-check the fast path
+ *   PSM_OPT_XCD_REMAP    [1]  1: workgroup ids are remapped so each of the 8
+ *                             XCDs walks a contiguous range of tiles */
+enum { PSM_OPT_GENERAL_PATH = 1, PSM_OPT_XCD_REMAP = 2 };
+int psm_set_option(psm_field *f, int option, int value);
+/* Device-to-device copy kernel (measured-bandwidth probe); 16-byte aligned
+ * src and dst. */
+int psm_stream_copy(const void *src, void *dst, size_t bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PSM_H */

@@ -28,7 +28,7 @@ def build(force: bool = True) -> str:
     """Compile liboracle.so with gcc (FP64, OpenMP, no FP contraction)."""
     if force or not os.path.exists(_LIB_PATH):
         cmd = ["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
-               "-fno-fast-math", os.path.join(_HERE, "oracle.c"), "-lm", "-o", _LIB_PATH + ".tmp"]
+               "-fno-fast-math", "-fno-builtin-sin", "-fno-builtin-cos", os.path.join(_HERE, "oracle.c"), "-lm", "-o", _LIB_PATH + ".tmp"]
         subprocess.check_call(cmd)
         os.replace(_LIB_PATH + ".tmp", _LIB_PATH)
     return _LIB_PATH
@@ -46,7 +46,8 @@ class Pose(C.Structure):
 
 class Geom(C.Structure):
     _fields_ = [("kind", C.c_int), ("p", C.c_double * 3), ("s", C.c_int), ("mmin", C.c_int * 3),
-                ("dims", C.c_int * 3), ("inside", C.c_void_p), ("r_bound", C.c_double)]
+                ("dims", C.c_int * 3), ("inside", C.c_void_p), ("r_bound", C.c_double),
+                ("verts", C.c_void_p), ("tris", C.c_void_p), ("nt", C.c_longlong)]
 
 
 def lib():
@@ -77,6 +78,8 @@ def lib():
         L.or_winding.restype = C.c_double
         L.or_voxelize.argtypes = [dp, C.POINTER(C.c_int), C.c_longlong, C.c_int, C.POINTER(C.c_int),
                                   C.POINTER(C.c_int), C.POINTER(C.c_ubyte)]
+        L.or_update_cell.argtypes = [C.POINTER(Config), C.c_int, C.c_int, C.c_int, dp, C.c_int, dp,
+                                     C.POINTER(Pose), dp]
         L.or_mesh_volume.argtypes = [dp, C.POINTER(C.c_int), C.c_longlong]
         L.or_mesh_volume.restype = C.c_double
         _lib = L
@@ -185,7 +188,7 @@ def mass(cfg: Config, f: np.ndarray) -> float:
 class OracleGeometry:
     """Geometry lattice of one body: analytic (ellipsoid/cube) or voxelised mesh."""
 
-    def __init__(self, shape, s: int):
+    def __init__(self, shape, s: int, lazy: bool = False):
         self.s = s
         self._keep = None
         g = Geom()
@@ -198,6 +201,16 @@ class OracleGeometry:
             g.kind = 1
             g.p = (C.c_double * 3)(shape.params[0], 0, 0)
             g.r_bound = float(shape.params[0]) * 3 ** 0.5
+        elif shape.kind == "mesh" and lazy:
+            # winding number evaluated at each queried lattice centre
+            v = np.ascontiguousarray(shape.mesh.verts, dtype=np.float64)
+            t = np.ascontiguousarray(shape.mesh.tris, dtype=np.int32)
+            self._keep = (v, t)
+            g.kind = 3
+            g.verts = v.ctypes.data_as(C.c_void_p)
+            g.tris = t.ctypes.data_as(C.c_void_p)
+            g.nt = t.shape[0]
+            g.r_bound = float(np.linalg.norm(v, axis=1).max()) + 1e-9
         elif shape.kind == "mesh":
             v = np.ascontiguousarray(shape.mesh.verts, dtype=np.float64)
             t = np.ascontiguousarray(shape.mesh.tris, dtype=np.int32)
@@ -303,3 +316,71 @@ class Run:
 
     def mass(self):
         return mass(self.cfg, self.f)
+
+
+def update_cell(cfg: Config, x: int, y: int, z: int, nbr: np.ndarray, Bn: np.ndarray, poses) -> np.ndarray:
+    """One-step update of cell (x,y,z) from its 3x3x3 pre-step neighbourhood
+    ``nbr`` (27, q) and solid fractions ``Bn`` (27, nb) (x fastest order)."""
+    q = cfg.q
+    nb = Bn.shape[1] if Bn is not None and Bn.ndim == 2 else 0
+    out = np.zeros(q)
+    nbr = np.ascontiguousarray(nbr, dtype=np.float64)
+    Bv = np.ascontiguousarray(Bn if nb else np.zeros((27, 1)), dtype=np.float64)
+    P = (Pose * max(1, nb))(*poses) if nb else (Pose * 1)()
+    r = lib().or_update_cell(C.byref(cfg), x, y, z, _dp(nbr), nb, _dp(Bv), P, _dp(out))
+    if r != 0:
+        raise RuntimeError(f"or_update_cell failed ({r})")
+    return out
+
+
+def sampled_steps(wl, cells, f_at, geoms, steps: int, b_form: int = 0, t0: int = 0):
+    """f(t0 + steps) at the given cells, computed one cell at a time.
+
+    ``f_at(xyz (m,3)) -> (m, q)`` gives the full f at t0 for any cells (the
+    seeded generator); ``geoms`` are OracleGeometry objects of the bodies.
+    The dependence cone of each cell (radius ``steps``) is evaluated
+    recursively with or_update_cell; solid fractions come from or_map_cell.
+    """
+    cfg = make_config(wl)
+    n3 = np.array([wl.nx, wl.ny, wl.nz])
+    per = np.array([wl.bc[0] == "periodic", wl.bc[2] == "periodic", wl.bc[4] == "periodic"])
+    offs = np.array([(dx, dy, dz) for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1)])
+    cache = {}
+
+    def nbrs(c):
+        p = c + offs
+        p = np.where(per, p % n3, p)
+        inside = np.all((p >= 0) & (p < n3), axis=1)
+        return p, inside
+
+    bcache = {}
+
+    def B_at(c, t):
+        key = (int(c[0]), int(c[1]), int(c[2]), t)
+        if key not in bcache:
+            poses = [pose_at(b.motion, t) for b in wl.bodies]
+            bcache[key] = np.array([b_from_eps(map_cell(g, P, *map(int, c)), wl.tau, b_form)
+                                    for g, P in zip(geoms, poses)])
+        return bcache[key]
+
+    def value(c, t):
+        key = (int(c[0]), int(c[1]), int(c[2]), t)
+        if key in cache:
+            return cache[key]
+        if t == t0:
+            v = f_at(np.asarray([c]))[0]
+        else:
+            p, inside = nbrs(np.asarray(c))
+            nbr = np.zeros((27, wl.q))
+            Bn = np.zeros((27, max(1, len(wl.bodies))))
+            for j in range(27):
+                if inside[j]:
+                    nbr[j] = value(p[j], t - 1)
+                    if wl.bodies:
+                        Bn[j] = B_at(p[j], t - 1)
+            poses = [pose_at(b.motion, t - 1) for b in wl.bodies]
+            v = update_cell(cfg, int(c[0]), int(c[1]), int(c[2]), nbr, Bn if wl.bodies else None, poses)
+        cache[key] = v
+        return v
+
+    return np.array([value(np.asarray(c), t0 + steps) for c in cells])

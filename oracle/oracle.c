@@ -364,6 +364,12 @@ int or_geom_inside(const or_geom *g, long long mx, long long my, long long mz) {
     return fabs((double)(2 * mx + 1)) < lim && fabs((double)(2 * my + 1)) < lim &&
            fabs((double)(2 * mz + 1)) < lim;
   }
+  if (g->kind == 3) {
+    const double h = ldexp(1.0, -g->s);
+    double p[3] = {((double)mx + 0.5) * h, ((double)my + 0.5) * h, ((double)mz + 0.5) * h};
+    if (p[0] * p[0] + p[1] * p[1] + p[2] * p[2] > g->r_bound * g->r_bound) return 0;
+    return or_winding(g->verts, g->tris, g->nt, p) > 0.5;
+  }
   long long jx = mx - g->mmin[0], jy = my - g->mmin[1], jz = mz - g->mmin[2];
   if (jx < 0 || jy < 0 || jz < 0 || jx >= g->dims[0] || jy >= g->dims[1] || jz >= g->dims[2]) return 0;
   return g->inside[jx + (long long)g->dims[0] * (jy + (long long)g->dims[1] * jz)] != 0;
@@ -496,4 +502,64 @@ double or_mesh_volume(const double *v, const int *t, long long nt) {
          a[2] * (b[0] * c[1] - b[1] * c[0]);
   }
   return s / 6.0;
+}
+
+/* ---------------------------------------------------------------------------
+ * One step of one cell, for sampled checks on domains too large for or_step:
+ * the same update as or_step restricted to the cell (x,y,z).  nbr holds the
+ * pre-step f of the 3x3x3 neighbourhood, nbr[(((dz+1)*3 + (dy+1))*3 + (dx+1))*q
+ * + i] for the cell at (x+dx, y+dy, z+dz) (periodic axes wrapped); entries of
+ * cells outside the domain are not read.  Bn[j*nb + b] is B of body b at
+ * neighbour j (same order).  out[i] = f_i(x, t+1).
+ * ------------------------------------------------------------------------- */
+int or_update_cell(const or_config *cfg, int x, int y, int z, const double *nbr, int nb, const double *Bn,
+                   const or_pose *poses, double *out) {
+  lat_t L;
+  if (lat_get(cfg->q, &L) != 0) return -1;
+  const int q = L.q;
+  const int n3[3] = {cfg->nx, cfg->ny, cfg->nz};
+  double post[27][OR_MAXQ];
+  int done[27] = {0};
+  const double cs2 = 1.0 / 3.0;
+  for (int k = 0; k < q; ++k) {
+    int s32;
+    int kind = classify(cfg, x, y, z, &L.c[3 * k], &s32);
+    int j, dir;
+    if (kind == 0) {
+      j = ((-L.c[3 * k + 2] + 1) * 3 + (-L.c[3 * k + 1] + 1)) * 3 + (-L.c[3 * k] + 1);
+      dir = k;
+    } else {
+      j = 13;
+      dir = (kind == OR_OUTLET) ? k : L.opp[k];
+    }
+    if (!done[j]) {
+      int d[3] = {j % 3 - 1, (j / 3) % 3 - 1, j / 9 - 1};
+      int p[3] = {x + d[0], y + d[1], z + d[2]};
+      for (int a = 0; a < 3; ++a) p[a] = (p[a] + n3[a]) % n3[a];
+      double Bs[2], us[6], dF[6];
+      int ns = 0;
+      if (cfg->psm)
+        for (int b = 0; b < nb; ++b) {
+          double v = Bn[j * nb + b];
+          if (v > 0.0) {
+            if (ns == 2) return -3;
+            const or_pose *P = &poses[b];
+            double r[3] = {p[0] + 0.5 - P->X[0], p[1] + 0.5 - P->X[1], p[2] + 0.5 - P->X[2]};
+            us[3 * ns + 0] = P->V[0] + (P->W[1] * r[2] - P->W[2] * r[1]);
+            us[3 * ns + 1] = P->V[1] + (P->W[2] * r[0] - P->W[0] * r[2]);
+            us[3 * ns + 2] = P->V[2] + (P->W[0] * r[1] - P->W[1] * r[0]);
+            Bs[ns++] = v;
+          }
+        }
+      collide_lat(cfg, &L, nbr + (size_t)j * q, ns, Bs, us, post[j], dF);
+      done[j] = 1;
+    }
+    double v = post[j][dir];
+    if (kind == OR_INLET) {
+      double cu = L.c[3 * k] * cfg->u_in[0] + L.c[3 * k + 1] * cfg->u_in[1] + L.c[3 * k + 2] * cfg->u_in[2];
+      v += 2.0 * L.w[k] * cu / cs2;
+    }
+    out[k] = v;
+  }
+  return 0;
 }

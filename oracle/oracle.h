@@ -56,7 +56,8 @@ typedef struct {
 } or_pose;
 
 /* Geometry: kind 0 = analytic ellipsoid (p = semi-axes), 1 = analytic cube
- * (p[0] = half side), 2 = stored inside flags over the box mmin..mmin+dims. */
+ * (p[0] = half side), 2 = stored inside flags over the box mmin..mmin+dims,
+ * 3 = mesh evaluated on demand (winding number at each queried centre). */
 typedef struct {
   int kind;
   double p[3];
@@ -65,6 +66,9 @@ typedef struct {
   int dims[3];
   const unsigned char *inside;
   double r_bound;  /* every inside lattice centre is within r_bound of the origin */
+  const double *verts;
+  const int *tris;
+  long long nt;
 } or_geom;
 
 int or_lattice(int q, int *c, double *w, int *opp);
@@ -87,6 +91,9 @@ double or_map_cell(const or_geom *g, const or_pose *pose, int ix, int iy, int iz
 int or_map(const or_config *cfg, const or_geom *g, const or_pose *pose, int b_form,
            double *B_out);
 float or_b_from_eps(double eps, double tau, int b_form);
+
+int or_update_cell(const or_config *cfg, int x, int y, int z, const double *nbr, int nb, const double *Bn,
+                   const or_pose *poses, double *out);
 
 double or_winding(const double *v, const int *t, long long nt, const double p[3]);
 int or_voxelize(const double *v, const int *t, long long nt, int s, const int mmin[3],

@@ -1,0 +1,103 @@
+"""ctypes binding of libpsm.so: the C entry points under the same names.
+
+Argument marshalling only; every step of the hot path runs in the library's
+HIP kernels.  Importing this module loads the library and raises if it has not
+been built (there is no fallback).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpsm.so")
+
+PSM_OK, PSM_EINVAL, PSM_ESIZE, PSM_EUNSUP, PSM_EHIP = 0, -1, -2, -3, -4
+PSM_F64, PSM_F32, PSM_F16 = 0, 1, 2
+PSM_PERIODIC, PSM_WALL, PSM_INLET, PSM_OUTLET = 0, 1, 2, 3
+PSM_BUF_PDF, PSM_BUF_B, PSM_BUF_WORK = 0, 1, 2
+PSM_SHAPE_ELLIPSOID, PSM_SHAPE_CUBE = 0, 1
+PSM_OPT_GENERAL_PATH, PSM_OPT_XCD_REMAP = 1, 2
+PSM_MAX_BODIES = 8
+
+# every symbol include/psm.h declares
+EXPORTS = [
+    "psm_last_error", "psm_required_bytes", "psm_lattice", "psm_body_pose", "pdf_field_create",
+    "pdf_field_destroy", "psm_field_reset", "psm_geometry_box", "psm_voxelize_host", "psm_analytic_host",
+    "geometry_field_create", "geometry_field_create_analytic", "geometry_field_destroy", "geometry_map_step",
+    "psm_stream_collide", "body_force_torque", "psm_mass_fp64", "psm_macroscopic", "psm_error_flags",
+    "psm_set_option", "psm_stream_copy",
+]
+
+
+class psm_config(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("q", C.c_int32),
+                ("storage", C.c_int32), ("psm", C.c_int32), ("sc", C.c_int32), ("b_form", C.c_int32),
+                ("slots", C.c_int32), ("max_bodies", C.c_int32), ("bc", C.c_int32 * 6),
+                ("tau", C.c_double), ("magic", C.c_double), ("force", C.c_double * 3),
+                ("u_in", C.c_double * 3)]
+
+
+class psm_body(C.Structure):
+    _fields_ = [("R", C.c_double * 9), ("X", C.c_double * 3), ("V", C.c_double * 3), ("W", C.c_double * 3)]
+
+
+class psm_motion(C.Structure):
+    _fields_ = [("axis", C.c_double * 3), ("theta0", C.c_double), ("omega", C.c_double),
+                ("x0", C.c_double * 3), ("v", C.c_double * 3)]
+
+
+class PSMError(RuntimeError):
+    pass
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_2502_20049_amd/build.py "
+                          "(or __graft_entry__.build()); there is no fallback path")
+    L = C.CDLL(LIB_PATH)
+    vp, sz, i64, dp = C.c_void_p, C.c_size_t, C.c_int64, C.POINTER(C.c_double)
+    i32p = C.POINTER(C.c_int32)
+    u32p = C.POINTER(C.c_uint32)
+    sig = {
+        "psm_last_error": (C.c_char_p, []),
+        "psm_required_bytes": (C.c_int, [C.POINTER(psm_config), C.c_int, C.POINTER(C.c_size_t)]),
+        "psm_lattice": (C.c_int, [C.c_int, i32p, dp, i32p]),
+        "psm_body_pose": (C.c_int, [C.POINTER(psm_motion), i64, C.POINTER(psm_body)]),
+        "pdf_field_create": (C.c_int, [C.POINTER(psm_config), vp, sz, vp, sz, vp, sz, vp, C.POINTER(vp)]),
+        "pdf_field_destroy": (C.c_int, [vp]),
+        "psm_field_reset": (C.c_int, [vp, vp]),
+        "psm_geometry_box": (C.c_int, [C.c_int, dp, dp, i64, C.c_int, i32p, i32p, C.POINTER(C.c_size_t)]),
+        "psm_voxelize_host": (C.c_int, [dp, i64, i32p, i64, C.c_int, i32p, i32p, u32p]),
+        "psm_analytic_host": (C.c_int, [C.c_int, dp, C.c_int, i32p, i32p, u32p]),
+        "geometry_field_create": (C.c_int, [dp, i64, i32p, i64, C.c_int, vp, sz, vp, C.POINTER(vp)]),
+        "geometry_field_create_analytic": (C.c_int, [C.c_int, dp, C.c_int, vp, sz, vp, C.POINTER(vp)]),
+        "geometry_field_destroy": (C.c_int, [vp]),
+        "geometry_map_step": (C.c_int, [vp, C.POINTER(psm_body), C.POINTER(vp), C.c_int, vp]),
+        "psm_stream_collide": (C.c_int, [vp, C.POINTER(psm_body), C.c_int, i64, vp]),
+        "body_force_torque": (C.c_int, [vp, C.c_int, vp, vp]),
+        "psm_mass_fp64": (C.c_int, [vp, i64, vp, vp]),
+        "psm_macroscopic": (C.c_int, [vp, i64, vp, vp, vp]),
+        "psm_error_flags": (C.c_int, [vp, vp, vp]),
+        "psm_set_option": (C.c_int, [vp, C.c_int, C.c_int]),
+        "psm_stream_copy": (C.c_int, [vp, vp, sz, vp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    return L
+
+
+lib = _load()
+
+
+def check(rc: int, what: str = ""):
+    if rc != PSM_OK:
+        msg = lib.psm_last_error().decode()
+        raise PSMError(f"{what or 'psm call'} failed ({rc}): {msg}")
+    return rc
+
+
+def last_error() -> str:
+    return lib.psm_last_error().decode()

@@ -1,0 +1,204 @@
+// Geometry field -> solid fraction mapping (section III) for gfx950.
+//
+// The rotation/translation is folded into the lookup: each lab cell's centre
+// is taken to the body frame once (FP64, fixed fma order), each of its
+// (2^s)^3 sub-sample offsets is rotated once per launch into an LDS table,
+// and sub-sample k of the cell lands in geometry lattice cell
+//   m = floor((rint(p * 2^(s+32)) + rint((R^T delta_k) * 2^(s+32))) / 2^32)
+// (signed 64-bit fixed point, 32 fraction bits, sub-cell units).
+//
+// Cost control: a coarse map (one byte per 2^s-cube block of the geometry
+// lattice: all out / all in / mixed) classifies most cells exactly from the
+// <= 3x3x3 blocks their sub-samples can touch; only surface cells are sampled,
+// one cell at a time per wave64 with every lane taking sub-samples and a
+// ballot/popcount giving the count.
+#include "psm_internal.hpp"
+
+#pragma clang fp contract(off)
+
+namespace psm {
+
+__device__ __forceinline__ double rt_comp(const double *R, int a, double v0, double v1, double v2) {
+  return __builtin_fma(R[a], v0, __builtin_fma(R[3 + a], v1, R[6 + a] * v2));
+}
+
+__device__ __forceinline__ void sub_offset(const MapBodyK &g, int k, long long D[3]) {
+  const int s = g.s, n = 1 << s;
+  const int kx = k & (n - 1), ky = (k >> s) & (n - 1), kz = k >> (2 * s);
+  const double h2 = 1.0 / (double)(2 << s);  // 2^-(s+1), exact
+  const double d0 = (2.0 * kx + 1.0) * h2 - 0.5;
+  const double d1 = (2.0 * ky + 1.0) * h2 - 0.5;
+  const double d2 = (2.0 * kz + 1.0) * h2 - 0.5;
+  const double sc = (double)(1ull << (s + 32));
+#pragma unroll
+  for (int c = 0; c < 3; ++c) D[c] = __double2ll_rn(rt_comp(g.R, c, d0, d1, d2) * sc);
+}
+
+__device__ __forceinline__ int geo_bit(const MapBodyK &g, long long mx, long long my, long long mz) {
+  const long long jx = mx - g.mmin[0], jy = my - g.mmin[1], jz = mz - g.mmin[2];
+  if ((unsigned long long)jx >= (unsigned long long)g.dims[0] || (unsigned long long)jy >= (unsigned long long)g.dims[1] ||
+      (unsigned long long)jz >= (unsigned long long)g.dims[2])
+    return 0;
+  const uint32_t w = g.bits[((size_t)jz * g.dims[1] + (size_t)jy) * g.wx + (size_t)(jx >> 5)];
+  return (w >> (jx & 31)) & 1;
+}
+
+__device__ __forceinline__ int coarse_state(const MapBodyK &g, long long bx, long long by, long long bz) {
+  const long long jx = bx - g.cmin[0], jy = by - g.cmin[1], jz = bz - g.cmin[2];
+  if ((unsigned long long)jx >= (unsigned long long)g.cdims[0] || (unsigned long long)jy >= (unsigned long long)g.cdims[1] ||
+      (unsigned long long)jz >= (unsigned long long)g.cdims[2])
+    return 0;
+  return g.coarse[((size_t)jz * g.cdims[1] + (size_t)jy) * g.cdims[0] + (size_t)jx];
+}
+
+__device__ __forceinline__ bool in_box(const IBox &b, int x, int y, int z) {
+  return x >= b.lo[0] && x <= b.hi[0] && y >= b.lo[1] && y <= b.hi[1] && z >= b.lo[2] && z <= b.hi[2];
+}
+
+__global__ __launch_bounds__(256) void k_map(const MapArgs a) {
+  const int rb = blockIdx.y;
+  const MapBodyK &G = a.body[rb];
+  if (blockIdx.x * 256u >= G.region_cells) return;  // whole workgroup idle
+  __shared__ long long tab[3][512];
+  const int nsr = 1 << (3 * G.s);
+  for (int k = threadIdx.x; k < nsr; k += 256) {
+    long long D[3];
+    sub_offset(G, k, D);
+    tab[0][k] = D[0];
+    tab[1][k] = D[1];
+    tab[2][k] = D[2];
+  }
+  __syncthreads();
+
+  const int lane = threadIdx.x & 63;
+  const uint32_t idx = blockIdx.x * 256u + threadIdx.x;
+  bool active = idx < G.region_cells;
+  const int rx = G.region.hi[0] - G.region.lo[0] + 1, ry = G.region.hi[1] - G.region.lo[1] + 1;
+  const int x = G.region.lo[0] + (int)(idx % (uint32_t)rx);
+  const int y = G.region.lo[1] + (int)((idx / (uint32_t)rx) % (uint32_t)ry);
+  const int z = G.region.lo[2] + (int)(idx / ((uint32_t)rx * (uint32_t)ry));
+  for (int b = 0; b < rb; ++b)
+    if (in_box(a.body[b].region, x, y, z)) active = false;  // written by an earlier region
+
+  float Bv[2] = {0.f, 0.f};
+  int id[2] = {0, 0};
+  int used = 0;
+  bool overflow = false;
+  for (int bb = 0; bb < a.nb; ++bb) {
+    const MapBodyK &g = a.body[bb];
+    const bool inb = active && in_box(g.active, x, y, z);
+    if (!__any(inb)) continue;
+    const int s = g.s;
+    const int ns = 1 << (3 * s);
+    long long P[3] = {0, 0, 0};
+    int state = 0;  // 0 all out, 1 all in, 2 sample
+    if (inb) {
+      const double d0 = (x + 0.5) - g.X[0], d1 = (y + 0.5) - g.X[1], d2 = (z + 0.5) - g.X[2];
+      const double sc = (double)(1ull << (s + 32));
+#pragma unroll
+      for (int c = 0; c < 3; ++c) P[c] = __double2ll_rn(rt_comp(g.R, c, d0, d1, d2) * sc);
+      if (s == 0) {
+        state = 2;
+      } else {
+        long long lo[3], hi[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          lo[c] = (P[c] - g.dabs[c]) >> (32 + s);
+          hi[c] = (P[c] + g.dabs[c]) >> (32 + s);
+        }
+        int st = -1;
+        for (long long bz = lo[2]; bz <= hi[2] && st != 2; ++bz)
+          for (long long by = lo[1]; by <= hi[1] && st != 2; ++by)
+            for (long long bx = lo[0]; bx <= hi[0] && st != 2; ++bx) {
+              const int v = coarse_state(g, bx, by, bz);
+              st = (st < 0) ? v : (st == v ? st : 2);
+            }
+        state = st;
+      }
+    }
+    int count = state == 1 ? ns : 0;
+    const bool own_tab = (bb == rb);
+    if (s <= 1) {
+      if (state == 2) {
+        int c = 0;
+        for (int k = 0; k < ns; ++k) {
+          long long D[3];
+          if (own_tab) {
+            D[0] = tab[0][k];
+            D[1] = tab[1][k];
+            D[2] = tab[2][k];
+          } else {
+            sub_offset(g, k, D);
+          }
+          c += geo_bit(g, (P[0] + D[0]) >> 32, (P[1] + D[1]) >> 32, (P[2] + D[2]) >> 32);
+        }
+        count = c;
+      }
+    } else {
+      unsigned long long mask = __ballot(state == 2);
+      while (mask) {
+        const int l = __ffsll((long long)mask) - 1;
+        mask &= mask - 1;
+        const long long Px = __shfl(P[0], l), Py = __shfl(P[1], l), Pz = __shfl(P[2], l);
+        int c = 0;
+        for (int k0 = 0; k0 < ns; k0 += 64) {
+          const int k = k0 + lane;
+          int in = 0;
+          if (k < ns) {
+            long long D[3];
+            if (own_tab) {
+              D[0] = tab[0][k];
+              D[1] = tab[1][k];
+              D[2] = tab[2][k];
+            } else {
+              sub_offset(g, k, D);
+            }
+            in = geo_bit(g, (Px + D[0]) >> 32, (Py + D[1]) >> 32, (Pz + D[2]) >> 32);
+          }
+          c += __popcll(__ballot(in));
+        }
+        if (lane == l) count = c;
+      }
+    }
+    if (inb && count > 0) {
+      float B;
+      const double eps = (double)count / (double)ns;
+      if (a.b_form == 0) {
+        B = (float)eps;
+      } else {
+        const double th = a.tau - 0.5;
+        const double num = eps * th;
+        const double den = (1.0 - eps) + th;
+        B = (float)(num / den);
+      }
+      if (used < a.slots) {
+        Bv[used] = B;
+        id[used] = bb;
+        ++used;
+      } else {
+        overflow = true;
+      }
+    }
+  }
+  if (active) {
+    const size_t n = (size_t)x + (size_t)a.nx * ((size_t)y + (size_t)a.ny * (size_t)z);
+    a.B0[n] = Bv[0];
+    uint8_t m = (uint8_t)(id[0] & 15);
+    if (a.slots == 2) {
+      a.B1[n] = Bv[1];
+      if (used == 2) m |= (uint8_t)((id[1] + 1) << 4);
+    }
+    a.meta[n] = m;
+    if (overflow) atomicOr(a.err, 1);
+  }
+}
+
+hipError_t launch_map(const MapArgs &a, uint32_t max_region_cells, int any_s_max, hipStream_t st) {
+  (void)any_s_max;
+  if (a.nb == 0 || max_region_cells == 0) return hipSuccess;
+  dim3 grid((max_region_cells + 255) / 256, a.nb), block(256);
+  hipLaunchKernelGGL(k_map, grid, block, 0, st, a);
+  return hipGetLastError();
+}
+
+}  // namespace psm

@@ -1,0 +1,210 @@
+// Reductions and utility kernels: per-body force/torque sum (FP64, fixed
+// order), parity-aware macroscopic fields and FP64 mass, zero fill, copy probe.
+#include "k_stream_collide.hpp"
+
+namespace psm {
+
+__device__ __forceinline__ double block_sum256(double v, double *sh) {
+  v = wave_sum(v);
+  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __syncthreads();
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  return ((sh[0] + sh[1]) + sh[2]) + sh[3];
+}
+
+struct TileBoxes {
+  int v[PSM_MAX_BODIES * 6];  // lo x,y,z, hi x,y,z in tile coordinates
+};
+
+// One workgroup per body: tiles of the body's swept box in increasing tile
+// index, thread t takes every 256th tile, then a fixed tree.
+__global__ __launch_bounds__(256) void k_ft_reduce(const double *ftp, int max_bodies, int ntx, int nty,
+                                                   const TileBoxes tb, double *ft) {
+  const int b = blockIdx.x;
+  const int *bx = tb.v + 6 * b;
+  const int lx = bx[0], ly = bx[1], lz = bx[2], hx = bx[3], hy = bx[4], hz = bx[5];
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  if (hx >= lx && hy >= ly && hz >= lz) {
+    const long long ex = hx - lx + 1, ey = hy - ly + 1, ez = hz - lz + 1;
+    const long long total = ex * ey * ez;
+    for (long long i = threadIdx.x; i < total; i += 256) {
+      const long long tx = lx + i % ex, ty = ly + (i / ex) % ey, tz = lz + i / (ex * ey);
+      const size_t tile = (size_t)((tz * nty + ty) * ntx + tx);
+      const double *p = ftp + (tile * max_bodies + b) * 6;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) acc[c] += p[c];
+    }
+  }
+  __shared__ double sh[4];
+  for (int c = 0; c < 6; ++c) {
+    const double s = block_sum256(acc[c], sh);
+    if (threadIdx.x == 0) ft[b * 6 + c] = s;
+  }
+}
+
+hipError_t launch_ft_reduce(const psm_field &f, int nb, double *ft, hipStream_t st) {
+  if (nb <= 0) return hipSuccess;
+  TileBoxes tb;
+  for (int b = 0; b < nb; ++b) {
+    const IBox &B = f.active[b];
+    const bool empty = B.hi[0] < B.lo[0] || B.hi[1] < B.lo[1] || B.hi[2] < B.lo[2];
+    tb.v[6 * b + 0] = empty ? 1 : B.lo[0] / f.TX;
+    tb.v[6 * b + 1] = empty ? 1 : B.lo[1] / f.TY;
+    tb.v[6 * b + 2] = empty ? 1 : B.lo[2];
+    tb.v[6 * b + 3] = empty ? 0 : B.hi[0] / f.TX;
+    tb.v[6 * b + 4] = empty ? 0 : B.hi[1] / f.TY;
+    tb.v[6 * b + 5] = empty ? 0 : B.hi[2];
+  }
+  hipLaunchKernelGGL(k_ft_reduce, dim3(nb), dim3(256), 0, st, (const double *)f.ftp, f.cfg.max_bodies, f.ntx,
+                     f.nty, tb, ft);
+  return hipGetLastError();
+}
+
+// Parity-aware read of f_k at cell (x,y,z): the standard slot at even parity;
+// at odd parity the slot (x - c_k, kbar), or the cell's own slot (plus the
+// inlet term) when the source is outside the domain.
+template <int Q, typename T>
+__device__ double read_f(const SCArgs &a, int parity, int k, int x, int y, int z, uint64_t n) {
+  const uint64_t N = a.N;
+  const T *A = (const T *)a.pdf;
+  if (parity == 0) return (double)A[(uint64_t)k * N + n];
+  const int ex = cx<Q>(k), ey = cy<Q>(k), ez = cz<Q>(k);
+  int sx = x - ex, sy = y - ey, sz = z - ez;
+  int kd = K_NONE;
+  const int nn[3] = {a.nx, a.ny, a.nz};
+  int *sp[3] = {&sx, &sy, &sz};
+  for (int d = 0; d < 3; ++d) {
+    int &v = *sp[d];
+    if (v < 0) {
+      if (a.periodic[d]) v += nn[d];
+      else kd = face_merge(kd, a.bc[2 * d]);
+    } else if (v >= nn[d]) {
+      if (a.periodic[d]) v -= nn[d];
+      else kd = face_merge(kd, a.bc[2 * d + 1]);
+    }
+  }
+  if (kd == K_NONE) {
+    const uint64_t src = (uint64_t)sx + (uint64_t)a.nx * ((uint64_t)sy + (uint64_t)a.ny * (uint64_t)sz);
+    return (double)A[(uint64_t)opp<Q>(k) * N + src];
+  }
+  double v = (double)A[(uint64_t)k * N + n];
+  if (kd == K_INLET) v += 6.0 * wt<Q>(k) * (ex * a.u_in_d[0] + ey * a.u_in_d[1] + ez * a.u_in_d[2]);
+  return v;
+}
+
+template <int Q, typename T>
+__global__ __launch_bounds__(256) void k_macro(const SCArgs a, int parity, double *rho, double *u,
+                                               double *partial, int want_field) {
+  const uint64_t n = (uint64_t)blockIdx.x * 256u + threadIdx.x;
+  const uint64_t N = a.N;
+  double r = 0.0;
+  if (n < N) {
+    const int x = (int)(n % (uint64_t)a.nx);
+    const int y = (int)((n / (uint64_t)a.nx) % (uint64_t)a.ny);
+    const int z = (int)(n / ((uint64_t)a.nx * (uint64_t)a.ny));
+    double dr = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+    for (int k = 0; k < Q; ++k) {
+      const double v = read_f<Q, T>(a, parity, k, x, y, z, n);
+      dr += v;
+      jx += cx<Q>(k) * v;
+      jy += cy<Q>(k) * v;
+      jz += cz<Q>(k) * v;
+    }
+    r = 1.0 + dr;
+    if (want_field) {
+      rho[n] = r;
+      u[3 * n + 0] = (jx + 0.5 * a.force[0]) / r;
+      u[3 * n + 1] = (jy + 0.5 * a.force[1]) / r;
+      u[3 * n + 2] = (jz + 0.5 * a.force[2]) / r;
+    }
+  }
+  __shared__ double sh[4];
+  const double s = block_sum256(r, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(256) void k_sum_final(const double *p, uint32_t n, double *out) {
+  double acc = 0.0;
+  for (uint32_t i = threadIdx.x; i < n; i += 256) acc += p[i];
+  __shared__ double sh[4];
+  const double s = block_sum256(acc, sh);
+  if (threadIdx.x == 0) out[0] = s;
+}
+
+uint32_t macro_blocks(const psm_field &f) { return (uint32_t)((f.N + 255) / 256); }
+
+SCArgs make_sc_args(const psm_field &f);  // defined in the C-ABI translation unit
+
+hipError_t launch_macro(const psm_field &f, int parity, double *rho, double *u, double *mass_partials,
+                        int want_field, hipStream_t st) {
+  const SCArgs a = make_sc_args(f);
+  const dim3 grid(macro_blocks(f)), block(256);
+  const int q = f.cfg.q, sto = f.cfg.storage;
+#define PSM_MACRO(QQ, TT) \
+  hipLaunchKernelGGL((k_macro<QQ, TT>), grid, block, 0, st, a, parity, rho, u, mass_partials, want_field)
+  if (q == 19 && sto == PSM_F64) PSM_MACRO(19, double);
+  else if (q == 19 && sto == PSM_F32) PSM_MACRO(19, float);
+  else if (q == 19 && sto == PSM_F16) PSM_MACRO(19, _Float16);
+  else if (q == 27 && sto == PSM_F64) PSM_MACRO(27, double);
+  else if (q == 27 && sto == PSM_F32) PSM_MACRO(27, float);
+  else PSM_MACRO(27, _Float16);
+#undef PSM_MACRO
+  return hipGetLastError();
+}
+
+hipError_t launch_mass_final(const double *partials, uint32_t n, double *out, hipStream_t st) {
+  hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, st, partials, n, out);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_fill_zero(uint4 *p, size_t n16, unsigned char *tail, size_t ntail) {
+  const size_t stride = (size_t)gridDim.x * 256u;
+  for (size_t i = (size_t)blockIdx.x * 256u + threadIdx.x; i < n16; i += stride) p[i] = make_uint4(0, 0, 0, 0);
+  if (blockIdx.x == 0 && threadIdx.x < ntail) tail[threadIdx.x] = 0;
+}
+
+hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t st) {
+  if (bytes == 0) return hipSuccess;
+  // callers pass 16-byte aligned buffers (device allocations, internal offsets)
+  const size_t n16 = bytes / 16, ntail = bytes % 16;
+  size_t blocks = (n16 + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  if (blocks == 0) blocks = 1;
+  hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)blocks), dim3(256), 0, st, (uint4 *)p, n16,
+                     (unsigned char *)p + n16 * 16, ntail);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_copy(const uint4 *__restrict__ s, uint4 *__restrict__ d, size_t n16) {
+  const size_t stride = (size_t)gridDim.x * 256u;
+  for (size_t i = (size_t)blockIdx.x * 256u + threadIdx.x; i < n16; i += stride) d[i] = s[i];
+}
+
+__global__ void k_copy_tail(const unsigned char *s, unsigned char *d, size_t n) {
+  if (threadIdx.x < n) d[threadIdx.x] = s[threadIdx.x];
+}
+
+hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t st) {
+  const size_t n16 = bytes / 16, tail = bytes % 16;
+  if (n16) {
+    size_t blocks = (n16 + 255) / 256;
+    if (blocks > 1u << 20) blocks = 1u << 20;
+    hipLaunchKernelGGL(k_copy, dim3((unsigned)blocks), dim3(256), 0, st, (const uint4 *)src, (uint4 *)dst, n16);
+  }
+  if (tail)
+    hipLaunchKernelGGL(k_copy_tail, dim3(1), dim3(16), 0, st, (const unsigned char *)src + n16 * 16,
+                       (unsigned char *)dst + n16 * 16, tail);
+  return hipGetLastError();
+}
+
+__global__ void k_flags_copy(const int32_t *s, int32_t *d) {
+  if (threadIdx.x < 4) d[threadIdx.x] = s[threadIdx.x];
+}
+
+hipError_t launch_flags_copy(const int32_t *src, int32_t *dst, hipStream_t st) {
+  hipLaunchKernelGGL(k_flags_copy, dim3(1), dim3(64), 0, st, src, dst);
+  return hipGetLastError();
+}
+
+}  // namespace psm

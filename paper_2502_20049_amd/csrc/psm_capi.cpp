@@ -1,0 +1,610 @@
+// C ABI of the PSM library: argument validation, host kinematics, handle
+// bookkeeping and kernel launches.  All device memory is caller-owned.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <string>
+
+#include "psm_internal.hpp"
+
+namespace psm {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string &msg) { g_err = msg; }
+
+int hip_fail(hipError_t e, const char *what) {
+  set_error(std::string(what) + ": " + hipGetErrorString(e));
+  return PSM_EHIP;
+}
+
+hipError_t launch_sc_f64(const psm_config &, const SCArgs &, int, bool, hipStream_t);
+hipError_t launch_sc_f32(const psm_config &, const SCArgs &, int, bool, hipStream_t);
+hipError_t launch_sc_f16(const psm_config &, const SCArgs &, int, bool, hipStream_t);
+
+static size_t storage_size(int st) { return st == PSM_F64 ? 8 : (st == PSM_F32 ? 4 : 2); }
+
+static void tile_shape(int nx, int &TX, int &lTX) {
+  // the smallest padded row length; ties go to the wider tile
+  int best = 256, bestpad = ((nx + 255) / 256) * 256;
+  for (int t : {128, 64}) {
+    const int pad = ((nx + t - 1) / t) * t;
+    if (pad < bestpad) {
+      best = t;
+      bestpad = pad;
+    }
+  }
+  TX = best;
+  lTX = best == 256 ? 8 : (best == 128 ? 7 : 6);
+}
+
+struct Layout {
+  int TX, TY, lTX, ntx, nty;
+  int64_t ntiles, N;
+  size_t off_ftp, off_red, work_bytes;
+  uint32_t red_count;
+};
+
+static Layout layout_of(const psm_config &c) {
+  Layout L{};
+  L.N = (int64_t)c.nx * c.ny * c.nz;
+  tile_shape(c.nx, L.TX, L.lTX);
+  L.TY = 256 / L.TX;
+  L.ntx = (c.nx + L.TX - 1) / L.TX;
+  L.nty = (c.ny + L.TY - 1) / L.TY;
+  L.ntiles = (int64_t)L.ntx * L.nty * c.nz;
+  const int mb = c.psm ? std::max(1, c.max_bodies) : 0;
+  L.off_ftp = 256;
+  L.off_red = L.off_ftp + (size_t)L.ntiles * mb * 6 * sizeof(double);
+  L.red_count = (uint32_t)((L.N + 255) / 256);
+  L.work_bytes = L.off_red + (size_t)L.red_count * sizeof(double) + 64;
+  return L;
+}
+
+static int check_config(const psm_config *c) {
+  if (!c) return set_error("null config"), PSM_EINVAL;
+  if (c->nx < 1 || c->ny < 1 || c->nz < 1) return set_error("grid dimensions must be >= 1"), PSM_EINVAL;
+  const int64_t N = (int64_t)c->nx * c->ny * c->nz;
+  if (N >= (int64_t)1 << 32) return set_error("more than 2^32 - 1 cells"), PSM_EUNSUP;
+  if (c->q != 19 && c->q != 27) return set_error("q must be 19 or 27"), PSM_EINVAL;
+  if (c->storage < PSM_F64 || c->storage > PSM_F16) return set_error("bad storage"), PSM_EINVAL;
+  if (c->psm != 0 && c->psm != 1) return set_error("psm must be 0 or 1"), PSM_EINVAL;
+  if (c->sc < 1 || c->sc > 3) return set_error("sc must be 1, 2 or 3"), PSM_EINVAL;
+  if (c->b_form != 0 && c->b_form != 1) return set_error("b_form must be 0 or 1"), PSM_EINVAL;
+  if (c->slots != 1 && c->slots != 2) return set_error("slots must be 1 or 2"), PSM_EINVAL;
+  if (c->psm && (c->max_bodies < 1 || c->max_bodies > PSM_MAX_BODIES))
+    return set_error("max_bodies must be in 1..8"), PSM_EINVAL;
+  if (!(c->tau > 0.5) || !isfinite(c->tau)) return set_error("tau must be > 1/2"), PSM_EINVAL;
+  if (!isfinite(c->magic) || !(c->magic > 0)) return set_error("magic must be > 0"), PSM_EINVAL;
+  for (int f = 0; f < 6; ++f)
+    if (c->bc[f] < PSM_PERIODIC || c->bc[f] > PSM_OUTLET) return set_error("bad face kind"), PSM_EINVAL;
+  for (int a = 0; a < 3; ++a)
+    if ((c->bc[2 * a] == PSM_PERIODIC) != (c->bc[2 * a + 1] == PSM_PERIODIC))
+      return set_error("periodic faces must come in pairs"), PSM_EINVAL;
+  const int64_t NS = N * (int64_t)storage_size(c->storage);
+  if (NS > ((int64_t)1 << 32) && c->sc != 1 && c->psm)
+    return set_error("direction arrays over 4 GiB support sc=1 only"), PSM_EUNSUP;
+  return PSM_OK;
+}
+
+SCArgs make_sc_args(const psm_field &f) {
+  SCArgs a;
+  memset(&a, 0, sizeof(a));
+  const psm_config &c = f.cfg;
+  a.pdf = (char *)f.pdf;
+  a.B0 = f.B0;
+  a.B1 = f.B1;
+  a.meta = f.meta;
+  a.ftp = f.ftp;
+  a.nx = c.nx;
+  a.ny = c.ny;
+  a.nz = c.nz;
+  a.N = (uint32_t)f.N;
+  a.TX = f.TX;
+  a.TY = f.TY;
+  a.lTX = f.lTX;
+  a.ntx = f.ntx;
+  a.nty = f.nty;
+  a.ntiles = (uint32_t)f.ntiles;
+  for (int i = 0; i < 6; ++i) a.bc[i] = c.bc[i];
+  for (int d = 0; d < 3; ++d) {
+    a.periodic[d] = c.bc[2 * d] == PSM_PERIODIC;
+    a.u_in[d] = (float)c.u_in[d];
+    a.u_in_d[d] = c.u_in[d];
+    a.force[d] = c.force[d];
+  }
+  a.has_force = (c.force[0] != 0.0 || c.force[1] != 0.0 || c.force[2] != 0.0);
+  a.lam_e = 1.0 / c.tau;
+  a.lam_o = 1.0 / (0.5 + c.magic / (c.tau - 0.5));
+  a.max_bodies = std::max(1, c.max_bodies);
+  a.slots = c.slots;
+  return a;
+}
+
+static IBox empty_box() {
+  IBox b;
+  for (int a = 0; a < 3; ++a) {
+    b.lo[a] = 1;
+    b.hi[a] = 0;
+  }
+  return b;
+}
+
+static bool box_empty(const IBox &b) { return b.hi[0] < b.lo[0] || b.hi[1] < b.lo[1] || b.hi[2] < b.lo[2]; }
+
+static IBox box_union(const IBox &a, const IBox &b) {
+  if (box_empty(a)) return b;
+  if (box_empty(b)) return a;
+  IBox r;
+  for (int d = 0; d < 3; ++d) {
+    r.lo[d] = std::min(a.lo[d], b.lo[d]);
+    r.hi[d] = std::max(a.hi[d], b.hi[d]);
+  }
+  return r;
+}
+
+}  // namespace psm
+
+using namespace psm;
+
+extern "C" {
+
+const char *psm_last_error(void) { return g_err.c_str(); }
+
+int psm_required_bytes(const psm_config *cfg, int which, size_t *out) {
+  int r = check_config(cfg);
+  if (r) return r;
+  if (!out) return set_error("null output"), PSM_EINVAL;
+  const Layout L = layout_of(*cfg);
+  switch (which) {
+    case PSM_BUF_PDF:
+      *out = (size_t)cfg->q * (size_t)L.N * storage_size(cfg->storage);
+      return PSM_OK;
+    case PSM_BUF_B:
+      *out = cfg->psm ? (size_t)L.N * 4 * cfg->slots + (size_t)L.N : 0;
+      return PSM_OK;
+    case PSM_BUF_WORK:
+      *out = L.work_bytes;
+      return PSM_OK;
+  }
+  return set_error("bad buffer id"), PSM_EINVAL;
+}
+
+int psm_lattice(int q, int32_t *c, double *w, int32_t *o) {
+  if ((q != 19 && q != 27) || !c || !w || !o) return set_error("psm_lattice: bad arguments"), PSM_EINVAL;
+  for (int k = 0; k < q; ++k) {
+    if (q == 19) {
+      c[3 * k] = cx<19>(k);
+      c[3 * k + 1] = cy<19>(k);
+      c[3 * k + 2] = cz<19>(k);
+      w[k] = wt<19>(k);
+      o[k] = opp<19>(k);
+    } else {
+      c[3 * k] = cx<27>(k);
+      c[3 * k + 1] = cy<27>(k);
+      c[3 * k + 2] = cz<27>(k);
+      w[k] = wt<27>(k);
+      o[k] = opp<27>(k);
+    }
+  }
+  return PSM_OK;
+}
+
+int psm_body_pose(const psm_motion *m, int64_t step, psm_body *out) {
+  if (!m || !out) return set_error("psm_body_pose: null argument"), PSM_EINVAL;
+  const double t = (double)step;
+  const double theta = m->theta0 + m->omega * t;
+  const double c = cos(theta), s = sin(theta), omc = 1.0 - c;
+  const double *a = m->axis;
+  const double K[9] = {0.0, -a[2], a[1], a[2], 0.0, -a[0], -a[1], a[0], 0.0};
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      const double d = (i == j) ? c : 0.0;
+      out->R[3 * i + j] = (d + (omc * a[i]) * a[j]) + s * K[3 * i + j];
+    }
+  for (int i = 0; i < 3; ++i) {
+    out->X[i] = m->x0[i] + m->v[i] * t;
+    out->V[i] = m->v[i];
+    out->W[i] = m->omega * a[i];
+  }
+  return PSM_OK;
+}
+
+int pdf_field_create(const psm_config *cfg, void *pdf, size_t pdf_bytes, void *b, size_t b_bytes, void *work,
+                     size_t work_bytes, void *stream, psm_field **out) {
+  (void)stream;
+  int r = check_config(cfg);
+  if (r) return r;
+  if (!out) return set_error("null output handle"), PSM_EINVAL;
+  size_t need_pdf, need_b, need_w;
+  psm_required_bytes(cfg, PSM_BUF_PDF, &need_pdf);
+  psm_required_bytes(cfg, PSM_BUF_B, &need_b);
+  psm_required_bytes(cfg, PSM_BUF_WORK, &need_w);
+  if (!pdf || !work || (cfg->psm && !b)) return set_error("null device buffer"), PSM_EINVAL;
+  if (pdf_bytes < need_pdf) return set_error("pdf buffer too small"), PSM_ESIZE;
+  if (b_bytes < need_b) return set_error("B buffer too small"), PSM_ESIZE;
+  if (work_bytes < need_w) return set_error("work buffer too small"), PSM_ESIZE;
+  if (((uintptr_t)pdf | (uintptr_t)work | (uintptr_t)b) & 15u)
+    return set_error("device buffers must be 16-byte aligned"), PSM_EINVAL;
+  psm_field *f = new (std::nothrow) psm_field;
+  if (!f) return set_error("out of host memory"), PSM_EINVAL;
+  memset(f, 0, sizeof(*f));
+  f->cfg = *cfg;
+  if (!cfg->psm) f->cfg.max_bodies = 0;
+  const Layout L = layout_of(*cfg);
+  f->pdf = pdf;
+  f->pdf_bytes = pdf_bytes;
+  f->N = L.N;
+  if (cfg->psm) {
+    f->B0 = (float *)b;
+    f->B1 = cfg->slots == 2 ? (float *)b + L.N : nullptr;
+    f->meta = (uint8_t *)((float *)b + L.N * cfg->slots);
+    f->b_bytes = b_bytes;
+  }
+  f->work = (char *)work;
+  f->work_bytes = work_bytes;
+  f->err = (int32_t *)work;
+  f->ftp = (double *)((char *)work + L.off_ftp);
+  f->red = (double *)((char *)work + L.off_red);
+  f->red_count = L.red_count;
+  f->TX = L.TX;
+  f->TY = L.TY;
+  f->lTX = L.lTX;
+  f->ntx = L.ntx;
+  f->nty = L.nty;
+  f->ntiles = L.ntiles;
+  for (int i = 0; i < PSM_MAX_BODIES; ++i) f->active[i] = empty_box();
+  f->opt_xcd_remap = 1;
+  if (hipGetDevice(&f->device) != hipSuccess) f->device = -1;
+  *out = f;
+  return PSM_OK;
+}
+
+int pdf_field_destroy(psm_field *f) {
+  if (!f) return set_error("null handle"), PSM_EINVAL;
+  delete f;
+  return PSM_OK;
+}
+
+int psm_field_reset(psm_field *f, void *stream) {
+  if (!f) return set_error("null handle"), PSM_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  size_t need;
+  psm_required_bytes(&f->cfg, PSM_BUF_PDF, &need);
+  hipError_t e = launch_fill_zero(f->pdf, need, st);
+  if (e == hipSuccess && f->cfg.psm) {
+    psm_required_bytes(&f->cfg, PSM_BUF_B, &need);
+    e = launch_fill_zero(f->B0, need, st);
+  }
+  if (e == hipSuccess) e = launch_fill_zero(f->work, 256, st);
+  if (e != hipSuccess) return hip_fail(e, "psm_field_reset");
+  f->nb_mapped = 0;
+  for (int i = 0; i < PSM_MAX_BODIES; ++i) {
+    f->have_prev[i] = false;
+    f->active[i] = empty_box();
+  }
+  return PSM_OK;
+}
+
+// ---- geometry ----------------------------------------------------------------
+static size_t geom_bytes(int s, const int32_t mmin[3], const int32_t dims[3], size_t *coarse_off) {
+  const size_t wx = ((size_t)dims[0] + 31) / 32;
+  const size_t bits = wx * (size_t)dims[1] * (size_t)dims[2] * 4;
+  int32_t cmin[3], cd[3];
+  coarse_extent(s, mmin, dims, cmin, cd);
+  const size_t off = (bits + 255) & ~(size_t)255;
+  *coarse_off = off;
+  return off + (size_t)cd[0] * cd[1] * cd[2];
+}
+
+int psm_geometry_box(int kind, const double *params, const double *verts, int64_t nv, int s, int32_t mmin[3],
+                     int32_t dims[3], size_t *dev_bytes) {
+  if (s < 0 || s > 3) return set_error("supersampling depth s must be 0..3"), PSM_EUNSUP;
+  if (!mmin || !dims || !dev_bytes || (!verts && !params)) return set_error("null argument"), PSM_EINVAL;
+  const int r = geom_box(kind, params, verts, nv, s, mmin, dims);
+  if (r) return set_error("bad geometry description"), r;
+  size_t off;
+  *dev_bytes = geom_bytes(s, mmin, dims, &off);
+  return PSM_OK;
+}
+
+int psm_voxelize_host(const double *verts, int64_t nv, const int32_t *tris, int64_t nt, int s,
+                      const int32_t mmin[3], const int32_t dims[3], uint32_t *bits) {
+  if (!verts || !tris || !mmin || !dims || !bits || nv <= 0 || nt <= 0 || s < 0 || s > 3)
+    return set_error("psm_voxelize_host: bad arguments"), PSM_EINVAL;
+  for (int64_t i = 0; i < 3 * nt; ++i)
+    if (tris[i] < 0 || tris[i] >= nv) return set_error("triangle index out of range"), PSM_EINVAL;
+  voxelize_rows(verts, tris, nt, s, mmin, dims, bits);
+  return PSM_OK;
+}
+
+int psm_analytic_host(int kind, const double *params, int s, const int32_t mmin[3], const int32_t dims[3],
+                      uint32_t *bits) {
+  if (!params || !mmin || !dims || !bits || s < 0 || s > 3 || (kind != PSM_SHAPE_ELLIPSOID && kind != PSM_SHAPE_CUBE))
+    return set_error("psm_analytic_host: bad arguments"), PSM_EINVAL;
+  analytic_rows(kind, params, s, mmin, dims, bits);
+  return PSM_OK;
+}
+
+static int geom_finish(psm_geom *g, void *dev, size_t bytes, hipStream_t st, psm_geom **out) {
+  size_t coff;
+  const size_t need = geom_bytes(g->s, g->mmin, g->dims, &coff);
+  if (bytes < need) {
+    delete[] g->host_bits;
+    delete g;
+    return set_error("geometry device buffer too small"), PSM_ESIZE;
+  }
+  int32_t cmin[3], cd[3];
+  coarse_extent(g->s, g->mmin, g->dims, cmin, cd);
+  const size_t nco = (size_t)cd[0] * cd[1] * cd[2];
+  g->host_coarse = new (std::nothrow) uint8_t[nco];
+  if (!g->host_coarse) {
+    delete[] g->host_bits;
+    delete g;
+    return set_error("out of host memory"), PSM_EINVAL;
+  }
+  coarse_map(g->s, g->mmin, g->dims, g->host_bits, g->cmin, g->cdims, g->host_coarse);
+  g->dev_bits = (uint32_t *)dev;
+  g->dev_coarse = (uint8_t *)dev + coff;
+  g->bytes = need;
+  double rb = 0.0;
+  const double h = ldexp(1.0, -g->s);
+  for (int a = 0; a < 3; ++a) {
+    const double m = std::max(fabs(g->mmin[a] * h), fabs((g->mmin[a] + g->dims[a]) * h));
+    rb += m * m;
+  }
+  g->r_bound = sqrt(rb);
+  const size_t wx = ((size_t)g->dims[0] + 31) / 32;
+  hipError_t e = hipMemcpyAsync(g->dev_bits, g->host_bits, wx * g->dims[1] * g->dims[2] * 4, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(g->dev_coarse, g->host_coarse, nco, hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) {
+    delete[] g->host_bits;
+    delete[] g->host_coarse;
+    delete g;
+    return hip_fail(e, "geometry upload");
+  }
+  *out = g;
+  return PSM_OK;
+}
+
+int geometry_field_create(const double *verts, int64_t nv, const int32_t *tris, int64_t nt, int s, void *dev,
+                          size_t bytes, void *stream, psm_geom **out) {
+  if (!out || !dev) return set_error("null argument"), PSM_EINVAL;
+  psm_geom *g = new (std::nothrow) psm_geom;
+  if (!g) return set_error("out of host memory"), PSM_EINVAL;
+  memset(g, 0, sizeof(*g));
+  g->s = s;
+  size_t b;
+  int r = psm_geometry_box(-1, nullptr, verts, nv, s, g->mmin, g->dims, &b);
+  if (r) {
+    delete g;
+    return r;
+  }
+  g->wx = (g->dims[0] + 31) / 32;
+  g->host_bits = new (std::nothrow) uint32_t[(size_t)g->wx * g->dims[1] * g->dims[2]];
+  if (!g->host_bits) {
+    delete g;
+    return set_error("out of host memory"), PSM_EINVAL;
+  }
+  r = psm_voxelize_host(verts, nv, tris, nt, s, g->mmin, g->dims, g->host_bits);
+  if (r) {
+    delete[] g->host_bits;
+    delete g;
+    return r;
+  }
+  return geom_finish(g, dev, bytes, (hipStream_t)stream, out);
+}
+
+int geometry_field_create_analytic(int kind, const double *params, int s, void *dev, size_t bytes, void *stream,
+                                   psm_geom **out) {
+  if (!out || !dev || !params) return set_error("null argument"), PSM_EINVAL;
+  psm_geom *g = new (std::nothrow) psm_geom;
+  if (!g) return set_error("out of host memory"), PSM_EINVAL;
+  memset(g, 0, sizeof(*g));
+  g->s = s;
+  size_t b;
+  int r = psm_geometry_box(kind, params, nullptr, 0, s, g->mmin, g->dims, &b);
+  if (r) {
+    delete g;
+    return r;
+  }
+  g->wx = (g->dims[0] + 31) / 32;
+  g->host_bits = new (std::nothrow) uint32_t[(size_t)g->wx * g->dims[1] * g->dims[2]];
+  if (!g->host_bits) {
+    delete g;
+    return set_error("out of host memory"), PSM_EINVAL;
+  }
+  analytic_rows(kind, params, s, g->mmin, g->dims, g->host_bits);
+  return geom_finish(g, dev, bytes, (hipStream_t)stream, out);
+}
+
+int geometry_field_destroy(psm_geom *g) {
+  if (!g) return set_error("null handle"), PSM_EINVAL;
+  delete[] g->host_bits;
+  delete[] g->host_coarse;
+  delete g;
+  return PSM_OK;
+}
+
+// ---- per-step path -----------------------------------------------------------
+static int check_bodies(const psm_field *f, const psm_body *bodies, int nb) {
+  if (!f) return set_error("null handle"), PSM_EINVAL;
+  if (nb < 0 || nb > f->cfg.max_bodies) return set_error("n_bodies exceeds max_bodies"), PSM_EINVAL;
+  if (nb > 0 && !bodies) return set_error("null bodies"), PSM_EINVAL;
+  for (int b = 0; b < nb; ++b)
+    for (int i = 0; i < 9; ++i)
+      if (!isfinite(bodies[b].R[i])) return set_error("non-finite pose"), PSM_EINVAL;
+  return PSM_OK;
+}
+
+int geometry_map_step(psm_field *f, const psm_body *bodies, const psm_geom *const *geoms, int nb, void *stream) {
+  int r = check_bodies(f, bodies, nb);
+  if (r) return r;
+  if (!f->cfg.psm) return set_error("geometry_map_step on a plain-LBM field"), PSM_EINVAL;
+  if (nb > 0 && !geoms) return set_error("null geometry list"), PSM_EINVAL;
+  if (f->nb_mapped && nb != f->nb_mapped)
+    return set_error("the number of bodies changed; reset the field first"), PSM_EINVAL;
+  MapArgs a;
+  memset(&a, 0, sizeof(a));
+  a.B0 = f->B0;
+  a.B1 = f->B1;
+  a.meta = f->meta;
+  a.err = f->err;
+  a.nx = f->cfg.nx;
+  a.ny = f->cfg.ny;
+  a.nz = f->cfg.nz;
+  a.nb = nb;
+  a.slots = f->cfg.slots;
+  a.b_form = f->cfg.b_form;
+  a.tau = f->cfg.tau;
+  uint32_t maxcells = 0;
+  IBox now[PSM_MAX_BODIES];
+  const int n3[3] = {f->cfg.nx, f->cfg.ny, f->cfg.nz};
+  for (int b = 0; b < nb; ++b) {
+    const psm_geom *g = geoms[b];
+    if (!g) return set_error("null geometry"), PSM_EINVAL;
+    MapBodyK &m = a.body[b];
+    memcpy(m.R, bodies[b].R, sizeof(m.R));
+    memcpy(m.X, bodies[b].X, sizeof(m.X));
+    m.bits = g->dev_bits;
+    m.coarse = g->dev_coarse;
+    m.s = g->s;
+    m.wx = g->wx;
+    for (int d = 0; d < 3; ++d) {
+      m.mmin[d] = g->mmin[d];
+      m.dims[d] = g->dims[d];
+      m.cmin[d] = g->cmin[d];
+      m.cdims[d] = g->cdims[d];
+      // |(R^T delta)_d| <= sum_j |R_jd| (1 - h)/2; plus two fixed-point units
+      const double sum = fabs(m.R[d]) + fabs(m.R[3 + d]) + fabs(m.R[6 + d]);
+      m.dabs[d] = (long long)ceil(sum * (1.0 - ldexp(1.0, -g->s)) * 0.5 * ldexp(1.0, g->s + 32)) + 2;
+    }
+    // swept box: cells whose centre lies within r_bound + 2 of X
+    IBox A;
+    bool empty = false;
+    for (int d = 0; d < 3; ++d) {
+      const double lo = floor(m.X[d] - g->r_bound - 2.5), hi = ceil(m.X[d] + g->r_bound + 2.5);
+      A.lo[d] = (int)std::max(0.0, std::min((double)n3[d], lo));
+      A.hi[d] = (int)std::min((double)n3[d] - 1, std::max(-1.0, hi));
+      if (A.hi[d] < A.lo[d]) empty = true;
+    }
+    if (empty) A = empty_box();
+    now[b] = A;
+    m.active = A;
+    m.region = f->have_prev[b] ? box_union(A, f->active[b]) : A;
+    if (box_empty(m.region)) {
+      m.region_cells = 0;
+    } else {
+      const uint64_t cells = (uint64_t)(m.region.hi[0] - m.region.lo[0] + 1) *
+                             (uint64_t)(m.region.hi[1] - m.region.lo[1] + 1) *
+                             (uint64_t)(m.region.hi[2] - m.region.lo[2] + 1);
+      if (cells >= (1ull << 32) - 256) return set_error("swept box too large"), PSM_EUNSUP;
+      m.region_cells = (uint32_t)cells;
+    }
+    maxcells = std::max(maxcells, m.region_cells);
+  }
+  hipError_t e = launch_map(a, maxcells, 0, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "geometry_map_step launch");
+  for (int b = 0; b < nb; ++b) {
+    f->active[b] = now[b];
+    f->have_prev[b] = true;
+  }
+  f->nb_mapped = nb;
+  return PSM_OK;
+}
+
+int psm_stream_collide(psm_field *f, const psm_body *bodies, int nb, int64_t step, void *stream) {
+  int r = check_bodies(f, bodies, nb);
+  if (r) return r;
+  if (step < 0) return set_error("negative step"), PSM_EINVAL;
+  if (f->cfg.psm && nb > 0 && nb != f->nb_mapped)
+    return set_error("psm_stream_collide: bodies do not match the mapped field"), PSM_EINVAL;
+  SCArgs a = make_sc_args(*f);
+  a.nb = f->cfg.psm ? nb : 0;
+  for (int b = 0; b < a.nb; ++b) {
+    BodyK &k = a.body[b];
+    for (int d = 0; d < 3; ++d) {
+      k.X[d] = bodies[b].X[d];
+      k.V[d] = bodies[b].V[d];
+      k.W[d] = bodies[b].W[d];
+    }
+    const IBox &B = f->active[b];
+    if (box_empty(B)) {
+      for (int d = 0; d < 3; ++d) {
+        k.tlo[d] = 1;
+        k.thi[d] = 0;
+      }
+    } else {
+      k.tlo[0] = B.lo[0] / f->TX;
+      k.thi[0] = B.hi[0] / f->TX;
+      k.tlo[1] = B.lo[1] / f->TY;
+      k.thi[1] = B.hi[1] / f->TY;
+      k.tlo[2] = B.lo[2];
+      k.thi[2] = B.hi[2];
+    }
+  }
+  a.force_general = f->opt_general_path;
+  a.xcd_remap = f->opt_xcd_remap;
+  const int parity = (int)(step & 1);
+  const bool big = (uint64_t)f->N * storage_size(f->cfg.storage) > 0xFFFFFFFFull;
+  hipError_t e;
+  switch (f->cfg.storage) {
+    case PSM_F64: e = launch_sc_f64(f->cfg, a, parity, big, (hipStream_t)stream); break;
+    case PSM_F32: e = launch_sc_f32(f->cfg, a, parity, big, (hipStream_t)stream); break;
+    default: e = launch_sc_f16(f->cfg, a, parity, big, (hipStream_t)stream); break;
+  }
+  if (e != hipSuccess) return hip_fail(e, "psm_stream_collide launch");
+  return PSM_OK;
+}
+
+int body_force_torque(psm_field *f, int nb, double *ft, void *stream) {
+  if (!f || !ft) return set_error("null argument"), PSM_EINVAL;
+  if (!f->cfg.psm) return set_error("body_force_torque on a plain-LBM field"), PSM_EINVAL;
+  if (nb < 1 || nb > f->nb_mapped) return set_error("n_bodies does not match the mapped bodies"), PSM_EINVAL;
+  hipError_t e = launch_ft_reduce(*f, nb, ft, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "body_force_torque launch");
+  return PSM_OK;
+}
+
+int psm_mass_fp64(psm_field *f, int64_t step, double *out, void *stream) {
+  if (!f || !out) return set_error("null argument"), PSM_EINVAL;
+  hipError_t e = launch_macro(*f, (int)(step & 1), nullptr, nullptr, f->red, 0, (hipStream_t)stream);
+  if (e == hipSuccess) e = launch_mass_final(f->red, f->red_count, out, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "psm_mass_fp64 launch");
+  return PSM_OK;
+}
+
+int psm_macroscopic(psm_field *f, int64_t step, double *rho, double *u, void *stream) {
+  if (!f || !rho || !u) return set_error("null argument"), PSM_EINVAL;
+  hipError_t e = launch_macro(*f, (int)(step & 1), rho, u, f->red, 1, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "psm_macroscopic launch");
+  return PSM_OK;
+}
+
+int psm_set_option(psm_field *f, int option, int value) {
+  if (!f) return set_error("null handle"), PSM_EINVAL;
+  switch (option) {
+    case PSM_OPT_GENERAL_PATH: f->opt_general_path = value ? 1 : 0; return PSM_OK;
+    case PSM_OPT_XCD_REMAP: f->opt_xcd_remap = value ? 1 : 0; return PSM_OK;
+  }
+  return set_error("unknown option"), PSM_EINVAL;
+}
+
+int psm_error_flags(psm_field *f, int32_t *out, void *stream) {
+  if (!f || !out) return set_error("null argument"), PSM_EINVAL;
+  hipError_t e = launch_flags_copy(f->err, out, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "psm_error_flags launch");
+  return PSM_OK;
+}
+
+int psm_stream_copy(const void *src, void *dst, size_t bytes, void *stream) {
+  if (!src || !dst) return set_error("null argument"), PSM_EINVAL;
+  if (((uintptr_t)src | (uintptr_t)dst) & 15u) return set_error("copy buffers must be 16-byte aligned"), PSM_EINVAL;
+  hipError_t e = launch_copy(src, dst, bytes, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "psm_stream_copy launch");
+  return PSM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,212 @@
+// Internal definitions of the PSM library: lattice tables, handle layouts and
+// kernel argument blocks.  Host and device code include this file.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/psm.h"
+
+namespace psm {
+
+// ---------------------------------------------------------------------------
+// Velocity sets.  Order: 0 = rest, 1..H = half set, H+k = -(k) (so the
+// opposite of i is i +- H).  D3Q19 half set: 3 axis + 6 face diagonals; D3Q27
+// adds the 4 body diagonals.  Weights by |c|^2: D3Q19 1/3, 1/18, 1/36;
+// D3Q27 8/27, 2/27, 1/54, 1/216.
+// ---------------------------------------------------------------------------
+template <int Q>
+struct Lat;
+
+template <>
+struct Lat<19> {
+  static constexpr int H = 9;
+  static constexpr int hx[9] = {1, 0, 0, 1, 1, 1, 1, 0, 0};
+  static constexpr int hy[9] = {0, 1, 0, 1, -1, 0, 0, 1, 1};
+  static constexpr int hz[9] = {0, 0, 1, 0, 0, 1, -1, 1, -1};
+  static constexpr double w0 = 1.0 / 3.0;
+  static constexpr double wn(int m) { return m == 1 ? 1.0 / 18.0 : 1.0 / 36.0; }
+};
+
+template <>
+struct Lat<27> {
+  static constexpr int H = 13;
+  static constexpr int hx[13] = {1, 0, 0, 1, 1, 1, 1, 0, 0, 1, 1, 1, 1};
+  static constexpr int hy[13] = {0, 1, 0, 1, -1, 0, 0, 1, 1, 1, 1, -1, -1};
+  static constexpr int hz[13] = {0, 0, 1, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1};
+  static constexpr double w0 = 8.0 / 27.0;
+  static constexpr double wn(int m) { return m == 1 ? 2.0 / 27.0 : (m == 2 ? 1.0 / 54.0 : 1.0 / 216.0); }
+};
+
+// full-set accessors (k in [0, Q))
+template <int Q>
+__host__ __device__ constexpr int cx(int k) {
+  return k == 0 ? 0 : (k <= Lat<Q>::H ? Lat<Q>::hx[k - 1] : -Lat<Q>::hx[k - 1 - Lat<Q>::H]);
+}
+template <int Q>
+__host__ __device__ constexpr int cy(int k) {
+  return k == 0 ? 0 : (k <= Lat<Q>::H ? Lat<Q>::hy[k - 1] : -Lat<Q>::hy[k - 1 - Lat<Q>::H]);
+}
+template <int Q>
+__host__ __device__ constexpr int cz(int k) {
+  return k == 0 ? 0 : (k <= Lat<Q>::H ? Lat<Q>::hz[k - 1] : -Lat<Q>::hz[k - 1 - Lat<Q>::H]);
+}
+template <int Q>
+__host__ __device__ constexpr int opp(int k) {
+  return k == 0 ? 0 : (k <= Lat<Q>::H ? k + Lat<Q>::H : k - Lat<Q>::H);
+}
+template <int Q>
+__host__ __device__ constexpr double wt(int k) {
+  return k == 0 ? Lat<Q>::w0 : Lat<Q>::wn(cx<Q>(k) * cx<Q>(k) + cy<Q>(k) * cy<Q>(k) + cz<Q>(k) * cz<Q>(k));
+}
+
+// ---------------------------------------------------------------------------
+// Face kinds and their precedence (wall > inlet > outlet).
+// ---------------------------------------------------------------------------
+enum : int { K_NONE = 0, K_WALL = PSM_WALL, K_INLET = PSM_INLET, K_OUTLET = PSM_OUTLET };
+
+__host__ __device__ inline int face_rank(int kind) {
+  return kind == K_WALL ? 3 : (kind == K_INLET ? 2 : (kind == K_OUTLET ? 1 : 0));
+}
+__host__ __device__ inline int face_merge(int a, int b) { return face_rank(b) > face_rank(a) ? b : a; }
+
+struct IBox {
+  int lo[3];
+  int hi[3];  // inclusive; empty when any hi < lo
+};
+
+// per-body data of the stream-collide kernel
+struct BodyK {
+  double X[3];
+  double V[3];
+  double W[3];
+  int tlo[3];  // tile box of the body's swept cells (force/torque partials)
+  int thi[3];
+};
+
+struct SCArgs {
+  char *pdf;
+  const float *B0;
+  const float *B1;
+  const uint8_t *meta;
+  double *ftp;  // [tile][max_bodies][6]
+  int nx, ny, nz;
+  uint32_t N;
+  int TX, TY, lTX;  // tile shape, log2(TX)
+  int ntx, nty;
+  uint32_t ntiles;
+  int bc[6];
+  int periodic[3];
+  float u_in[3];
+  double u_in_d[3];
+  double force[3];
+  int has_force;
+  double lam_e, lam_o;
+  int nb;
+  int max_bodies;
+  int slots;
+  int force_general;  // PSM_OPT_GENERAL_PATH: general addressing for every row
+  int xcd_remap;      // PSM_OPT_XCD_REMAP: contiguous tile ranges per XCD
+  BodyK body[PSM_MAX_BODIES];
+};
+
+// per-body data of the mapping kernel
+struct MapBodyK {
+  double R[9];
+  double X[3];
+  const uint32_t *bits;
+  const uint8_t *coarse;
+  int mmin[3], dims[3], wx;
+  int cmin[3], cdims[3];
+  int s;
+  long long dabs[3];  // bound on |fixed-point sub-sample offset| per axis
+  IBox region;        // cells rewritten this step (swept box now and before)
+  IBox active;        // cells that can touch the body this step
+  uint32_t region_cells;
+};
+
+struct MapArgs {
+  float *B0;
+  float *B1;
+  uint8_t *meta;
+  int32_t *err;
+  int nx, ny, nz;
+  int nb;
+  int slots;
+  int b_form;
+  double tau;
+  MapBodyK body[PSM_MAX_BODIES];
+};
+
+}  // namespace psm
+
+// ---------------------------------------------------------------------------
+// Host handles
+// ---------------------------------------------------------------------------
+struct psm_field {
+  psm_config cfg;
+  void *pdf;
+  size_t pdf_bytes;
+  float *B0;
+  float *B1;
+  uint8_t *meta;
+  size_t b_bytes;
+  char *work;
+  size_t work_bytes;
+  int32_t *err;
+  double *ftp;
+  double *red;  // reduction scratch
+  size_t red_count;
+  int64_t N;
+  int TX, TY, lTX, ntx, nty;
+  int64_t ntiles;
+  int nb_mapped;
+  bool have_prev[PSM_MAX_BODIES];
+  psm::IBox active[PSM_MAX_BODIES];
+  int device;
+  int opt_general_path;
+  int opt_xcd_remap;
+};
+
+struct psm_geom {
+  int s;
+  int32_t mmin[3], dims[3];
+  int wx;
+  int32_t cmin[3], cdims[3];
+  double r_bound;  // every inside lattice centre lies within r_bound of the body origin
+  uint32_t *dev_bits;
+  uint8_t *dev_coarse;
+  size_t bytes;
+  uint32_t *host_bits;   // kept until destroy (source of the async upload)
+  uint8_t *host_coarse;
+};
+
+namespace psm {
+void set_error(const std::string &msg);
+int hip_fail(hipError_t e, const char *what);
+
+// launchers (defined in the .hip translation units)
+hipError_t launch_stream_collide(const psm_config &cfg, const SCArgs &a, int parity, hipStream_t st);
+hipError_t launch_map(const MapArgs &a, uint32_t max_region_cells, int any_s_max, hipStream_t st);
+hipError_t launch_ft_reduce(const psm_field &f, int nb, double *ft, hipStream_t st);
+hipError_t launch_macro(const psm_field &f, int parity, double *rho, double *u, double *mass_partials,
+                        int want_field, hipStream_t st);
+hipError_t launch_mass_final(const double *partials, uint32_t n, double *out, hipStream_t st);
+hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t st);
+hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t st);
+hipError_t launch_flags_copy(const int32_t *src, int32_t *dst, hipStream_t st);
+uint32_t macro_blocks(const psm_field &f);
+
+// host geometry
+int geom_box(int kind, const double *params, const double *verts, int64_t nv, int s, int32_t mmin[3],
+             int32_t dims[3]);
+void voxelize_rows(const double *verts, const int32_t *tris, int64_t nt, int s, const int32_t mmin[3],
+                   const int32_t dims[3], uint32_t *bits);
+void analytic_rows(int kind, const double *params, int s, const int32_t mmin[3], const int32_t dims[3],
+                   uint32_t *bits);
+void coarse_map(int s, const int32_t mmin[3], const int32_t dims[3], const uint32_t *bits, int32_t cmin[3],
+                int32_t cdims[3], uint8_t *out);
+void coarse_extent(int s, const int32_t mmin[3], const int32_t dims[3], int32_t cmin[3], int32_t cdims[3]);
+}  // namespace psm

@@ -422,3 +422,31 @@ def workload_capacity(n=1024, steps=500, radius=300.0, s=2, n_chord=100, n_span=
     return Workload(f"capacity_{n}^3_d3q19", n, n, n, 19, "f32", 0.8, 3 / 16, (0, 0, 0),
                     ("inlet", "outlet", "periodic", "periodic", "periodic", "periodic"), (0.05, 0, 0),
                     1, 0, 1, steps, bodies)
+
+
+# ----------------------------------------------------------------------------
+# random lattice states keyed by velocity (independent of any direction order)
+# ----------------------------------------------------------------------------
+def velocity_code(c) -> int:
+    """Base-3 code (cx+1) + 3(cy+1) + 9(cz+1) in [0, 27) of a lattice velocity."""
+    return int(c[0] + 1) + 3 * int(c[1] + 1) + 9 * int(c[2] + 1)
+
+
+def random_state(seed: int, velocities, n_cells: int, cells, amp: float = 8.0):
+    """delta f (len(cells), q) for the given velocities (q,3): exact in fp16 when
+    ``amp`` is a power of two up to 8 (values are multiples of amp * 2^-17)."""
+    cells = np.asarray(cells, dtype=np.int64)
+    out = np.empty((cells.shape[0], len(velocities)))
+    for j, c in enumerate(velocities):
+        out[:, j] = pdf_deviation(seed, 27, n_cells, velocity_code(c), cells) * amp
+    return out
+
+
+def random_state_torch(seed: int, c, n_cells: int, device, dtype, amp: float = 8.0):
+    """Whole (q, n_cells) delta f for the velocities c (q,3) as a torch tensor."""
+    import torch
+
+    out = torch.empty((len(c), n_cells), dtype=dtype, device=device)
+    for k, ck in enumerate(c):
+        out[k] = pdf_deviation_torch(seed, 27, n_cells, velocity_code(ck), device, torch.float64) .mul_(amp).to(dtype)
+    return out

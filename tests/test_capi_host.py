@@ -1,0 +1,193 @@
+"""Host-side checks of the C ABI (no GPU): exported symbols, sizes, argument
+validation, lattice table, kinematics and the host voxeliser, each against the
+oracle or a closed form."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import psm_inputs as pi
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def capi():
+    from paper_2502_20049_amd import _capi
+
+    return _capi
+
+
+@pytest.fixture(scope="module")
+def sim():
+    from paper_2502_20049_amd import sim
+
+    return sim
+
+
+def _declared_functions():
+    src = open(os.path.join(ROOT, "include", "psm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(\w+)\s*\(", src, flags=re.M)
+    return sorted(set(n for n in names if n not in ("defined",)))
+
+
+def test_library_exports_every_declared_symbol(capi):
+    decl = _declared_functions()
+    assert len(decl) >= 20
+    for name in decl:
+        assert hasattr(capi.lib, name), name
+    assert sorted(decl) == sorted(capi.EXPORTS)
+
+
+def _cfg(sim, **kw):
+    wl = pi.Workload("t", 40, 30, 20, bodies=[])
+    for k, v in kw.items():
+        setattr(wl, k, v)
+    return sim.make_config(wl, max_bodies=2)
+
+
+def test_required_bytes(capi, sim):
+    cfg = _cfg(sim)
+    N = 40 * 30 * 20
+    assert sim.required_bytes(cfg, capi.PSM_BUF_PDF) == 19 * N * 4
+    assert sim.required_bytes(cfg, capi.PSM_BUF_B) == N * 4 + N
+    cfg.slots = 2
+    assert sim.required_bytes(cfg, capi.PSM_BUF_B) == 2 * N * 4 + N
+    cfg.q, cfg.storage = 27, capi.PSM_F16
+    assert sim.required_bytes(cfg, capi.PSM_BUF_PDF) == 27 * N * 2
+    cfg.psm = 0
+    assert sim.required_bytes(cfg, capi.PSM_BUF_B) == 0
+    assert sim.required_bytes(cfg, capi.PSM_BUF_WORK) > 256
+
+
+@pytest.mark.parametrize("field,value,code", [
+    ("q", 15, -1), ("storage", 7, -1), ("sc", 4, -1), ("slots", 3, -1), ("tau", 0.5, -1),
+    ("b_form", 2, -1), ("max_bodies", 9, -1), ("nx", 0, -1),
+])
+def test_config_validation(capi, sim, field, value, code):
+    cfg = _cfg(sim)
+    setattr(cfg, field, value)
+    n = C.c_size_t()
+    assert capi.lib.psm_required_bytes(C.byref(cfg), 0, C.byref(n)) == code
+    assert capi.last_error()
+
+
+def test_unpaired_periodic_face_rejected(capi, sim):
+    cfg = _cfg(sim)
+    cfg.bc[0] = capi.PSM_PERIODIC
+    cfg.bc[1] = capi.PSM_WALL
+    n = C.c_size_t()
+    assert capi.lib.psm_required_bytes(C.byref(cfg), 0, C.byref(n)) == capi.PSM_EINVAL
+
+
+def test_create_rejects_bad_buffers(capi, sim):
+    cfg = _cfg(sim)
+    h = C.c_void_p()
+    need = sim.required_bytes(cfg, capi.PSM_BUF_PDF)
+    # null buffers and undersized buffers are rejected before any device access
+    assert capi.lib.pdf_field_create(C.byref(cfg), None, need, None, 0, None, 0, None, C.byref(h)) == capi.PSM_EINVAL
+    fake = C.c_void_p(1 << 20)  # never dereferenced: size checks fail first
+    assert capi.lib.pdf_field_create(C.byref(cfg), fake, need - 1, fake, 1 << 30, fake, 1 << 30, None,
+                                     C.byref(h)) == capi.PSM_ESIZE
+    assert capi.lib.pdf_field_destroy(None) == capi.PSM_EINVAL
+
+
+def test_lattice_matches_oracle_set(orc, sim):
+    for q in (19, 27):
+        c, w, o = sim.lattice(q)
+        oc, ow, oo = orc.lattice(q)
+        # same velocity set and weights, in a different order
+        key = {tuple(v): wv for v, wv in zip(oc, ow)}
+        assert len(key) == q
+        for v, wv in zip(c, w):
+            assert key[tuple(v)] == wv
+        assert np.all(c[o] == -c)
+        assert c[0].tolist() == [0, 0, 0]
+
+
+def test_body_pose_bit_identical_to_oracle(orc, sim):
+    rng = np.random.default_rng(1)
+    for trial in range(20):
+        ax = rng.normal(size=3)
+        ax /= np.linalg.norm(ax)
+        m = pi.Motion(axis=tuple(ax), theta0=float(rng.uniform(-3, 3)), omega=float(rng.uniform(-0.01, 0.01)),
+                      x0=tuple(rng.uniform(0, 100, 3)), v=tuple(rng.uniform(-0.1, 0.1, 3)))
+        for t in (0, 1, 17, 799, 123456):
+            a = sim.body_pose(m, t)
+            b = orc.pose_at(m, t)
+            assert list(a.R) == list(b.R) and list(a.X) == list(b.X)
+            assert list(a.V) == list(b.V) and list(a.W) == list(b.W)
+
+
+def _box(capi, shape, s, mesh=None):
+    dp = C.POINTER(C.c_double)
+    mmin = (C.c_int32 * 3)()
+    dims = (C.c_int32 * 3)()
+    nb = C.c_size_t()
+    if mesh is not None:
+        v = np.ascontiguousarray(mesh.verts)
+        assert capi.lib.psm_geometry_box(-1, None, v.ctypes.data_as(dp), v.shape[0], s, mmin, dims, C.byref(nb)) == 0
+    else:
+        p = np.zeros(3)
+        p[: len(shape[1])] = shape[1]
+        assert capi.lib.psm_geometry_box(shape[0], p.ctypes.data_as(dp), None, 0, s, mmin, dims, C.byref(nb)) == 0
+    return np.array(mmin), np.array(dims)
+
+
+def _unpack(bits, dims):
+    wx = (dims[0] + 31) // 32
+    w = bits.reshape(dims[2], dims[1], wx)
+    out = np.zeros((dims[2], dims[1], wx * 32), dtype=np.uint8)
+    for b in range(32):
+        out[:, :, b::32] = (w >> np.uint32(b)) & 1
+    return out[:, :, : dims[0]]
+
+
+def test_analytic_fill_matches_oracle(capi, orc):
+    for shape, params, s in [(capi.PSM_SHAPE_ELLIPSOID, (5.0, 3.0, 2.0), 2), (capi.PSM_SHAPE_ELLIPSOID, (6.0, 6.0, 6.0), 1),
+                             (capi.PSM_SHAPE_CUBE, (2.5,), 3)]:
+        mmin, dims = _box(capi, (shape, params), s)
+        wx = (dims[0] + 31) // 32
+        bits = np.zeros(wx * dims[1] * dims[2], dtype=np.uint32)
+        p = np.zeros(3)
+        p[: len(params)] = params
+        assert capi.lib.psm_analytic_host(shape, p.ctypes.data_as(C.POINTER(C.c_double)), s,
+                                          (C.c_int32 * 3)(*mmin), (C.c_int32 * 3)(*dims),
+                                          bits.ctypes.data_as(C.POINTER(C.c_uint32))) == 0
+        got = _unpack(bits, dims)
+        g = orc.OracleGeometry(pi.Shape("ellipsoid" if shape == 0 else "cube", params), s)
+        mz, my, mx = np.meshgrid(*[np.arange(mmin[a], mmin[a] + dims[a]) for a in (2, 1, 0)], indexing="ij")
+        ref = g.inside(np.stack([mx.ravel(), my.ravel(), mz.ravel()], 1)).reshape(got.shape)
+        assert np.array_equal(got.astype(bool), ref)
+        # one LBM cell of padding around the shape: the border planes are empty
+        assert got[0].sum() == 0 and got[-1].sum() == 0 and got[:, :, 0].sum() == 0
+
+
+@pytest.mark.parametrize("which", ["rotor", "ellipsoid", "cube"])
+def test_voxeliser_matches_winding_number(capi, orc, which):
+    if which == "rotor":
+        mesh = pi.rotor_mesh(pi.RotorSpec(n_blades=3, radius=5.0, hub_radius=1.25, hub_length=2.5, chord_root=1.5,
+                                          chord_tip=0.75, n_chord=8, n_span=5, n_hub=16, seed=3))
+        s = 2
+    elif which == "ellipsoid":
+        mesh = pi.ellipsoid_mesh(4.0, 2.5, 1.75, n_lat=10, n_lon=20, phase=0.1)
+        s = 2
+    else:
+        mesh = pi.cube_mesh(1.3)
+        s = 3
+    mmin, dims = _box(capi, None, s, mesh)
+    wx = (dims[0] + 31) // 32
+    bits = np.zeros(wx * dims[1] * dims[2], dtype=np.uint32)
+    v = np.ascontiguousarray(mesh.verts)
+    t = np.ascontiguousarray(mesh.tris)
+    assert capi.lib.psm_voxelize_host(v.ctypes.data_as(C.POINTER(C.c_double)), v.shape[0],
+                                      t.ctypes.data_as(C.POINTER(C.c_int32)), t.shape[0], s,
+                                      (C.c_int32 * 3)(*mmin), (C.c_int32 * 3)(*dims),
+                                      bits.ctypes.data_as(C.POINTER(C.c_uint32))) == 0
+    got = _unpack(bits, dims).astype(bool)
+    ref = orc.voxelize(v, t, s, mmin.astype(np.int32), dims.astype(np.int32)).reshape(got.shape).astype(bool)
+    assert got.sum() > 50
+    assert np.array_equal(got, ref), int((got != ref).sum())

@@ -1,0 +1,260 @@
+"""GPU parity of the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerances (max abs error of f, lattice units) follow from the arithmetic:
+FP64 storage/arithmetic: a few ulp of O(1) sums over two steps -> 1e-13;
+FP32: arithmetic rounding ~6e-8 relative on O(1) terms (rho, 1 - B) over two
+steps -> 2e-6; FP16 storage: half an ulp of |delta f| <= 0.04 per store
+(2^-11 * 0.04 = 2e-5) over two steps -> 6e-5.  Solid fractions and body ids
+must match bit for bit.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import psm_inputs as pi
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-13, "f32": 2e-6, "f16": 6e-5}
+TOL_FT = {"f64": 1e-12, "f32": 2e-5, "f16": 5e-4}
+
+
+@pytest.fixture(scope="module")
+def sim():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2502_20049_amd import sim as s
+
+    return s
+
+
+@pytest.fixture(scope="module")
+def gc():
+    import gpu_common
+
+    return gpu_common
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+BCS = {
+    "periodic": ("periodic",) * 6,
+    "channel": ("inlet", "outlet", "wall", "wall", "wall", "wall"),
+    "box": ("wall",) * 6,
+    "mixed": ("inlet", "outlet", "periodic", "periodic", "wall", "wall"),
+    "zpipe": ("periodic", "periodic", "wall", "wall", "inlet", "outlet"),
+}
+
+
+def _workload(q, storage, bc, sc=1, two=False, s=2, force=(0, 0, 0), nx=70, ny=22, nz=13, b_form=0):
+    bodies = [pi.Body(pi.Shape("ellipsoid", (9.0, 5.0, 4.0)),
+                      pi.Motion(axis=(0.0, 0.6, 0.8), theta0=0.3, omega=0.05, x0=(31.0, 11.0, 6.0)), s=s)]
+    if two:
+        bodies.append(pi.Body(pi.Shape("ellipsoid", (4.0, 4.0, 4.0)),
+                              pi.Motion(axis=(0, 0, 1), omega=-0.1, x0=(39.0, 12.0, 7.0), v=(0.2, 0.0, 0.0)), s=1))
+    return pi.Workload(f"small_{q}_{storage}_{bc}", nx, ny, nz, q, storage, 0.8, 3 / 16, force, BCS[bc],
+                       (0.04, 0.01, -0.02), sc, b_form, 2 if two else 1, 2, bodies)
+
+
+def _two_step_compare(orc, sim, gc, wl, seed=5, general=False):
+    import torch
+
+    torch.manual_seed(0)
+    f = sim.Field(wl)
+    if general:
+        f.set_option(1, 1)
+    gc.load_random_state(f, seed)
+    run = orc.Run(wl, f0=gc.oracle_state(orc, wl, seed))
+    out = {}
+    for t in range(2):
+        f.step(t)
+        ftg = f.force_torque().cpu().numpy().copy()
+        torch.cuda.synchronize()
+        Bg = gc.gpu_B_per_body(f, len(wl.bodies))
+        run.advance(1)
+        assert np.array_equal(Bg, run.B), f"B mismatch at t={t}: {(Bg != run.B).sum()} cells"
+        fto = run.ft[-1]
+        scale = max(1e-12, np.abs(fto).max())
+        err = np.abs(ftg - fto).max() / scale
+        _say(f"  t={t} F/T rel err {err:.2e}")
+        assert err < TOL_FT[wl.storage], (ftg, fto)
+    g = gc.gpu_state_oracle_order(f, orc, sim)
+    err = np.abs(g - run.f).max()
+    _say(f"  {wl.name}: max |f_gpu - f_oracle| = {err:.3e}")
+    assert err < TOL[wl.storage]
+    flags = f.error_flags().cpu().numpy()
+    assert flags[0] == 0
+    out["f"] = f
+    return out
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
+@pytest.mark.parametrize("q", [19, 27])
+@pytest.mark.parametrize("bc", list(BCS))
+def test_two_steps_parity(orc, sim, gc, q, storage, bc):
+    _say(f"[two_steps] q={q} storage={storage} bc={bc}")
+    wl = _workload(q, storage, bc)
+    _two_step_compare(orc, sim, gc, wl)
+
+
+@pytest.mark.parametrize("sc", [1, 2, 3])
+@pytest.mark.parametrize("q", [19, 27])
+def test_solid_operators_two_bodies_force(orc, sim, gc, sc, q):
+    """SC1/SC2/SC3, two overlapping moving bodies (two slots, one translating),
+    Guo body force, tau-weighted B (eq. 6) for SC2."""
+    _say(f"[solid_ops] q={q} sc={sc}")
+    wl = _workload(q, "f64", "mixed", sc=sc, two=True, force=(1e-4, -5e-5, 2e-5), b_form=1 if sc == 2 else 0)
+    _two_step_compare(orc, sim, gc, wl)
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_fast_path_bitwise_equals_general_path(orc, sim, gc, storage):
+    import torch
+
+    _say(f"[fast_vs_general] {storage}")
+    wl = _workload(19, storage, "mixed", two=True)
+    res = []
+    for general in (False, True):
+        f = sim.Field(wl)
+        f.set_option(1, 1 if general else 0)
+        gc.load_random_state(f, 9)
+        for t in range(4):
+            f.step(t)
+        torch.cuda.synchronize()
+        res.append(f.pdf_view().clone())
+    assert torch.equal(res[0], res[1])
+
+
+def test_xcd_remap_bitwise_identical(sim, gc):
+    import torch
+
+    wl = _workload(19, "f32", "channel")
+    res = []
+    for remap in (0, 1):
+        f = sim.Field(wl)
+        f.set_option(2, remap)
+        gc.load_random_state(f, 3)
+        for t in range(2):
+            f.step(t)
+        ft = f.force_torque().clone()
+        torch.cuda.synchronize()
+        res.append((f.pdf_view().clone(), ft))
+    assert torch.equal(res[0][0], res[1][0]) and torch.equal(res[0][1], res[1][1])
+
+
+@pytest.mark.parametrize("s", [0, 1, 2, 3])
+def test_mapping_bit_exact(orc, sim, gc, s):
+    """B(t) of rotating analytic and mesh bodies, two slots, random poses."""
+    import torch
+
+    _say(f"[mapping] s={s}")
+    rotor = pi.rotor_mesh(pi.RotorSpec(n_blades=3, radius=7.0, hub_radius=1.75, hub_length=3.0, chord_root=2.1,
+                                       chord_tip=1.05, n_chord=8, n_span=6, n_hub=16, seed=7))
+    bodies = [pi.Body(pi.Shape("mesh", (), rotor), pi.Motion(axis=(1, 0, 0), theta0=0.2, omega=0.37,
+                                                              x0=(16.0, 15.0, 14.0)), s=s),
+              pi.Body(pi.Shape("cube", (3.0,)), pi.Motion(axis=(0.48, 0.6, 0.64), theta0=1.0, omega=-0.3,
+                                                          x0=(22.5, 13.0, 15.5), v=(0.3, -0.1, 0.2)), s=s),
+              pi.Body(pi.Shape("ellipsoid", (4.0, 3.0, 2.0)), pi.Motion(axis=(0, 1, 0), omega=0.7,
+                                                                       x0=(8.0, 20.0, 9.0)), s=max(0, s - 1))]
+    wl = pi.Workload("map", 33, 30, 28, 19, "f32", 0.8, 3 / 16, (0, 0, 0), ("periodic",) * 6, (0, 0, 0), 1, 0, 2, 3,
+                     bodies)
+    f = sim.Field(wl, max_bodies=3)
+    run = orc.Run(wl)
+    for t in (0, 1, 2, 5):
+        f.map(t)
+        torch.cuda.synchronize()
+        Bg = gc.gpu_B_per_body(f, 3)
+        run.map(t)
+        diff = (Bg != run.B).sum()
+        _say(f"  t={t}: sum B = {Bg.sum(axis=1)}, mismatches {diff}")
+        assert diff == 0
+        assert f.error_flags().cpu().numpy()[0] == 0
+
+
+def test_three_bodies_in_two_slots_flags_error(sim):
+    import torch
+
+    bodies = [pi.Body(pi.Shape("ellipsoid", (4.0, 4.0, 4.0)), pi.Motion(x0=(10.0 + d, 10.0, 10.0)), s=1)
+              for d in (0.0, 1.0, 2.0)]
+    wl = pi.Workload("three", 24, 20, 20, 19, "f32", 0.8, 3 / 16, (0, 0, 0), ("periodic",) * 6, (0, 0, 0), 1, 0, 2, 1,
+                     bodies)
+    f = sim.Field(wl, max_bodies=3)
+    f.map(0)
+    torch.cuda.synchronize()
+    assert f.error_flags().cpu().numpy()[0] & 1
+    wl2 = pi.Workload("two", 24, 20, 20, 19, "f32", 0.8, 3 / 16, (0, 0, 0), ("periodic",) * 6, (0, 0, 0), 1, 0, 2, 1,
+                      bodies[:2])
+    f2 = sim.Field(wl2)
+    f2.map(0)
+    torch.cuda.synchronize()
+    assert f2.error_flags().cpu().numpy()[0] == 0
+
+
+def test_sphere32_periodic_fp64_trajectory(orc, sim, gc):
+    """32^3 periodic box, static sphere r=6 (s=2), force 1e-6 along x, FP64,
+    200 steps: drag series, velocity field and exact mass conservation."""
+    import torch
+
+    _say("[sphere32] 200 steps")
+    wl = pi.workload_sphere32()
+    f = sim.Field(wl, remap_every_step=False)
+    run = orc.Run(wl)
+    m0 = f.mass(0).item()
+    drag_g = []
+    for t in range(wl.steps):
+        f.step(t)
+        drag_g.append(f.force_torque().cpu().numpy().copy())
+    torch.cuda.synchronize()
+    run.advance(wl.steps, remap=False)
+    drag_g = np.array(drag_g)[:, 0]
+    drag_o = np.array(run.ft)[:, 0]
+    rel = np.abs(drag_g[:, 0] - drag_o[:, 0]).max() / np.abs(drag_o[:, 0]).max()
+    _say(f"  drag rel err {rel:.2e}; final drag {drag_o[-1, 0]:.6e}")
+    assert rel < 1e-10
+    # symmetric body centred on a lattice corner, force along x: no torque, no lift
+    assert np.abs(drag_g[:, 3:]).max() < 1e-12 * np.abs(drag_o[:, 0]).max()
+    assert np.abs(drag_g[:, 1:3]).max() < 1e-12 * np.abs(drag_o[:, 0]).max()
+    m1 = f.mass(wl.steps).item()
+    assert abs(m1 - m0) / m0 < 1e-13 and abs(m0 - wl.n_cells) < 1e-9
+    rho_g, u_g = f.macroscopic(wl.steps)
+    rho_o, u_o = run.macro()
+    u_g = u_g.cpu().numpy()
+    relu = np.linalg.norm(u_g - u_o) / np.linalg.norm(u_o)
+    _say(f"  u rel L2 {relu:.2e}, mass drift {abs(m1 - m0) / m0:.2e}")
+    assert relu < 1e-10
+
+
+def test_ellipsoid_channel_fp32_trajectory(orc, sim, gc):
+    """Reduced copy of the rotating-ellipsoid channel (64^3, semi-axes 10,5,3
+    (integer-scaled), s=3, inlet 0.05, FP32 storage) for 200 steps against the
+    FP64 oracle: velocity rel. L2 <= 1e-5 and torque <= 1e-4 (the targets for
+    FP32 storage)."""
+    import torch
+
+    _say("[ellipsoid channel 64^3] 200 steps")
+    wl = pi.workload_ellipsoid_channel(n=64, storage="f32", steps=200, scale=0.25, s=3)
+    wl.bodies[0].motion.omega = 4e-3
+    f = sim.Field(wl)
+    run = orc.Run(wl)
+    ftg = []
+    for t in range(wl.steps):
+        f.step(t)
+        ftg.append(f.force_torque().cpu().numpy().copy())
+    torch.cuda.synchronize()
+    run.advance(wl.steps)
+    rho_g, u_g = f.macroscopic(wl.steps)
+    rho_o, u_o = run.macro()
+    relu = np.linalg.norm(u_g.cpu().numpy() - u_o) / np.linalg.norm(u_o)
+    ftg = np.array(ftg)[:, 0]
+    fto = np.array(run.ft)[:, 0]
+    Tz_g, Tz_o = ftg[:, 5], fto[:, 5]
+    relT = np.abs(Tz_g - Tz_o).max() / np.abs(Tz_o).max()
+    relJ = abs(Tz_g[-50:].mean() - Tz_o[-50:].mean()) / abs(Tz_o[-50:].mean())
+    _say(f"  u rel L2 {relu:.2e}; torque series rel {relT:.2e}; window mean rel {relJ:.2e}")
+    assert relu < 1e-5
+    assert relT < 1e-4 and relJ < 1e-4

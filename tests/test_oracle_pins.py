@@ -436,3 +436,26 @@ def test_fraction_volume_rotating_cube(orc):
         assert np.all(np.abs(vals - N ** 3) < bound)
         rms.append(np.sqrt(np.mean((vals - N ** 3) ** 2)) / N ** 3)
     assert rms[0] > rms[1] > rms[2] > rms[3]
+
+
+@pytest.mark.parametrize("bc", [("periodic",) * 6, ("inlet", "outlet", "wall", "wall", "wall", "wall"),
+                                ("wall", "wall", "periodic", "periodic", "inlet", "outlet")])
+def test_sampled_update_equals_full_step(orc, bc):
+    """The one-cell update (used for sampled checks on full-size grids) gives
+    the same two steps as the full-domain step on every cell of a small grid."""
+    wl = pi.Workload("t", 9, 7, 6, 19, "f64", 0.8, 3 / 16, (1e-4, 0, 0), bc, (0.03, 0.0, 0.01), 1, 0, 1, 2,
+                     [pi.Body(pi.Shape("ellipsoid", (2.0, 1.5, 1.0)),
+                              pi.Motion(axis=(0, 0, 1), omega=0.2, x0=(4.0, 3.0, 3.0)), s=1)])
+    c, w, _ = orc.lattice(19)
+    f0 = w[:, None] + pi.pdf_deviation_full(11, 19, wl.n_cells) * 10
+    run = orc.Run(wl, f0=f0.copy()).advance(2)
+    geoms = [orc.OracleGeometry(b.shape, b.s) for b in wl.bodies]
+
+    def f_at(xyz):
+        n = xyz[:, 0] + wl.nx * (xyz[:, 1] + wl.ny * xyz[:, 2])
+        return f0[:, n].T
+
+    cells = np.array([(x, y, z) for z in range(6) for y in range(7) for x in range(9)])[::5]
+    got = orc.sampled_steps(wl, cells, f_at, geoms, 2)
+    n = cells[:, 0] + 9 * (cells[:, 1] + 7 * cells[:, 2])
+    assert np.allclose(got, run.f[:, n].T, atol=1e-15, rtol=0)
