@@ -106,13 +106,18 @@ __global__ __launch_bounds__(256) void k_map(const MapArgs a) {
           lo[c] = (P[c] - g.dabs[c]) >> (32 + s);
           hi[c] = (P[c] + g.dabs[c]) >> (32 + s);
         }
-        int st = -1;
-        for (long long bz = lo[2]; bz <= hi[2] && st != 2; ++bz)
-          for (long long by = lo[1]; by <= hi[1] && st != 2; ++by)
-            for (long long bx = lo[0]; bx <= hi[0] && st != 2; ++bx) {
-              const int v = coarse_state(g, bx, by, bz);
-              st = (st < 0) ? v : (st == v ? st : 2);
-            }
+        // the sub-samples span at most 3 coarse blocks per axis: issue all
+        // (up to 27) byte loads, then combine
+        int vals[27];
+#pragma unroll
+        for (int j = 0; j < 27; ++j) {
+          const long long bx = lo[0] + j % 3, by = lo[1] + (j / 3) % 3, bz = lo[2] + j / 9;
+          vals[j] = (bx <= hi[0] && by <= hi[1] && bz <= hi[2]) ? coarse_state(g, bx, by, bz) : -1;
+        }
+        int st = vals[0];
+#pragma unroll
+        for (int j = 1; j < 27; ++j)
+          if (vals[j] >= 0) st = (st == vals[j]) ? st : 2;
         state = st;
       }
     }
@@ -136,15 +141,20 @@ __global__ __launch_bounds__(256) void k_map(const MapArgs a) {
       }
     } else {
       unsigned long long mask = __ballot(state == 2);
+      const int nit = ns >> 6;  // 1 (s = 2) or 8 (s = 3) sub-samples per lane
       while (mask) {
         const int l = __ffsll((long long)mask) - 1;
         mask &= mask - 1;
         const long long Px = __shfl(P[0], l), Py = __shfl(P[1], l), Pz = __shfl(P[2], l);
-        int c = 0;
-        for (int k0 = 0; k0 < ns; k0 += 64) {
-          const int k = k0 + lane;
-          int in = 0;
-          if (k < ns) {
+        // all of this lane's word loads first, then the ballots
+        uint32_t word[8];
+        int bit[8];
+#pragma unroll
+        for (int it = 0; it < 8; ++it) {
+          word[it] = 0;
+          bit[it] = 0;
+          if (it < nit) {
+            const int k = it * 64 + lane;
             long long D[3];
             if (own_tab) {
               D[0] = tab[0][k];
@@ -153,10 +163,20 @@ __global__ __launch_bounds__(256) void k_map(const MapArgs a) {
             } else {
               sub_offset(g, k, D);
             }
-            in = geo_bit(g, (Px + D[0]) >> 32, (Py + D[1]) >> 32, (Pz + D[2]) >> 32);
+            const long long jx = ((Px + D[0]) >> 32) - g.mmin[0], jy = ((Py + D[1]) >> 32) - g.mmin[1],
+                            jz = ((Pz + D[2]) >> 32) - g.mmin[2];
+            if ((unsigned long long)jx < (unsigned long long)g.dims[0] &&
+                (unsigned long long)jy < (unsigned long long)g.dims[1] &&
+                (unsigned long long)jz < (unsigned long long)g.dims[2]) {
+              word[it] = g.bits[((size_t)jz * g.dims[1] + (size_t)jy) * g.wx + (size_t)(jx >> 5)];
+              bit[it] = (int)(jx & 31);
+            }
           }
-          c += __popcll(__ballot(in));
         }
+        int c = 0;
+#pragma unroll
+        for (int it = 0; it < 8; ++it)
+          if (it < nit) c += __popcll(__ballot((word[it] >> bit[it]) & 1u));
         if (lane == l) count = c;
       }
     }

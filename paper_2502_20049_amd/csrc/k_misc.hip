@@ -13,28 +13,15 @@ __device__ __forceinline__ double block_sum256(double v, double *sh) {
   return ((sh[0] + sh[1]) + sh[2]) + sh[3];
 }
 
-struct TileBoxes {
-  int v[PSM_MAX_BODIES * 6];  // lo x,y,z, hi x,y,z in tile coordinates
-};
-
-// One workgroup per body: tiles of the body's swept box in increasing tile
-// index, thread t takes every 256th tile, then a fixed tree.
-__global__ __launch_bounds__(256) void k_ft_reduce(const double *ftp, int max_bodies, int ntx, int nty,
-                                                   const TileBoxes tb, double *ft) {
+// One workgroup per body: the solid-kernel partials of the last step in
+// increasing workgroup order (thread t takes every 256th), then a fixed tree.
+__global__ __launch_bounds__(256) void k_ft_reduce(const double *ftp, int max_bodies, int nblocks, double *ft) {
   const int b = blockIdx.x;
-  const int *bx = tb.v + 6 * b;
-  const int lx = bx[0], ly = bx[1], lz = bx[2], hx = bx[3], hy = bx[4], hz = bx[5];
   double acc[6] = {0, 0, 0, 0, 0, 0};
-  if (hx >= lx && hy >= ly && hz >= lz) {
-    const long long ex = hx - lx + 1, ey = hy - ly + 1, ez = hz - lz + 1;
-    const long long total = ex * ey * ez;
-    for (long long i = threadIdx.x; i < total; i += 256) {
-      const long long tx = lx + i % ex, ty = ly + (i / ex) % ey, tz = lz + i / (ex * ey);
-      const size_t tile = (size_t)((tz * nty + ty) * ntx + tx);
-      const double *p = ftp + (tile * max_bodies + b) * 6;
+  for (int i = threadIdx.x; i < nblocks; i += 256) {
+    const double *p = ftp + ((size_t)i * max_bodies + b) * 6;
 #pragma unroll
-      for (int c = 0; c < 6; ++c) acc[c] += p[c];
-    }
+    for (int c = 0; c < 6; ++c) acc[c] += p[c];
   }
   __shared__ double sh[4];
   for (int c = 0; c < 6; ++c) {
@@ -45,19 +32,8 @@ __global__ __launch_bounds__(256) void k_ft_reduce(const double *ftp, int max_bo
 
 hipError_t launch_ft_reduce(const psm_field &f, int nb, double *ft, hipStream_t st) {
   if (nb <= 0) return hipSuccess;
-  TileBoxes tb;
-  for (int b = 0; b < nb; ++b) {
-    const IBox &B = f.active[b];
-    const bool empty = B.hi[0] < B.lo[0] || B.hi[1] < B.lo[1] || B.hi[2] < B.lo[2];
-    tb.v[6 * b + 0] = empty ? 1 : B.lo[0] / f.TX;
-    tb.v[6 * b + 1] = empty ? 1 : B.lo[1] / f.TY;
-    tb.v[6 * b + 2] = empty ? 1 : B.lo[2];
-    tb.v[6 * b + 3] = empty ? 0 : B.hi[0] / f.TX;
-    tb.v[6 * b + 4] = empty ? 0 : B.hi[1] / f.TY;
-    tb.v[6 * b + 5] = empty ? 0 : B.hi[2];
-  }
-  hipLaunchKernelGGL(k_ft_reduce, dim3(nb), dim3(256), 0, st, (const double *)f.ftp, f.cfg.max_bodies, f.ntx,
-                     f.nty, tb, ft);
+  hipLaunchKernelGGL(k_ft_reduce, dim3(nb), dim3(256), 0, st, (const double *)f.ftp, f.cfg.max_bodies,
+                     f.solid_blocks, ft);
   return hipGetLastError();
 }
 
@@ -134,7 +110,6 @@ __global__ __launch_bounds__(256) void k_sum_final(const double *p, uint32_t n, 
 
 uint32_t macro_blocks(const psm_field &f) { return (uint32_t)((f.N + 255) / 256); }
 
-SCArgs make_sc_args(const psm_field &f);  // defined in the C-ABI translation unit
 
 hipError_t launch_macro(const psm_field &f, int parity, double *rho, double *u, double *mass_partials,
                         int want_field, hipStream_t st) {

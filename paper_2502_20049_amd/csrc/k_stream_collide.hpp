@@ -82,7 +82,11 @@ __device__ __forceinline__ void collide(R (&f)[Q], const SCArgs &a, R B0, const 
     if constexpr (cz<Q>(k) < 0) jz -= f[k];
   });
   const R rho = R(1) + dr;
-  const R inv = R(1) / rho;
+  R inv;
+  if constexpr (std::is_same<R, float>::value)
+    inv = __builtin_amdgcn_rcpf(rho);  // 1 ulp; FP32 arithmetic budget
+  else
+    inv = R(1) / rho;
   const bool hf = a.has_force != 0;
   const R Fx = (R)a.force[0], Fy = (R)a.force[1], Fz = (R)a.force[2];
   R ux, uy, uz;
@@ -204,195 +208,372 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-template <int Q, typename T, int PAR, int SC, bool PSM, bool BIG>
-__global__ __launch_bounds__(256) void k_stream_collide(const SCArgs a) {
-  using R = typename Comp<T>::type;
-  using Off = typename std::conditional<BIG, uint64_t, uint32_t>::type;
-  constexpr Off S = sizeof(T);
-  constexpr int H = Lat<Q>::H;
-  (void)H;
+template <int Q, typename R>
+__device__ __forceinline__ R inlet_term(const SCArgs &a, int k) {
+  return R(6.0 * wt<Q>(k)) *
+         (R(cx<Q>(k)) * (R)a.u_in_d[0] + R(cy<Q>(k)) * (R)a.u_in_d[1] + R(cz<Q>(k)) * (R)a.u_in_d[2]);
+}
 
-  const uint32_t tile = a.xcd_remap ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x;
-  const int tid = threadIdx.x;
-  const int txi = (int)(tile % (uint32_t)a.ntx);
-  const uint32_t rr = tile / (uint32_t)a.ntx;
-  const int tyi = (int)(rr % (uint32_t)a.nty);
-  const int z = (int)(rr / (uint32_t)a.nty);
-  const int x = txi * a.TX + (tid & (a.TX - 1));
-  const int y = tyi * a.TY + (tid >> a.lTX);
-  const int nx = a.nx, ny = a.ny, nz = a.nz;
-  const bool active = (x < nx) && (y < ny);
-  const Off n = (Off)x + (Off)nx * ((Off)y + (Off)ny * (Off)z);
-  char *const A = a.pdf;
+__device__ __forceinline__ bool box_has(const IBox &b, int x, int y, int z) {
+  return x >= b.lo[0] && x <= b.hi[0] && y >= b.lo[1] && y <= b.hi[1] && z >= b.lo[2] && z <= b.hi[2];
+}
 
-  // face classification of every incoming direction (source x - c_k)
-  uint32_t bcm = 0, outm = 0, inm = 0;
+// Face kinds of every incoming direction of cell (x,y,z) (source x - c_k):
+// bit k of bcm set when the source is outside a non-periodic face; outm / inm
+// mark the outlet / inlet kinds (after the wall > inlet > outlet precedence).
+template <int Q>
+__device__ __forceinline__ void classify(const SCArgs &a, int x, int y, int z, uint32_t &bcm, uint32_t &outm,
+                                         uint32_t &inm) {
+  bcm = outm = inm = 0;
   sfor<Q>([&](auto K) {
     constexpr int k = K;
     constexpr int ex = cx<Q>(k), ey = cy<Q>(k), ez = cz<Q>(k);
     int kd = K_NONE;
     if constexpr (ex == 1) if (x == 0 && !a.periodic[0]) kd = face_merge(kd, a.bc[0]);
-    if constexpr (ex == -1) if (x == nx - 1 && !a.periodic[0]) kd = face_merge(kd, a.bc[1]);
+    if constexpr (ex == -1) if (x == a.nx - 1 && !a.periodic[0]) kd = face_merge(kd, a.bc[1]);
     if constexpr (ey == 1) if (y == 0 && !a.periodic[1]) kd = face_merge(kd, a.bc[2]);
-    if constexpr (ey == -1) if (y == ny - 1 && !a.periodic[1]) kd = face_merge(kd, a.bc[3]);
+    if constexpr (ey == -1) if (y == a.ny - 1 && !a.periodic[1]) kd = face_merge(kd, a.bc[3]);
     if constexpr (ez == 1) if (z == 0 && !a.periodic[2]) kd = face_merge(kd, a.bc[4]);
-    if constexpr (ez == -1) if (z == nz - 1 && !a.periodic[2]) kd = face_merge(kd, a.bc[5]);
+    if constexpr (ez == -1) if (z == a.nz - 1 && !a.periodic[2]) kd = face_merge(kd, a.bc[5]);
     if (kd != K_NONE) bcm |= 1u << k;
     if (kd == K_OUTLET) outm |= 1u << k;
     if (kd == K_INLET) inm |= 1u << k;
   });
+}
 
-  // odd-parity source offsets: interior rows need only the x wrap
-  const bool general = a.force_general || y == 0 || y == ny - 1 || z == 0 || z == nz - 1;
-  const Off rb = n - (Off)x;
-  int xm, xp;
-  if (a.periodic[0]) {
-    xm = x == 0 ? nx - 1 : x - 1;
-    xp = x == nx - 1 ? 0 : x + 1;
-  } else {
-    xm = x == 0 ? 0 : x - 1;
-    xp = x == nx - 1 ? nx - 1 : x + 1;
+// Slot of direction k for cell (x,y,z) with full face handling (face cells,
+// solid cells): own slot at even parity or for a face direction, else the
+// slot (x - c_k, kbar) with periodic wrap.
+template <int Q, typename T, int PAR>
+__device__ __forceinline__ char *slot_general(const SCArgs &a, int k, int x, int y, int z, uint64_t n,
+                                              uint32_t bcm) {
+  const size_t NS = (size_t)a.N * sizeof(T);
+  if (PAR == 0 || ((bcm >> k) & 1u)) return a.pdf + (size_t)k * NS + (size_t)n * sizeof(T);
+  int sx = x - cx<Q>(k), sy = y - cy<Q>(k), sz = z - cz<Q>(k);
+  if (sx < 0) sx += a.nx;
+  if (sx >= a.nx) sx -= a.nx;
+  if (sy < 0) sy += a.ny;
+  if (sy >= a.ny) sy -= a.ny;
+  if (sz < 0) sz += a.nz;
+  if (sz >= a.nz) sz -= a.nz;
+  const uint64_t src = (uint64_t)sx + (uint64_t)a.nx * ((uint64_t)sy + (uint64_t)a.ny * (uint64_t)sz);
+  return a.pdf + (size_t)opp<Q>(k) * NS + (size_t)src * sizeof(T);
+}
+
+// Does the tile / cell need the solid-fraction read?  B can only be nonzero
+// inside the bodies' current boxes (the mapping keeps it so).
+__device__ __forceinline__ bool boxes_touch(const SCArgs &a, int x0, int x1, int y0, int y1, int z0, int z1) {
+  for (int b = 0; b < a.nbox; ++b) {
+    const IBox &B = a.box[b];
+    if (x1 >= B.lo[0] && x0 <= B.hi[0] && y1 >= B.lo[1] && y0 <= B.hi[1] && z1 >= B.lo[2] && z0 <= B.hi[2])
+      return true;
   }
-  auto src_of = [&](auto K) -> Off {
-    constexpr int k = K;
-    constexpr int ex = cx<Q>(k), ey = cy<Q>(k), ez = cz<Q>(k);
-    const Off xs = (Off)(ex == 1 ? xm : (ex == -1 ? xp : x));
-    if (!general) {
-      return rb + xs - (Off)((long long)ey * nx) - (Off)((long long)ez * nx * ny);
+  return false;
+}
+
+// ---------------------------------------------------------------------------
+// Fluid cells of interior rows (1 <= y <= ny-2, 1 <= z <= nz-2).  Each
+// direction is one uniform 64-bit base plus a 32-bit lane offset chosen from
+// three (x-1, x, x+1, wrapped when x is periodic).  With a non-periodic x the
+// first and last cell of a row take the face rule for the five directions
+// whose source lies outside, in a divergent fix-up that only the two edge
+// waves of a row execute.  With PSM, cells whose B is nonzero are left to
+// the solid kernel.
+// ---------------------------------------------------------------------------
+template <int Q, typename T, int PAR, bool PSM, bool BIG>
+__global__ __launch_bounds__(256) void k_fluid(const SCArgs a) {
+  using R = typename Comp<T>::type;
+  using Off = typename std::conditional<BIG, uint64_t, uint32_t>::type;
+  constexpr Off S = sizeof(T);
+  const uint32_t tile = a.xcd_remap ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x;
+  const int tid = threadIdx.x;
+  const int txi = (int)(tile % (uint32_t)a.ntx);
+  const uint32_t rr = tile / (uint32_t)a.ntx;
+  const int tyi = (int)(rr % (uint32_t)a.nty_i);
+  const int z = 1 + (int)(rr / (uint32_t)a.nty_i);
+  const int x = txi * a.TX + (tid & (a.TX - 1));
+  const int y = 1 + tyi * a.TY + (tid >> a.lTX);
+  const int nx = a.nx, ny = a.ny;
+  bool active = (x < nx) && (y <= ny - 2);
+  const Off nxy = (Off)nx * (Off)ny;
+  const Off n = (Off)x + (Off)nx * (Off)y + nxy * (Off)z;
+  if constexpr (PSM) {
+    const int x0 = txi * a.TX, y0 = 1 + tyi * a.TY;
+    if (boxes_touch(a, x0, x0 + a.TX - 1, y0, y0 + a.TY - 1, z, z)) {
+      if (active && a.B0[n] != 0.0f) active = false;
     }
-    int sy = y - ey, sz = z - ez;
-    if (sy < 0) sy += ny;
-    if (sy >= ny) sy -= ny;
-    if (sz < 0) sz += nz;
-    if (sz >= nz) sz -= nz;
-    return xs + (Off)nx * ((Off)sy + (Off)ny * (Off)sz);
-  };
-  // direction base (uniform, 64-bit) + in-direction byte offset (32-bit unless
-  // a direction array exceeds 4 GiB)
+  }
+  if (!active) return;
+  const bool xper = a.periodic[0] != 0;
+  const bool lo_face = !xper && x == 0;        // sources x-1 are outside (face -x)
+  const bool hi_face = !xper && x == nx - 1;   // sources x+1 are outside (face +x)
+  char *const A = a.pdf;
   const size_t NS = (size_t)a.N * S;
+  const Off rb = n - (Off)x;
+  int xm = x - 1, xp = x + 1;
+  if (xm < 0) xm = xper ? xm + nx : 0;
+  if (xp >= nx) xp = xper ? xp - nx : nx - 1;
+  const Off o0 = n * S, om = (rb + (Off)xm) * S, op = (rb + (Off)xp) * S;
   auto addr = [&](auto K) -> char * {
     constexpr int k = K;
     if constexpr (PAR == 0) {
-      return A + (size_t)k * NS + (size_t)(Off)(n * S);
+      return A + (size_t)k * NS + (size_t)o0;
     } else {
-      if ((bcm >> k) & 1u) return A + (size_t)k * NS + (size_t)(Off)(n * S);
-      return A + (size_t)opp<Q>(k) * NS + (size_t)(Off)(src_of(K) * S);
+      constexpr int ex = cx<Q>(k), ey = cy<Q>(k), ez = cz<Q>(k);
+      const long long rowoff = (long long)ey * nx + (long long)ez * (long long)nxy;
+      char *base = A + (size_t)opp<Q>(k) * NS - rowoff * (long long)S;
+      const Off lo = ex == 1 ? om : (ex == -1 ? op : o0);
+      return base + (size_t)lo;
     }
   };
-  auto inlet_term = [&](auto K) -> R {
-    constexpr int k = K;
-    return R(6.0 * wt<Q>(k)) *
-           (R(cx<Q>(k)) * (R)a.u_in_d[0] + R(cy<Q>(k)) * (R)a.u_in_d[1] + R(cz<Q>(k)) * (R)a.u_in_d[2]);
-  };
-
+  auto own = [&](auto K) -> char * { return A + (size_t)(int)K * NS + (size_t)o0; };
   R f[Q];
-  if (active) {
+  sfor<Q>([&](auto K) { f[K] = ldv<T, R>(addr(K)); });
+  const bool xface = lo_face || hi_face;
+  int kind_lo = K_NONE, kind_hi = K_NONE;
+  if (xface) {
+    kind_lo = lo_face ? a.bc[0] : K_NONE;
+    kind_hi = hi_face ? a.bc[1] : K_NONE;
+    if constexpr (PAR == 1) {
+      // odd parity: incoming directions from outside read the cell's own slot
+      sfor<Q>([&](auto K) {
+        constexpr int k = K;
+        constexpr int ex = cx<Q>(k);
+        const int kd = ex == 1 ? kind_lo : (ex == -1 ? kind_hi : K_NONE);
+        if (kd != K_NONE) {
+          R v = ldv<T, R>(own(K));
+          if (kd == K_INLET) v += inlet_term<Q, R>(a, k);
+          f[k] = v;
+        }
+      });
+    }
+  }
+  R z3[3] = {0, 0, 0}, m0[3] = {0, 0, 0}, m1[3] = {0, 0, 0};
+  collide<Q, 1, 0, R>(f, a, R(0), z3, R(0), z3, m0, m1);
+  if (!xface) {
+    sfor<Q>([&](auto K) { stv<T, R>(addr(K), f[opp<Q>(K)]); });
+  } else {
     sfor<Q>([&](auto K) {
       constexpr int k = K;
-      R v = ldv<T, R>(addr(K));
-      if constexpr (PAR == 1) {
-        if ((inm >> k) & 1u) v += inlet_term(K);
+      constexpr int ex = cx<Q>(k);
+      const int kd = ex == 1 ? kind_lo : (ex == -1 ? kind_hi : K_NONE);
+      if (kd == K_NONE) {
+        stv<T, R>(addr(K), f[opp<Q>(k)]);
+      } else {
+        R v = kd == K_OUTLET ? f[k] : f[opp<Q>(k)];
+        if constexpr (PAR == 1) {
+          if (kd == K_INLET) v += inlet_term<Q, R>(a, k);
+        }
+        stv<T, R>(own(K), v);
       }
-      f[k] = v;
     });
-  } else {
-    sfor<Q>([&](auto K) { f[K] = R(0); });
   }
+}
 
-  // body slots of this cell
-  R B0 = 0, B1 = 0;
-  int b0 = 0, b1 = 0;
-  bool two = false;
+// ---------------------------------------------------------------------------
+// Fluid cells on the rows with y or z on a domain face (coalesced along x).
+// Full face handling.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void face_row_yz(const SCArgs &a, int r, int &y, int &z) {
+  // planes z = 0 (and z = nz-1), then rows y = 0 (and y = ny-1) of the others
+  const int ny = a.ny, nz = a.nz;
+  const int nzp = nz >= 2 ? 2 : 1;
+  if (r < nzp * ny) {
+    z = (r < ny) ? 0 : nz - 1;
+    y = r % ny;
+    return;
+  }
+  const int r2 = r - nzp * ny;
+  const int nyp = ny >= 2 ? 2 : 1;
+  z = 1 + r2 / nyp;
+  y = (r2 % nyp) ? ny - 1 : 0;
+}
+
+template <int Q, typename T, int PAR, bool PSM>
+__global__ __launch_bounds__(256) void k_fluid_face(const SCArgs a) {
+  using R = typename Comp<T>::type;
+  const uint64_t i = (uint64_t)blockIdx.x * 256u + threadIdx.x;
+  if (i >= a.nface) return;
+  int x, y, z;
+  const uint64_t nrc = (uint64_t)a.nfrows * (uint64_t)a.nx;
+  if (a.face_all) {
+    x = (int)(i % (uint64_t)a.nx);
+    y = (int)((i / (uint64_t)a.nx) % (uint64_t)a.ny);
+    z = (int)(i / ((uint64_t)a.nx * (uint64_t)a.ny));
+  } else {
+    (void)nrc;
+    face_row_yz(a, (int)(i / (uint64_t)a.nx), y, z);
+    x = (int)(i % (uint64_t)a.nx);
+  }
+  const uint64_t n = (uint64_t)x + (uint64_t)a.nx * ((uint64_t)y + (uint64_t)a.ny * (uint64_t)z);
   if constexpr (PSM) {
-    if (active) {
+    if (boxes_touch(a, x, x, y, y, z, z) && a.B0[n] != 0.0f) return;
+  }
+  uint32_t bcm, outm, inm;
+  classify<Q>(a, x, y, z, bcm, outm, inm);
+  R f[Q];
+  sfor<Q>([&](auto K) {
+    constexpr int k = K;
+    R v = ldv<T, R>(slot_general<Q, T, PAR>(a, k, x, y, z, n, bcm));
+    if constexpr (PAR == 1) {
+      if ((inm >> k) & 1u) v += inlet_term<Q, R>(a, k);
+    }
+    f[k] = v;
+  });
+  R z3[3] = {0, 0, 0}, m0[3] = {0, 0, 0}, m1[3] = {0, 0, 0};
+  collide<Q, 1, 0, R>(f, a, R(0), z3, R(0), z3, m0, m1);
+  sfor<Q>([&](auto K) {
+    constexpr int k = K;
+    R v = ((outm >> k) & 1u) ? f[k] : f[opp<Q>(k)];
+    if constexpr (PAR == 1) {
+      if ((inm >> k) & 1u) v += inlet_term<Q, R>(a, k);
+    }
+    stv<T, R>(slot_general<Q, T, PAR>(a, k, x, y, z, n, bcm), v);
+  });
+}
+
+// ---------------------------------------------------------------------------
+// Cells with a nonzero solid fraction (inside the bodies' current boxes):
+// the PSM blend of eq. (4) with SC1/2/3 over up to two body slots, full face
+// handling, and the force / torque of eqs. (10)-(11) on each body.  A fixed
+// grid of workgroups walks the boxes' 256-cell chunks in a fixed order and
+// keeps per-body FP64 sums in LDS (deterministic), written once per
+// workgroup.  A cell inside several boxes is taken by the lowest-index box.
+// ---------------------------------------------------------------------------
+template <int Q, typename T, int PAR, int SC>
+__global__ __launch_bounds__(256) void k_solid(const SCArgs a) {
+  using R = typename Comp<T>::type;
+  __shared__ double acc[PSM_MAX_BODIES][6];
+  __shared__ double wred[4][6];
+  const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
+  if (tid < PSM_MAX_BODIES * 6) acc[tid / 6][tid % 6] = 0.0;
+  __syncthreads();
+  for (uint32_t ch = blockIdx.x; ch < a.nchunks; ch += gridDim.x) {
+    int rb = 0;
+    while (rb + 1 < a.nbox && ch >= a.cprefix[rb + 1]) ++rb;
+    const IBox &G = a.box[rb];
+    const uint64_t idx = (uint64_t)(ch - a.cprefix[rb]) * 256u + tid;
+    const int ex_ = G.hi[0] - G.lo[0] + 1, ey_ = G.hi[1] - G.lo[1] + 1;
+    const uint64_t cells = (uint64_t)ex_ * (uint64_t)ey_ * (uint64_t)(G.hi[2] - G.lo[2] + 1);
+    const int x = G.lo[0] + (int)(idx % (uint64_t)ex_);
+    const int y = G.lo[1] + (int)((idx / (uint64_t)ex_) % (uint64_t)ey_);
+    const int z = G.lo[2] + (int)(idx / ((uint64_t)ex_ * (uint64_t)ey_));
+    bool act = idx < cells;
+    for (int b = 0; b < rb; ++b)
+      if (box_has(a.box[b], x, y, z)) act = false;
+    const uint64_t n = act ? (uint64_t)x + (uint64_t)a.nx * ((uint64_t)y + (uint64_t)a.ny * (uint64_t)z) : 0;
+    R B0 = 0, B1 = 0;
+    int b0 = 0, b1 = 0;
+    bool two = false;
+    if (act) {
       B0 = (R)a.B0[n];
-      if (B0 > R(0)) {
-        const uint8_t m = a.meta[n];
-        b0 = m & 15;
-        if (b0 >= a.nb) b0 = 0;  // ids come from the mapping; never index past the body table
-        if (a.slots == 2 && (m >> 4)) {
-          b1 = (m >> 4) - 1;
-          if (b1 >= a.nb) b1 = 0;
-          B1 = (R)a.B1[n];
-          two = true;
+      act = B0 != R(0);
+    }
+    if (act) {
+      const uint8_t m = a.meta[n];
+      b0 = m & 15;
+      if (b0 >= a.nb) b0 = 0;  // ids come from the mapping; never index past the body table
+      if (a.slots == 2 && (m >> 4)) {
+        b1 = (m >> 4) - 1;
+        if (b1 >= a.nb) b1 = 0;
+        B1 = (R)a.B1[n];
+        two = true;
+      }
+    }
+    R mom0[3] = {0, 0, 0}, mom1[3] = {0, 0, 0};
+    if (__syncthreads_or(act)) {
+      uint32_t bcm = 0, outm = 0, inm = 0;
+      R f[Q];
+      if (act) {
+        classify<Q>(a, x, y, z, bcm, outm, inm);
+        sfor<Q>([&](auto K) {
+          constexpr int k = K;
+          R v = ldv<T, R>(slot_general<Q, T, PAR>(a, k, x, y, z, n, bcm));
+          if constexpr (PAR == 1) {
+            if ((inm >> k) & 1u) v += inlet_term<Q, R>(a, k);
+          }
+          f[k] = v;
+        });
+      } else {
+        sfor<Q>([&](auto K) { f[K] = R(0); });
+      }
+      R us0[3] = {0, 0, 0}, us1[3] = {0, 0, 0};
+      const double xc = x + 0.5, yc = y + 0.5, zc = z + 0.5;
+      for (int b = 0; b < a.nb; ++b) {  // uniform loop: body data stays scalar
+        const BodyK &bd = a.body[b];
+        if (act && (b0 == b || (two && b1 == b))) {
+          const R rx = (R)(xc - bd.X[0]), ry = (R)(yc - bd.X[1]), rz = (R)(zc - bd.X[2]);
+          const R wx = (R)bd.W[0], wy = (R)bd.W[1], wz = (R)bd.W[2];
+          R u0 = (R)bd.V[0] + (wy * rz - wz * ry);
+          R u1 = (R)bd.V[1] + (wz * rx - wx * rz);
+          R u2 = (R)bd.V[2] + (wx * ry - wy * rx);
+          if (b0 == b) {
+            us0[0] = u0;
+            us0[1] = u1;
+            us0[2] = u2;
+          }
+          if (two && b1 == b) {
+            us1[0] = u0;
+            us1[1] = u1;
+            us1[2] = u2;
+          }
         }
       }
-    }
-  }
-  R us0[3] = {0, 0, 0}, us1[3] = {0, 0, 0};
-  R mom0[3] = {0, 0, 0}, mom1[3] = {0, 0, 0};
-  const double xc = x + 0.5, yc = y + 0.5, zc = z + 0.5;
-  bool solid_wave = false;
-  if constexpr (PSM) solid_wave = __any(B0 > R(0));
-  if (solid_wave) {
-    auto usolid = [&](int b, R(&us)[3]) {
-      const BodyK &bd = a.body[b];
-      const R rx = (R)(xc - bd.X[0]), ry = (R)(yc - bd.X[1]), rz = (R)(zc - bd.X[2]);
-      const R wx = (R)bd.W[0], wy = (R)bd.W[1], wz = (R)bd.W[2];
-      us[0] = (R)bd.V[0] + (wy * rz - wz * ry);
-      us[1] = (R)bd.V[1] + (wz * rx - wx * rz);
-      us[2] = (R)bd.V[2] + (wx * ry - wy * rx);
-    };
-    if (B0 > R(0)) usolid(b0, us0);
-    if (two) usolid(b1, us1);
-    if (__any(two)) {
-      collide<Q, SC, 2, R>(f, a, B0, us0, B1, us1, mom0, mom1);
-    } else {
-      collide<Q, SC, 1, R>(f, a, B0, us0, B1, us1, mom0, mom1);
-    }
-  } else {
-    collide<Q, SC, 0, R>(f, a, B0, us0, B1, us1, mom0, mom1);
-  }
-
-  if (active) {
-    sfor<Q>([&](auto K) {
-      constexpr int k = K;
-      R v = ((outm >> k) & 1u) ? f[k] : f[opp<Q>(k)];
-      if constexpr (PAR == 1) {
-        if ((inm >> k) & 1u) v += inlet_term(K);
+      if (__any(two)) {
+        collide<Q, SC, 2, R>(f, a, B0, us0, B1, us1, mom0, mom1);
+      } else {
+        collide<Q, SC, 1, R>(f, a, B0, us0, B1, us1, mom0, mom1);
       }
-      stv<T, R>(addr(K), v);
-    });
-  }
-
-  // force / torque partials of tiles inside a body's swept box (eqs. (10)-(11))
-  if constexpr (PSM) {
-    __shared__ double red[4][6];
-    const int wid = tid >> 6, lane = tid & 63;
-    for (int b = 0; b < a.nb; ++b) {
-      const BodyK &bd = a.body[b];
-      const bool inbox = txi >= bd.tlo[0] && txi <= bd.thi[0] && tyi >= bd.tlo[1] && tyi <= bd.thi[1] &&
-                         z >= bd.tlo[2] && z <= bd.thi[2];
-      if (!inbox) continue;  // uniform over the workgroup
-      double v[6] = {0, 0, 0, 0, 0, 0};
-      auto add = [&](const R(&m)[3]) {
-        const double dx = (double)m[0], dy = (double)m[1], dz = (double)m[2];
+      if (act) {
+        sfor<Q>([&](auto K) {
+          constexpr int k = K;
+          R v = ((outm >> k) & 1u) ? f[k] : f[opp<Q>(k)];
+          if constexpr (PAR == 1) {
+            if ((inm >> k) & 1u) v += inlet_term<Q, R>(a, k);
+          }
+          stv<T, R>(slot_general<Q, T, PAR>(a, k, x, y, z, n, bcm), v);
+        });
+      }
+      // force / torque on each body touched by this chunk
+      for (int b = 0; b < a.nb; ++b) {
+        const bool has = act && (b0 == b || (two && b1 == b));
+        if (!__syncthreads_or(has)) continue;
+        const BodyK &bd = a.body[b];
+        double v0 = 0, v1 = 0, v2 = 0;
+        if (act && b0 == b) {
+          v0 += (double)mom0[0];
+          v1 += (double)mom0[1];
+          v2 += (double)mom0[2];
+        }
+        if (act && two && b1 == b) {
+          v0 += (double)mom1[0];
+          v1 += (double)mom1[1];
+          v2 += (double)mom1[2];
+        }
         const double rx = xc - bd.X[0], ry = yc - bd.X[1], rz = zc - bd.X[2];
-        v[0] += dx;
-        v[1] += dy;
-        v[2] += dz;
-        v[3] += ry * dz - rz * dy;
-        v[4] += rz * dx - rx * dz;
-        v[5] += rx * dy - ry * dx;
-      };
-      if (B0 > R(0) && b0 == b) add(mom0);
-      if (two && b1 == b) add(mom1);
-      if (__any(B0 > R(0))) {
-#pragma unroll
-        for (int c = 0; c < 6; ++c) v[c] = wave_sum(v[c]);
+        double v3 = ry * v2 - rz * v1, v4 = rz * v0 - rx * v2, v5 = rx * v1 - ry * v0;
+        v0 = wave_sum(v0);
+        v1 = wave_sum(v1);
+        v2 = wave_sum(v2);
+        v3 = wave_sum(v3);
+        v4 = wave_sum(v4);
+        v5 = wave_sum(v5);
+        if (lane == 0) {
+          wred[wid][0] = v0;
+          wred[wid][1] = v1;
+          wred[wid][2] = v2;
+          wred[wid][3] = v3;
+          wred[wid][4] = v4;
+          wred[wid][5] = v5;
+        }
+        __syncthreads();
+        if (tid < 6) acc[b][tid] += ((wred[0][tid] + wred[1][tid]) + wred[2][tid]) + wred[3][tid];
+        __syncthreads();
       }
-      if (lane == 0) {
-#pragma unroll
-        for (int c = 0; c < 6; ++c) red[wid][c] = v[c];
-      }
-      __syncthreads();
-      if (tid < 6) {
-        const double s = ((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid];
-        a.ftp[((size_t)tile * a.max_bodies + b) * 6 + tid] = s;
-      }
-      __syncthreads();
     }
   }
+  __syncthreads();
+  if (tid < a.nb * 6) a.ftp[((size_t)blockIdx.x * a.max_bodies + tid / 6) * 6 + tid % 6] = acc[tid / 6][tid % 6];
 }
 
 }  // namespace psm

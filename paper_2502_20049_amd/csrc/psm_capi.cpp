@@ -20,9 +20,9 @@ int hip_fail(hipError_t e, const char *what) {
   return PSM_EHIP;
 }
 
-hipError_t launch_sc_f64(const psm_config &, const SCArgs &, int, bool, hipStream_t);
-hipError_t launch_sc_f32(const psm_config &, const SCArgs &, int, bool, hipStream_t);
-hipError_t launch_sc_f16(const psm_config &, const SCArgs &, int, bool, hipStream_t);
+hipError_t launch_sc_f64(const psm_config &, const SCArgs &, int, bool, hipStream_t, int *);
+hipError_t launch_sc_f32(const psm_config &, const SCArgs &, int, bool, hipStream_t, int *);
+hipError_t launch_sc_f16(const psm_config &, const SCArgs &, int, bool, hipStream_t, int *);
 
 static size_t storage_size(int st) { return st == PSM_F64 ? 8 : (st == PSM_F32 ? 4 : 2); }
 
@@ -57,7 +57,7 @@ static Layout layout_of(const psm_config &c) {
   L.ntiles = (int64_t)L.ntx * L.nty * c.nz;
   const int mb = c.psm ? std::max(1, c.max_bodies) : 0;
   L.off_ftp = 256;
-  L.off_red = L.off_ftp + (size_t)L.ntiles * mb * 6 * sizeof(double);
+  L.off_red = L.off_ftp + (size_t)SOLID_BLOCKS * mb * 6 * sizeof(double);
   L.red_count = (uint32_t)((L.N + 255) / 256);
   L.work_bytes = L.off_red + (size_t)L.red_count * sizeof(double) + 64;
   return L;
@@ -106,12 +106,17 @@ SCArgs make_sc_args(const psm_field &f) {
   a.TY = f.TY;
   a.lTX = f.lTX;
   a.ntx = f.ntx;
-  a.nty = f.nty;
-  a.ntiles = (uint32_t)f.ntiles;
+  const bool interior = c.ny >= 3 && c.nz >= 3;
+  a.nty_i = interior ? (c.ny - 2 + f.TY - 1) / f.TY : 0;
+  a.ntiles_i = interior ? (uint32_t)((int64_t)f.ntx * a.nty_i * (c.nz - 2)) : 0u;
+  const int nzp = c.nz >= 2 ? 2 : 1, nyp = c.ny >= 2 ? 2 : 1;
+  a.nfrows = nzp * c.ny + (c.nz > 2 ? (c.nz - 2) * nyp : 0);
+  a.nface = (uint64_t)a.nfrows * c.nx;
+  a.face_all = f.opt_general_path;
+  if (a.face_all) a.nface = (uint64_t)f.N;
   for (int i = 0; i < 6; ++i) a.bc[i] = c.bc[i];
   for (int d = 0; d < 3; ++d) {
     a.periodic[d] = c.bc[2 * d] == PSM_PERIODIC;
-    a.u_in[d] = (float)c.u_in[d];
     a.u_in_d[d] = c.u_in[d];
     a.force[d] = c.force[d];
   }
@@ -481,11 +486,30 @@ int geometry_map_step(psm_field *f, const psm_body *bodies, const psm_geom *cons
       const double sum = fabs(m.R[d]) + fabs(m.R[3 + d]) + fabs(m.R[6 + d]);
       m.dabs[d] = (long long)ceil(sum * (1.0 - ldexp(1.0, -g->s)) * 0.5 * ldexp(1.0, g->s + 32)) + 2;
     }
-    // swept box: cells whose centre lies within r_bound + 2 of X
+    // cells the body can touch at this pose: lab AABB of the rotated
+    // geometry box (a cell [i, i+1] meets [lo, hi] iff floor(lo) <= i < hi),
+    // one cell of margin
+    double blo[3], bhi[3];
+    {
+      const double h = ldexp(1.0, -g->s);
+      for (int d = 0; d < 3; ++d) {
+        blo[d] = 1e300;
+        bhi[d] = -1e300;
+      }
+      for (int c = 0; c < 8; ++c) {
+        double p[3];
+        for (int d = 0; d < 3; ++d) p[d] = (((c >> d) & 1) ? (double)(g->mmin[d] + g->dims[d]) : (double)g->mmin[d]) * h;
+        for (int d = 0; d < 3; ++d) {
+          const double v = m.R[3 * d] * p[0] + m.R[3 * d + 1] * p[1] + m.R[3 * d + 2] * p[2] + m.X[d];
+          blo[d] = std::min(blo[d], v);
+          bhi[d] = std::max(bhi[d], v);
+        }
+      }
+    }
     IBox A;
     bool empty = false;
     for (int d = 0; d < 3; ++d) {
-      const double lo = floor(m.X[d] - g->r_bound - 2.5), hi = ceil(m.X[d] + g->r_bound + 2.5);
+      const double lo = floor(blo[d]) - 1.0, hi = ceil(bhi[d]);
       A.lo[d] = (int)std::max(0.0, std::min((double)n3[d], lo));
       A.hi[d] = (int)std::min((double)n3[d] - 1, std::max(-1.0, hi));
       if (A.hi[d] < A.lo[d]) empty = true;
@@ -523,6 +547,7 @@ int psm_stream_collide(psm_field *f, const psm_body *bodies, int nb, int64_t ste
     return set_error("psm_stream_collide: bodies do not match the mapped field"), PSM_EINVAL;
   SCArgs a = make_sc_args(*f);
   a.nb = f->cfg.psm ? nb : 0;
+  uint32_t chunks = 0;
   for (int b = 0; b < a.nb; ++b) {
     BodyK &k = a.body[b];
     for (int d = 0; d < 3; ++d) {
@@ -530,32 +555,31 @@ int psm_stream_collide(psm_field *f, const psm_body *bodies, int nb, int64_t ste
       k.V[d] = bodies[b].V[d];
       k.W[d] = bodies[b].W[d];
     }
+    // B is zero outside the mapped boxes; the solid kernel walks them
     const IBox &B = f->active[b];
-    if (box_empty(B)) {
-      for (int d = 0; d < 3; ++d) {
-        k.tlo[d] = 1;
-        k.thi[d] = 0;
-      }
-    } else {
-      k.tlo[0] = B.lo[0] / f->TX;
-      k.thi[0] = B.hi[0] / f->TX;
-      k.tlo[1] = B.lo[1] / f->TY;
-      k.thi[1] = B.hi[1] / f->TY;
-      k.tlo[2] = B.lo[2];
-      k.thi[2] = B.hi[2];
+    a.box[b] = B;
+    a.cprefix[b] = chunks;
+    if (!box_empty(B)) {
+      const uint64_t cells = (uint64_t)(B.hi[0] - B.lo[0] + 1) * (uint64_t)(B.hi[1] - B.lo[1] + 1) *
+                             (uint64_t)(B.hi[2] - B.lo[2] + 1);
+      chunks += (uint32_t)((cells + 255) / 256);
     }
   }
-  a.force_general = f->opt_general_path;
+  a.nbox = a.nb;
+  a.cprefix[a.nb] = chunks;
+  a.nchunks = chunks;
   a.xcd_remap = f->opt_xcd_remap;
   const int parity = (int)(step & 1);
   const bool big = (uint64_t)f->N * storage_size(f->cfg.storage) > 0xFFFFFFFFull;
   hipError_t e;
+  int sb = 0;
   switch (f->cfg.storage) {
-    case PSM_F64: e = launch_sc_f64(f->cfg, a, parity, big, (hipStream_t)stream); break;
-    case PSM_F32: e = launch_sc_f32(f->cfg, a, parity, big, (hipStream_t)stream); break;
-    default: e = launch_sc_f16(f->cfg, a, parity, big, (hipStream_t)stream); break;
+    case PSM_F64: e = launch_sc_f64(f->cfg, a, parity, big, (hipStream_t)stream, &sb); break;
+    case PSM_F32: e = launch_sc_f32(f->cfg, a, parity, big, (hipStream_t)stream, &sb); break;
+    default: e = launch_sc_f16(f->cfg, a, parity, big, (hipStream_t)stream, &sb); break;
   }
   if (e != hipSuccess) return hip_fail(e, "psm_stream_collide launch");
+  f->solid_blocks = sb;
   return PSM_OK;
 }
 

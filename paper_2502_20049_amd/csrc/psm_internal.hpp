@@ -77,29 +77,34 @@ struct IBox {
   int hi[3];  // inclusive; empty when any hi < lo
 };
 
-// per-body data of the stream-collide kernel
+// per-body data of the stream-collide kernels
 struct BodyK {
   double X[3];
   double V[3];
   double W[3];
-  int tlo[3];  // tile box of the body's swept cells (force/torque partials)
-  int thi[3];
 };
+
+// workgroups of the solid-cell kernel (fixed: its per-body partial sums are
+// independent of the grid size)
+constexpr int SOLID_BLOCKS = 2048;
 
 struct SCArgs {
   char *pdf;
   const float *B0;
   const float *B1;
   const uint8_t *meta;
-  double *ftp;  // [tile][max_bodies][6]
+  double *ftp;  // [solid workgroup][max_bodies][6]
   int nx, ny, nz;
   uint32_t N;
-  int TX, TY, lTX;  // tile shape, log2(TX)
-  int ntx, nty;
-  uint32_t ntiles;
+  int TX, TY, lTX;  // tile shape of the interior kernel, log2(TX)
+  int ntx;
+  int nty_i;          // tile rows over the interior rows 1..ny-2
+  uint32_t ntiles_i;  // ntx * nty_i * (nz - 2)
+  int nfrows;         // rows with y or z on a face
+  uint64_t nface;     // cells of the face kernel
+  int face_all;       // PSM_OPT_GENERAL_PATH: the face kernel takes every cell
   int bc[6];
   int periodic[3];
-  float u_in[3];
   double u_in_d[3];
   double force[3];
   int has_force;
@@ -107,8 +112,11 @@ struct SCArgs {
   int nb;
   int max_bodies;
   int slots;
-  int force_general;  // PSM_OPT_GENERAL_PATH: general addressing for every row
-  int xcd_remap;      // PSM_OPT_XCD_REMAP: contiguous tile ranges per XCD
+  int xcd_remap;  // PSM_OPT_XCD_REMAP: contiguous tile ranges per XCD
+  int nbox;       // boxes outside which every B is zero (one per body)
+  IBox box[PSM_MAX_BODIES];
+  uint32_t cprefix[PSM_MAX_BODIES + 1];  // 256-cell chunk offsets of the boxes
+  uint32_t nchunks;
   BodyK body[PSM_MAX_BODIES];
 };
 
@@ -163,6 +171,7 @@ struct psm_field {
   int TX, TY, lTX, ntx, nty;
   int64_t ntiles;
   int nb_mapped;
+  int solid_blocks;  // workgroups of the last solid-cell launch (partials written)
   bool have_prev[PSM_MAX_BODIES];
   psm::IBox active[PSM_MAX_BODIES];
   int device;
@@ -188,9 +197,9 @@ void set_error(const std::string &msg);
 int hip_fail(hipError_t e, const char *what);
 
 // launchers (defined in the .hip translation units)
-hipError_t launch_stream_collide(const psm_config &cfg, const SCArgs &a, int parity, hipStream_t st);
 hipError_t launch_map(const MapArgs &a, uint32_t max_region_cells, int any_s_max, hipStream_t st);
 hipError_t launch_ft_reduce(const psm_field &f, int nb, double *ft, hipStream_t st);
+SCArgs make_sc_args(const psm_field &f);
 hipError_t launch_macro(const psm_field &f, int parity, double *rho, double *u, double *mass_partials,
                         int want_field, hipStream_t st);
 hipError_t launch_mass_final(const double *partials, uint32_t n, double *out, hipStream_t st);

@@ -417,7 +417,7 @@ def workload_adjoint_rotor(n=128, steps=800, radius=40.0, s=2, n_chord=50, n_spa
 def workload_capacity(n=1024, steps=500, radius=300.0, s=2, n_chord=100, n_span=100):
     """1024^3 in-place FP32 run with two counter-rotating 6-blade rotors."""
     c = n / 2
-    bodies = cror_rotors(radius, 6, 0.33 * radius, n_chord, n_span, 5,
+    bodies = cror_rotors(radius, 6, 0.333 * radius, n_chord, n_span, 5,
                          [(0.35 * n, c, c), (0.35 * n + 0.5 * radius, c, c)], [5e-4, -5e-4], s=s)
     return Workload(f"capacity_{n}^3_d3q19", n, n, n, 19, "f32", 0.8, 3 / 16, (0, 0, 0),
                     ("inlet", "outlet", "periodic", "periodic", "periodic", "periodic"), (0.05, 0, 0),

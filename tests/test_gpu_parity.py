@@ -1,11 +1,13 @@
 """GPU parity of the HIP path (through the C ABI) against the FP64 oracle.
 
-Tolerances (max abs error of f, lattice units) follow from the arithmetic:
+Tolerances (error of f, lattice units) follow from the arithmetic:
 FP64 storage/arithmetic: a few ulp of O(1) sums over two steps -> 1e-13;
 FP32: arithmetic rounding ~6e-8 relative on O(1) terms (rho, 1 - B) over two
-steps -> 2e-6; FP16 storage: half an ulp of |delta f| <= 0.04 per store
-(2^-11 * 0.04 = 2e-5) over two steps -> 6e-5.  Solid fractions and body ids
-must match bit for bit.
+steps -> 2e-6; FP16 storage: each store rounds delta f to half an ulp,
+2^-11 |delta f|; the first step's roundings of all Q neighbours feed the
+second collision, so max |err| <= 4 * 2^-11 max |delta f| + 2e-6.  Solid
+fractions and body ids must match bit for bit.  Test meshes avoid vertices
+or faces on sample centres (no on-surface ties between the two voxelisers).
 """
 import sys
 
@@ -86,7 +88,12 @@ def _two_step_compare(orc, sim, gc, wl, seed=5, general=False):
     g = gc.gpu_state_oracle_order(f, orc, sim)
     err = np.abs(g - run.f).max()
     _say(f"  {wl.name}: max |f_gpu - f_oracle| = {err:.3e}")
-    assert err < TOL[wl.storage]
+    if wl.storage == "f16":
+        _, ow, _ = orc.lattice(wl.q)
+        bound = 4 * 2.0 ** -11 * np.abs(run.f - ow[:, None]).max() + 2e-6
+        assert err <= bound, (err, bound)
+    else:
+        assert err < TOL[wl.storage]
     flags = f.error_flags().cpu().numpy()
     assert flags[0] == 0
     out["f"] = f
@@ -153,7 +160,7 @@ def test_mapping_bit_exact(orc, sim, gc, s):
     import torch
 
     _say(f"[mapping] s={s}")
-    rotor = pi.rotor_mesh(pi.RotorSpec(n_blades=3, radius=7.0, hub_radius=1.75, hub_length=3.0, chord_root=2.1,
+    rotor = pi.rotor_mesh(pi.RotorSpec(n_blades=3, radius=7.0, hub_radius=1.75, hub_length=3.1, chord_root=2.1,
                                        chord_tip=1.05, n_chord=8, n_span=6, n_hub=16, seed=7))
     bodies = [pi.Body(pi.Shape("mesh", (), rotor), pi.Motion(axis=(1, 0, 0), theta0=0.2, omega=0.37,
                                                               x0=(16.0, 15.0, 14.0)), s=s),
