@@ -54,7 +54,7 @@ extern "C" {
 /* ---- enums --------------------------------------------------------------- */
 enum { PSM_F64 = 0, PSM_F32 = 1, PSM_F16 = 2 };                 /* PDF storage */
 enum { PSM_PERIODIC = 0, PSM_WALL = 1, PSM_INLET = 2, PSM_OUTLET = 3 }; /* faces */
-enum { PSM_BUF_PDF = 0, PSM_BUF_B = 1, PSM_BUF_WORK = 2 };
+enum { PSM_BUF_PDF = 0, PSM_BUF_B = 1, PSM_BUF_WORK = 2, PSM_BUF_ADJOINT = 3, PSM_BUF_GRAD_B = 4 };
 enum { PSM_SHAPE_ELLIPSOID = 0, PSM_SHAPE_CUBE = 1 };
 #define PSM_MAX_BODIES 8
 
@@ -121,8 +121,12 @@ const char *psm_last_error(void);
 /* Bytes the caller must provide for buffer `which` (PSM_BUF_*):
  *   PDF  q*N*sizeof(storage)
  *   B    psm ? N*4*slots + N (FP32 fraction per slot + one body-id byte) : 0
- *   WORK flags + force/torque partials (max_bodies*6 doubles per tile) +
- *        reduction scratch.                                                  */
+ *   WORK flags + force/torque partials (max_bodies*6 doubles per solid-kernel
+ *        workgroup, 2048 of them) + reduction scratch
+ *   ADJOINT  one adjoint PDF buffer of psm_adjoint_step: q*N values in the
+ *        adjoint precision (FP64 for PSM_F64 fields, else FP32)
+ *   GRAD_B   the dJ/dB accumulator of psm_adjoint_step: N adjoint-precision
+ *        values                                                               */
 int psm_required_bytes(const psm_config *cfg, int which, size_t *out_bytes);
 
 /* This library's lattice: velocities c[q][3], weights w[q], opposite opp[q]
@@ -211,6 +215,34 @@ int psm_stream_collide(psm_field *f, const psm_body *bodies, int n_bodies, int64
  * units. */
 int body_force_torque(psm_field *f, int n_bodies, double *ft_dev, void *stream);
 
+/* ---- sensitivities (adjoint) ------------------------------------------------ */
+/* Optional time-invariant offset field dB (device, N floats, caller-owned,
+ * NULL to clear): every later step uses B_eff = B + dB in slot 0 (body 0).
+ * The offset can make B nonzero anywhere, so the field then treats the whole
+ * domain as possibly solid (slower; meant for sensitivity runs). */
+int psm_set_fraction_offset(psm_field *f, const float *dB_dev);
+
+/* Reverse-mode (adjoint) of step `step` for the torque objective
+ *   J = sum_t wt(t) * axis . T(t)
+ * of body 0 (eq. (11), force on the body, about X), under the frozen-B
+ * convention: the fractions B(t) are inputs (call geometry_map_step for this
+ * step first); the rotation rate enters through u_s = V + W x (x - X) only.
+ * Needs a PSM field with sc = 1, slots = 1 and one mapped body.
+ *   fwd_pdf   the forward PDF buffer as it was before step `step` (parity
+ *             step&1, the field's storage type and layout)
+ *   ahat_in   adjoint of f(step+1): [q][N], standard layout, adjoint precision
+ *   ahat_out  adjoint of f(step) (written; must not alias ahat_in)
+ *   dJdB      accumulated: dJdB[n] += dJ/dB(n, step)
+ *   body      the pose/velocity of body 0 used by the forward step (W may
+ *             differ from the rotation that produced B)
+ *   axis      unit vector a; wt the weight of this step's torque in J
+ * The dJ/dW-along-axis contribution of this step is kept in the field's work
+ * buffer until the next psm_adjoint_step; psm_adjoint_omega adds it (FP64,
+ * fixed order) to out_dev[0]. */
+int psm_adjoint_step(psm_field *f, const void *fwd_pdf, int64_t step, const void *ahat_in, void *ahat_out,
+                     void *dJdB, const psm_body *body, const double axis[3], double wt, void *stream);
+int psm_adjoint_omega(psm_field *f, double *out_dev, void *stream);
+
 /* ---- diagnostics ------------------------------------------------------------ */
 /* Total mass sum_x rho(x) in FP64 (fixed-order tree) into out_dev[0];
  * `step` is the number of steps taken (selects the AA parity). */
@@ -223,7 +255,7 @@ int psm_error_flags(psm_field *f, int32_t *out_dev, void *stream);
  *   PSM_OPT_GENERAL_PATH [0]  1: every row of psm_stream_collide takes the
  *                             general (face-row) addressing path; results are
  *                             bitwise identical, used to cross-check the fast path
- *   PSM_OPT_XCD_REMAP    [1]  1: workgroup ids are remapped so each of the 8
+ *   PSM_OPT_XCD_REMAP    [0]  1: workgroup ids are remapped so each of the 8
  *                             XCDs walks a contiguous range of tiles */
 enum { PSM_OPT_GENERAL_PATH = 1, PSM_OPT_XCD_REMAP = 2 };
 int psm_set_option(psm_field *f, int option, int value);

@@ -80,6 +80,7 @@ def lib():
                                   C.POINTER(C.c_int), C.POINTER(C.c_ubyte)]
         L.or_update_cell.argtypes = [C.POINTER(Config), C.c_int, C.c_int, C.c_int, dp, C.c_int, dp,
                                      C.POINTER(Pose), dp]
+        L.or_adjoint_step.argtypes = [C.POINTER(Config), dp, dp, dp, dp, C.POINTER(Pose), dp, C.c_double, dp, dp]
         L.or_mesh_volume.argtypes = [dp, C.POINTER(C.c_int), C.c_longlong]
         L.or_mesh_volume.restype = C.c_double
         _lib = L
@@ -384,3 +385,57 @@ def sampled_steps(wl, cells, f_at, geoms, steps: int, b_form: int = 0, t0: int =
         return v
 
     return np.array([value(np.asarray(c), t0 + steps) for c in cells])
+
+
+# ----------------------------------------------------------------------------
+# torque objective and its discrete adjoint (frozen solid fractions)
+def _pose_with_rate(motion, t, omega_us):
+    """Pose at t from the prescribed motion (drives the mapping); the solid
+    velocity uses the rate ``omega_us`` instead when given."""
+    p = pose_at(motion, t)
+    if omega_us is not None:
+        p.W = (C.c_double * 3)(*[omega_us * a for a in motion.axis])
+    return p
+
+
+def torque_forward(wl, f0, steps, weights, dB=None, omega_us=None, keep_states=False):
+    """J = sum_t weights[t] * a . T_0(t) for the single body of ``wl``, with
+    B_eff = B_map(t) + dB and u_s from ``omega_us`` (mapping from the motion)."""
+    cfg = make_config(wl)
+    body = wl.bodies[0]
+    geom = OracleGeometry(body.shape, body.s)
+    f = np.ascontiguousarray(f0, dtype=np.float64).copy()
+    axis = np.asarray(body.motion.axis, dtype=np.float64)
+    J = 0.0
+    states, Bs = [], []
+    for t in range(steps):
+        B = map_body(cfg, geom, pose_at(body.motion, t), wl.b_form)
+        if dB is not None:
+            B = B + dB
+        if keep_states:
+            states.append(f.copy())
+            Bs.append(B.copy())
+        ft = step(cfg, f, B[None, :].copy(), [_pose_with_rate(body.motion, t, omega_us)])
+        J += weights[t] * float(axis @ ft[0, 3:])
+    return J, f, states, Bs
+
+
+def torque_adjoint(wl, f0, steps, weights, dB=None, omega_us=None):
+    """(J, dJ/dB (N,), dJ/domega, dJ/df0 (q,N)) by the oracle's adjoint steps."""
+    cfg = make_config(wl)
+    body = wl.bodies[0]
+    J, _, states, Bs = torque_forward(wl, f0, steps, weights, dB, omega_us, keep_states=True)
+    q, N = f0.shape
+    axis = np.ascontiguousarray(body.motion.axis, dtype=np.float64)
+    gnext = np.zeros((q, N))
+    g = np.zeros((q, N))
+    dJdB = np.zeros(N)
+    dJdW = np.zeros(1)
+    for t in range(steps - 1, -1, -1):
+        pose = _pose_with_rate(body.motion, t, omega_us)
+        r = lib().or_adjoint_step(C.byref(cfg), _dp(states[t]), _dp(gnext), _dp(g), _dp(Bs[t]), C.byref(pose),
+                                  _dp(axis), float(weights[t]), _dp(dJdB), _dp(dJdW))
+        if r != 0:
+            raise RuntimeError("or_adjoint_step failed")
+        gnext, g = g, gnext
+    return J, dJdB, float(dJdW[0]), gnext

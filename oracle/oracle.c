@@ -9,6 +9,7 @@
  */
 #include "oracle.h"
 
+#include <complex.h>
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
@@ -150,10 +151,12 @@ static void collide_lat(const or_config *cfg, const lat_t *L, const double *fin,
     for (int i = 0; i < q; ++i) fout[i] = fin[i] + OmF[i];
     return;
   }
+  /* several bodies in one cell: fractions summing past one are scaled to one */
   double B[2], Bsum = 0.0;
   for (int k = 0; k < nslot; ++k) Bsum += Bin[k];
-  for (int k = 0; k < nslot; ++k) B[k] = Bsum > 1.0 ? Bin[k] / Bsum : Bin[k];
-  double fluid = Bsum > 1.0 ? 0.0 : 1.0 - Bsum;
+  const int scale = nslot == 2 && Bsum > 1.0;
+  for (int k = 0; k < nslot; ++k) B[k] = scale ? Bin[k] / Bsum : Bin[k];
+  double fluid = scale ? 0.0 : 1.0 - Bsum;
   for (int i = 0; i < q; ++i) fout[i] = fin[i] + fluid * OmF[i];
   for (int k = 0; k < nslot; ++k) {
     double feqs[OR_MAXQ];
@@ -237,7 +240,7 @@ int or_step(const or_config *cfg, double *f, double *fpost, int nb, const double
         if (cfg->psm)
           for (int b = 0; b < nb; ++b) {
             double v = B[b * N + n];
-            if (v > 0.0) {
+            if (v != 0.0) {
               if (ns == 2) { err |= 1; continue; }
               bid[ns] = b;
               Bs[ns] = v;
@@ -541,7 +544,7 @@ int or_update_cell(const or_config *cfg, int x, int y, int z, const double *nbr,
       if (cfg->psm)
         for (int b = 0; b < nb; ++b) {
           double v = Bn[j * nb + b];
-          if (v > 0.0) {
+          if (v != 0.0) {
             if (ns == 2) return -3;
             const or_pose *P = &poses[b];
             double r[3] = {p[0] + 0.5 - P->X[0], p[1] + 0.5 - P->X[1], p[2] + 0.5 - P->X[2]};
@@ -561,5 +564,140 @@ int or_update_cell(const or_config *cfg, int x, int y, int z, const double *nbr,
     }
     out[k] = v;
   }
+  return 0;
+}
+
+/* ---------------------------------------------------------------------------
+ * Discrete adjoint of one step for the torque objective
+ *   J_t = wt * a . T_0(t)  (torque of body 0 about X, eq. (11), body side)
+ * with frozen solid fractions.  Independent of any hand-derived Jacobian:
+ * every per-cell derivative is obtained by complex-step differentiation of the
+ * collision above, re-evaluated in complex arithmetic (step 1e-30, exact to
+ * rounding), and the transposed streaming is the literal scatter of the pull
+ * rules of or_step.
+ * ------------------------------------------------------------------------- */
+typedef double complex zc;
+
+static void feq_z(const lat_t *L, zc rho, const zc u[3], zc *feq) {
+  const double cs2 = 1.0 / 3.0;
+  zc uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+  for (int i = 0; i < L->q; ++i) {
+    zc cu = L->c[3 * i] * u[0] + L->c[3 * i + 1] * u[1] + L->c[3 * i + 2] * u[2];
+    feq[i] = L->w[i] * rho * (1.0 + cu / cs2 + cu * cu / (2.0 * cs2 * cs2) - uu / (2.0 * cs2));
+  }
+}
+
+/* the collision of collide_lat for one body slot, in complex arithmetic */
+static void collide_z(const or_config *cfg, const lat_t *L, const zc *fin, zc B, const zc us[3], zc *fout,
+                      zc dF[3]) {
+  const int q = L->q;
+  const double cs2 = 1.0 / 3.0;
+  zc rho = 0.0, j[3] = {0.0, 0.0, 0.0};
+  for (int i = 0; i < q; ++i) {
+    rho += fin[i];
+    for (int a = 0; a < 3; ++a) j[a] += L->c[3 * i + a] * fin[i];
+  }
+  zc u[3];
+  for (int a = 0; a < 3; ++a) u[a] = (j[a] + 0.5 * cfg->force[a]) / rho;
+  zc feq[OR_MAXQ], S[OR_MAXQ], OmF[OR_MAXQ], feqs[OR_MAXQ];
+  feq_z(L, rho, u, feq);
+  for (int i = 0; i < q; ++i) {
+    zc cu = 0.0, uF = 0.0;
+    double cF = 0.0;
+    for (int a = 0; a < 3; ++a) {
+      cu += L->c[3 * i + a] * u[a];
+      cF += L->c[3 * i + a] * cfg->force[a];
+      uF += u[a] * cfg->force[a];
+    }
+    S[i] = L->w[i] * ((cF - uF) / cs2 + cu * cF / (cs2 * cs2));
+  }
+  double le = 1.0 / cfg->tau;
+  double lo = 1.0 / (0.5 + cfg->magic / (cfg->tau - 0.5));
+  for (int i = 0; i < q; ++i) {
+    int k = L->opp[i];
+    zc fp = 0.5 * (fin[i] + fin[k]), fm = 0.5 * (fin[i] - fin[k]);
+    zc ep = 0.5 * (feq[i] + feq[k]), em = 0.5 * (feq[i] - feq[k]);
+    zc sp = 0.5 * (S[i] + S[k]), sm = 0.5 * (S[i] - S[k]);
+    OmF[i] = -le * (fp - ep) - lo * (fm - em) + (1.0 - 0.5 * le) * sp + (1.0 - 0.5 * lo) * sm;
+  }
+  feq_z(L, rho, us, feqs);
+  zc mom[3] = {0.0, 0.0, 0.0};
+  for (int i = 0; i < q; ++i) {
+    int ib = L->opp[i];
+    zc om;
+    if (cfg->sc == 1)
+      om = (fin[ib] - feq[ib]) - (fin[i] - feqs[i]);
+    else if (cfg->sc == 2)
+      om = (feqs[i] - fin[i]) + (1.0 - 1.0 / cfg->tau) * (fin[i] - feqs[i]);
+    else
+      om = (fin[ib] - feqs[ib]) - (fin[i] - feqs[i]);
+    fout[i] = fin[i] + (1.0 - B) * OmF[i] + B * om;
+    for (int a = 0; a < 3; ++a) mom[a] += L->c[3 * i + a] * om;
+  }
+  for (int a = 0; a < 3; ++a) dF[a] = -B * mom[a];
+}
+
+int or_adjoint_step(const or_config *cfg, const double *f, const double *ghat_next, double *ghat, const double *B,
+                    const or_pose *pose, const double *axis, double wt, double *dJdB, double *dJdW) {
+  lat_t L;
+  if (lat_get(cfg->q, &L) != 0) return -1;
+  const int q = L.q, nx = cfg->nx, ny = cfg->ny, nz = cfg->nz;
+  const long long N = (long long)nx * ny * nz;
+  /* adjoint of the post-collision values: scatter of the pull rules */
+  double *gpost = (double *)calloc((size_t)q * N, sizeof(double));
+  for (int z = 0; z < nz; ++z)
+    for (int y = 0; y < ny; ++y)
+      for (int x = 0; x < nx; ++x) {
+        long long n = x + (long long)nx * (y + (long long)ny * z);
+        for (int k = 0; k < q; ++k) {
+          int s32;
+          int kind = classify(cfg, x, y, z, &L.c[3 * k], &s32);
+          double g = ghat_next[k * N + n];
+          if (kind == 0) gpost[k * N + s32] += g;
+          else if (kind == OR_WALL || kind == OR_INLET) gpost[L.opp[k] * N + n] += g;
+          else gpost[k * N + n] += g;
+        }
+      }
+  const double h = 1e-30;
+  double *slab = (double *)calloc((size_t)nz, sizeof(double));
+#pragma omp parallel for schedule(static)
+  for (int z = 0; z < nz; ++z) {
+    double acc = 0.0;
+    for (int y = 0; y < ny; ++y)
+      for (int x = 0; x < nx; ++x) {
+        long long n = x + (long long)nx * (y + (long long)ny * z);
+        double r[3] = {x + 0.5 - pose->X[0], y + 0.5 - pose->X[1], z + 0.5 - pose->X[2]};
+        double us[3] = {pose->V[0] + (pose->W[1] * r[2] - pose->W[2] * r[1]),
+                        pose->V[1] + (pose->W[2] * r[0] - pose->W[0] * r[2]),
+                        pose->V[2] + (pose->W[0] * r[1] - pose->W[1] * r[0])};
+        double axr[3] = {axis[1] * r[2] - axis[2] * r[1], axis[2] * r[0] - axis[0] * r[2],
+                         axis[0] * r[1] - axis[1] * r[0]};
+        zc fin[OR_MAXQ], fo[OR_MAXQ], usz[3], dF[3];
+        /* d(objective contribution)/d(parameter) for a perturbed evaluation:
+         * sum_i gpost_i Im(f*_i)/h + wt * Im(a . (r x dF))/h */
+        for (int j = -2; j < q; ++j) {
+          for (int i = 0; i < q; ++i) fin[i] = f[i * N + n];
+          for (int a = 0; a < 3; ++a) usz[a] = us[a];
+          zc Bz = B[n];
+          if (j >= 0) fin[j] += I * h;
+          else if (j == -1) Bz += I * h;
+          else
+            for (int a = 0; a < 3; ++a) usz[a] += I * h * axr[a];
+          collide_z(cfg, &L, fin, Bz, usz, fo, dF);
+          double d = 0.0;
+          for (int i = 0; i < q; ++i) d += gpost[i * N + n] * cimag(fo[i]) / h;
+          zc tq = axis[0] * (r[1] * dF[2] - r[2] * dF[1]) + axis[1] * (r[2] * dF[0] - r[0] * dF[2]) +
+                  axis[2] * (r[0] * dF[1] - r[1] * dF[0]);
+          d += wt * cimag(tq) / h;
+          if (j >= 0) ghat[j * N + n] = d;
+          else if (j == -1) dJdB[n] += d;
+          else acc += d;
+        }
+      }
+    slab[z] = acc;
+  }
+  for (int z = 0; z < nz; ++z) *dJdW += slab[z];
+  free(slab);
+  free(gpost);
   return 0;
 }

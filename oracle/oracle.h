@@ -95,6 +95,9 @@ float or_b_from_eps(double eps, double tau, int b_form);
 int or_update_cell(const or_config *cfg, int x, int y, int z, const double *nbr, int nb, const double *Bn,
                    const or_pose *poses, double *out);
 
+int or_adjoint_step(const or_config *cfg, const double *f, const double *ghat_next, double *ghat, const double *B,
+                    const or_pose *pose, const double *axis, double wt, double *dJdB, double *dJdW);
+
 double or_winding(const double *v, const int *t, long long nt, const double p[3]);
 int or_voxelize(const double *v, const int *t, long long nt, int s, const int mmin[3],
                 const int dims[3], unsigned char *out);

@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(HERE, "libpsm.so")
 PSM_OK, PSM_EINVAL, PSM_ESIZE, PSM_EUNSUP, PSM_EHIP = 0, -1, -2, -3, -4
 PSM_F64, PSM_F32, PSM_F16 = 0, 1, 2
 PSM_PERIODIC, PSM_WALL, PSM_INLET, PSM_OUTLET = 0, 1, 2, 3
-PSM_BUF_PDF, PSM_BUF_B, PSM_BUF_WORK = 0, 1, 2
+PSM_BUF_PDF, PSM_BUF_B, PSM_BUF_WORK, PSM_BUF_ADJOINT, PSM_BUF_GRAD_B = 0, 1, 2, 3, 4
 PSM_SHAPE_ELLIPSOID, PSM_SHAPE_CUBE = 0, 1
 PSM_OPT_GENERAL_PATH, PSM_OPT_XCD_REMAP = 1, 2
 PSM_MAX_BODIES = 8
@@ -26,7 +26,7 @@ EXPORTS = [
     "pdf_field_destroy", "psm_field_reset", "psm_geometry_box", "psm_voxelize_host", "psm_analytic_host",
     "geometry_field_create", "geometry_field_create_analytic", "geometry_field_destroy", "geometry_map_step",
     "psm_stream_collide", "body_force_torque", "psm_mass_fp64", "psm_macroscopic", "psm_error_flags",
-    "psm_set_option", "psm_stream_copy",
+    "psm_set_option", "psm_stream_copy", "psm_set_fraction_offset", "psm_adjoint_step", "psm_adjoint_omega",
 ]
 
 
@@ -53,8 +53,8 @@ class PSMError(RuntimeError):
 
 def _load():
     if not os.path.exists(LIB_PATH):
-        raise ImportError(f"{LIB_PATH} is missing: build it with paper_2502_20049_amd/build.py "
-                          "(or __graft_entry__.build()); there is no fallback path")
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_2502_20049_amd/build.py; "
+                          "there is no fallback path")
     L = C.CDLL(LIB_PATH)
     vp, sz, i64, dp = C.c_void_p, C.c_size_t, C.c_int64, C.POINTER(C.c_double)
     i32p = C.POINTER(C.c_int32)
@@ -81,6 +81,9 @@ def _load():
         "psm_error_flags": (C.c_int, [vp, vp, vp]),
         "psm_set_option": (C.c_int, [vp, C.c_int, C.c_int]),
         "psm_stream_copy": (C.c_int, [vp, vp, sz, vp]),
+        "psm_set_fraction_offset": (C.c_int, [vp, vp]),
+        "psm_adjoint_step": (C.c_int, [vp, vp, i64, vp, vp, vp, C.POINTER(psm_body), dp, C.c_double, vp]),
+        "psm_adjoint_omega": (C.c_int, [vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)

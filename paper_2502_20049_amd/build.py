@@ -31,6 +31,7 @@ SOURCES = [
     ("geometry.cpp", ["-x", "hip", "-ffp-contract=off"]),
     ("k_mapping.hip", ["-ffp-contract=off"]),
     ("k_misc.hip", []),
+    ("k_adjoint.hip", []),
     ("k_sc_f64.hip", []),
     ("k_sc_f32.hip", []),
     ("k_sc_f16.hip", []),

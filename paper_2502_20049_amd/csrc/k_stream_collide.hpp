@@ -245,10 +245,10 @@ __device__ __forceinline__ void classify(const SCArgs &a, int x, int y, int z, u
 // solid cells): own slot at even parity or for a face direction, else the
 // slot (x - c_k, kbar) with periodic wrap.
 template <int Q, typename T, int PAR>
-__device__ __forceinline__ char *slot_general(const SCArgs &a, int k, int x, int y, int z, uint64_t n,
+__device__ __forceinline__ char *slot_general(const SCArgs &a, char *pdf, int k, int x, int y, int z, uint64_t n,
                                               uint32_t bcm) {
   const size_t NS = (size_t)a.N * sizeof(T);
-  if (PAR == 0 || ((bcm >> k) & 1u)) return a.pdf + (size_t)k * NS + (size_t)n * sizeof(T);
+  if (PAR == 0 || ((bcm >> k) & 1u)) return pdf + (size_t)k * NS + (size_t)n * sizeof(T);
   int sx = x - cx<Q>(k), sy = y - cy<Q>(k), sz = z - cz<Q>(k);
   if (sx < 0) sx += a.nx;
   if (sx >= a.nx) sx -= a.nx;
@@ -257,7 +257,14 @@ __device__ __forceinline__ char *slot_general(const SCArgs &a, int k, int x, int
   if (sz < 0) sz += a.nz;
   if (sz >= a.nz) sz -= a.nz;
   const uint64_t src = (uint64_t)sx + (uint64_t)a.nx * ((uint64_t)sy + (uint64_t)a.ny * (uint64_t)sz);
-  return a.pdf + (size_t)opp<Q>(k) * NS + (size_t)src * sizeof(T);
+  return pdf + (size_t)opp<Q>(k) * NS + (size_t)src * sizeof(T);
+}
+
+// Solid fraction of slot 0, plus the optional time-invariant offset field.
+__device__ __forceinline__ float solid_fraction(const SCArgs &a, uint64_t n) {
+  float b = a.B0[n];
+  if (a.dB) b += a.dB[n];
+  return b;
 }
 
 // Does the tile / cell need the solid-fraction read?  B can only be nonzero
@@ -300,7 +307,7 @@ __global__ __launch_bounds__(256) void k_fluid(const SCArgs a) {
   if constexpr (PSM) {
     const int x0 = txi * a.TX, y0 = 1 + tyi * a.TY;
     if (boxes_touch(a, x0, x0 + a.TX - 1, y0, y0 + a.TY - 1, z, z)) {
-      if (active && a.B0[n] != 0.0f) active = false;
+      if (active && solid_fraction(a, n) != 0.0f) active = false;
     }
   }
   if (!active) return;
@@ -407,14 +414,14 @@ __global__ __launch_bounds__(256) void k_fluid_face(const SCArgs a) {
   }
   const uint64_t n = (uint64_t)x + (uint64_t)a.nx * ((uint64_t)y + (uint64_t)a.ny * (uint64_t)z);
   if constexpr (PSM) {
-    if (boxes_touch(a, x, x, y, y, z, z) && a.B0[n] != 0.0f) return;
+    if (boxes_touch(a, x, x, y, y, z, z) && solid_fraction(a, n) != 0.0f) return;
   }
   uint32_t bcm, outm, inm;
   classify<Q>(a, x, y, z, bcm, outm, inm);
   R f[Q];
   sfor<Q>([&](auto K) {
     constexpr int k = K;
-    R v = ldv<T, R>(slot_general<Q, T, PAR>(a, k, x, y, z, n, bcm));
+    R v = ldv<T, R>(slot_general<Q, T, PAR>(a, a.pdf, k, x, y, z, n, bcm));
     if constexpr (PAR == 1) {
       if ((inm >> k) & 1u) v += inlet_term<Q, R>(a, k);
     }
@@ -428,7 +435,7 @@ __global__ __launch_bounds__(256) void k_fluid_face(const SCArgs a) {
     if constexpr (PAR == 1) {
       if ((inm >> k) & 1u) v += inlet_term<Q, R>(a, k);
     }
-    stv<T, R>(slot_general<Q, T, PAR>(a, k, x, y, z, n, bcm), v);
+    stv<T, R>(slot_general<Q, T, PAR>(a, a.pdf, k, x, y, z, n, bcm), v);
   });
 }
 
@@ -466,7 +473,7 @@ __global__ __launch_bounds__(256) void k_solid(const SCArgs a) {
     int b0 = 0, b1 = 0;
     bool two = false;
     if (act) {
-      B0 = (R)a.B0[n];
+      B0 = (R)solid_fraction(a, n);
       act = B0 != R(0);
     }
     if (act) {
@@ -488,7 +495,7 @@ __global__ __launch_bounds__(256) void k_solid(const SCArgs a) {
         classify<Q>(a, x, y, z, bcm, outm, inm);
         sfor<Q>([&](auto K) {
           constexpr int k = K;
-          R v = ldv<T, R>(slot_general<Q, T, PAR>(a, k, x, y, z, n, bcm));
+          R v = ldv<T, R>(slot_general<Q, T, PAR>(a, a.pdf, k, x, y, z, n, bcm));
           if constexpr (PAR == 1) {
             if ((inm >> k) & 1u) v += inlet_term<Q, R>(a, k);
           }
@@ -531,7 +538,7 @@ __global__ __launch_bounds__(256) void k_solid(const SCArgs a) {
           if constexpr (PAR == 1) {
             if ((inm >> k) & 1u) v += inlet_term<Q, R>(a, k);
           }
-          stv<T, R>(slot_general<Q, T, PAR>(a, k, x, y, z, n, bcm), v);
+          stv<T, R>(slot_general<Q, T, PAR>(a, a.pdf, k, x, y, z, n, bcm), v);
         });
       }
       // force / torque on each body touched by this chunk

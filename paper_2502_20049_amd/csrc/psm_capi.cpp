@@ -20,6 +20,7 @@ int hip_fail(hipError_t e, const char *what) {
   return PSM_EHIP;
 }
 
+hipError_t launch_adjoint(const psm_field &f, const AdjArgs &A, hipStream_t st);
 hipError_t launch_sc_f64(const psm_config &, const SCArgs &, int, bool, hipStream_t, int *);
 hipError_t launch_sc_f32(const psm_config &, const SCArgs &, int, bool, hipStream_t, int *);
 hipError_t launch_sc_f16(const psm_config &, const SCArgs &, int, bool, hipStream_t, int *);
@@ -125,6 +126,7 @@ SCArgs make_sc_args(const psm_field &f) {
   a.lam_o = 1.0 / (0.5 + c.magic / (c.tau - 0.5));
   a.max_bodies = std::max(1, c.max_bodies);
   a.slots = c.slots;
+  a.dB = f.opt_whole_domain ? f.dB : nullptr;
   return a;
 }
 
@@ -172,6 +174,12 @@ int psm_required_bytes(const psm_config *cfg, int which, size_t *out) {
       return PSM_OK;
     case PSM_BUF_WORK:
       *out = L.work_bytes;
+      return PSM_OK;
+    case PSM_BUF_ADJOINT:
+      *out = (size_t)cfg->q * (size_t)L.N * (cfg->storage == PSM_F64 ? 8 : 4);
+      return PSM_OK;
+    case PSM_BUF_GRAD_B:
+      *out = (size_t)L.N * (cfg->storage == PSM_F64 ? 8 : 4);
       return PSM_OK;
   }
   return set_error("bad buffer id"), PSM_EINVAL;
@@ -261,7 +269,7 @@ int pdf_field_create(const psm_config *cfg, void *pdf, size_t pdf_bytes, void *b
   f->nty = L.nty;
   f->ntiles = L.ntiles;
   for (int i = 0; i < PSM_MAX_BODIES; ++i) f->active[i] = empty_box();
-  f->opt_xcd_remap = 1;
+  f->opt_xcd_remap = 0;
   if (hipGetDevice(&f->device) != hipSuccess) f->device = -1;
   *out = f;
   return PSM_OK;
@@ -568,6 +576,20 @@ int psm_stream_collide(psm_field *f, const psm_body *bodies, int nb, int64_t ste
   a.nbox = a.nb;
   a.cprefix[a.nb] = chunks;
   a.nchunks = chunks;
+  if (f->opt_whole_domain && a.nb > 0) {
+    // the offset field can make B nonzero anywhere: one box, the whole domain
+    IBox W;
+    W.lo[0] = W.lo[1] = W.lo[2] = 0;
+    W.hi[0] = f->cfg.nx - 1;
+    W.hi[1] = f->cfg.ny - 1;
+    W.hi[2] = f->cfg.nz - 1;
+    a.box[0] = W;
+    for (int b = 1; b < a.nb; ++b) a.box[b] = empty_box();
+    a.cprefix[0] = 0;
+    const uint32_t whole = (uint32_t)((f->N + 255) / 256);
+    for (int b = 1; b <= a.nb; ++b) a.cprefix[b] = whole;
+    a.nchunks = whole;
+  }
   a.xcd_remap = f->opt_xcd_remap;
   const int parity = (int)(step & 1);
   const bool big = (uint64_t)f->N * storage_size(f->cfg.storage) > 0xFFFFFFFFull;
@@ -614,6 +636,53 @@ int psm_set_option(psm_field *f, int option, int value) {
     case PSM_OPT_XCD_REMAP: f->opt_xcd_remap = value ? 1 : 0; return PSM_OK;
   }
   return set_error("unknown option"), PSM_EINVAL;
+}
+
+int psm_set_fraction_offset(psm_field *f, const float *dB) {
+  if (!f) return set_error("null handle"), PSM_EINVAL;
+  if (!f->cfg.psm) return set_error("fraction offset on a plain-LBM field"), PSM_EINVAL;
+  if (((uintptr_t)dB) & 3u) return set_error("offset field must be 4-byte aligned"), PSM_EINVAL;
+  f->dB = dB;
+  f->opt_whole_domain = dB != nullptr;
+  return PSM_OK;
+}
+
+int psm_adjoint_step(psm_field *f, const void *fwd, int64_t step, const void *ain, void *aout, void *dJdB,
+                     const psm_body *body, const double axis[3], double wt, void *stream) {
+  if (!f || !fwd || !ain || !aout || !dJdB || !body || !axis) return set_error("null argument"), PSM_EINVAL;
+  if (step < 0) return set_error("negative step"), PSM_EINVAL;
+  if (!f->cfg.psm || f->cfg.sc != 1 || f->cfg.slots != 1)
+    return set_error("psm_adjoint_step supports PSM fields with SC1 and one body slot"), PSM_EUNSUP;
+  if (f->nb_mapped != 1) return set_error("psm_adjoint_step needs the single body mapped for this step"), PSM_EINVAL;
+  if (ain == aout) return set_error("adjoint input and output must differ"), PSM_EINVAL;
+  const double an = axis[0] * axis[0] + axis[1] * axis[1] + axis[2] * axis[2];
+  if (!(fabs(an - 1.0) < 1e-12) || !isfinite(wt)) return set_error("axis must be a unit vector, wt finite"), PSM_EINVAL;
+  AdjArgs A;
+  memset(&A, 0, sizeof(A));
+  A.s = make_sc_args(*f);
+  A.fwd = (const char *)fwd;
+  A.parity = (int)(step & 1);
+  A.ain = ain;
+  A.aout = aout;
+  A.dJdB = dJdB;
+  for (int d = 0; d < 3; ++d) {
+    A.X[d] = body->X[d];
+    A.V[d] = body->V[d];
+    A.W[d] = body->W[d];
+    A.axis[d] = axis[d];
+  }
+  A.wt = wt;
+  A.part = f->red;
+  hipError_t e = launch_adjoint(*f, A, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "psm_adjoint_step launch");
+  return PSM_OK;
+}
+
+int psm_adjoint_omega(psm_field *f, double *out, void *stream) {
+  if (!f || !out) return set_error("null argument"), PSM_EINVAL;
+  hipError_t e = launch_sum_accumulate(f->red, f->red_count, out, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "psm_adjoint_omega launch");
+  return PSM_OK;
 }
 
 int psm_error_flags(psm_field *f, int32_t *out, void *stream) {

@@ -7,7 +7,7 @@
 
 #include <string>
 
-#include "../../include/psm.h"
+#include "psm.h"
 
 namespace psm {
 
@@ -93,7 +93,8 @@ struct SCArgs {
   const float *B0;
   const float *B1;
   const uint8_t *meta;
-  double *ftp;  // [solid workgroup][max_bodies][6]
+  const float *dB;  // optional offset added to the slot-0 fraction (whole-domain mode)
+  double *ftp;      // [solid workgroup][max_bodies][6]
   int nx, ny, nz;
   uint32_t N;
   int TX, TY, lTX;  // tile shape of the interior kernel, log2(TX)
@@ -118,6 +119,19 @@ struct SCArgs {
   uint32_t cprefix[PSM_MAX_BODIES + 1];  // 256-cell chunk offsets of the boxes
   uint32_t nchunks;
   BodyK body[PSM_MAX_BODIES];
+};
+
+// arguments of the adjoint step kernel
+struct AdjArgs {
+  SCArgs s;           // field geometry, faces, rates, B pointers
+  const char *fwd;    // forward state before step t (storage type, parity t&1)
+  int parity;
+  const void *ain;    // fhat(t+1), [q][N], adjoint precision
+  void *aout;         // fhat(t)
+  void *dJdB;         // accumulated, [N], adjoint precision
+  double X[3], V[3], W[3], axis[3];
+  double wt;
+  double *part;       // per-workgroup dJ/dOmega partial sums
 };
 
 // per-body data of the mapping kernel
@@ -177,6 +191,8 @@ struct psm_field {
   int device;
   int opt_general_path;
   int opt_xcd_remap;
+  int opt_whole_domain;  // B may be nonzero anywhere (offset field set)
+  const float *dB;       // caller-owned offset added to the slot-0 fraction
 };
 
 struct psm_geom {
@@ -207,6 +223,7 @@ hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t st);
 hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t st);
 hipError_t launch_flags_copy(const int32_t *src, int32_t *dst, hipStream_t st);
 uint32_t macro_blocks(const psm_field &f);
+hipError_t launch_sum_accumulate(const double *p, uint32_t n, double *out, hipStream_t st);
 
 // host geometry
 int geom_box(int kind, const double *params, const double *verts, int64_t nv, int s, int32_t mmin[3],
