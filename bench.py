@@ -58,12 +58,17 @@ def bytes_per_cell(q, storage, psm=True):
     return 2 * q * sz + (4 if psm else 0)
 
 
-def run_steps(field, t0, n, events=None, map_events=None):
-    import torch
-
+def run_steps(field, t0, n, events=None, map_events=None, fused=True):
+    """Steps t0 .. t0+n-1.  fused: one psm_step per step (mapping overlapped
+    with the bulk of the update, F/T summed); else the separate calls
+    geometry_map_step / psm_stream_collide / body_force_torque, with HIP
+    events on the launch stream around the first two when given."""
     for i in range(n):
         t = t0 + i
         poses = field.poses(t) if field.nb else None
+        if fused:
+            field.step(t, poses, ft=field.ft if field.nb else None)
+            continue
         if field.nb and (field.remap_every_step or not field._mapped_once):
             if map_events is not None:
                 map_events[i][0].record()
@@ -81,20 +86,32 @@ def run_steps(field, t0, n, events=None, map_events=None):
 
 
 def time_field(field, steps, warmup, t0=0):
+    """Wall time of `steps` whole steps (psm_step) after `warmup` untimed ones."""
     import torch
 
     t = run_steps(field, t0, warmup)
     torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    t = run_steps(field, t, steps)
+    torch.cuda.synchronize()
+    return time.perf_counter() - w0, t
+
+
+def time_kernels(field, steps, t0):
+    """Average launch times (ms) of psm_stream_collide and geometry_map_step,
+    from HIP events on the launch stream, over `steps` steps run as separate
+    calls."""
+    import torch
+
+    t = run_steps(field, t0, 5, fused=False)
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
     mev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
     torch.cuda.synchronize()
-    w0 = time.perf_counter()
-    run_steps(field, t, steps, ev, mev if field.nb and field.remap_every_step else None)
+    run_steps(field, t, steps, ev, mev if field.nb and field.remap_every_step else None, fused=False)
     torch.cuda.synchronize()
-    wall = time.perf_counter() - w0
     sc_ms = sum(a.elapsed_time(b) for a, b in ev) / steps
     map_ms = (sum(a.elapsed_time(b) for a, b in mev) / steps) if field.nb and field.remap_every_step else 0.0
-    return wall, sc_ms, map_ms
+    return sc_ms, map_ms
 
 
 def copy_probe(nbytes=4 << 30, reps=20):
@@ -161,6 +178,86 @@ def accuracy_check(steps=100):
     return out
 
 
+def s_sweep(steps=200):
+    """The channel workload at supersampling s = 0..3 (PSM + mapping every step)."""
+    import torch
+
+    import psm_inputs as pi
+    from paper_2502_20049_amd import sim
+
+    out = {}
+    for s in (0, 1, 2, 3):
+        wl = pi.workload_ellipsoid_channel(256, "f32", steps=steps, s=s)
+        f = sim.Field(wl)
+        wall, t = time_field(f, steps, 20)
+        sc, mp = time_kernels(f, 100, t)
+        out[f"s{s}"] = {"mlups": round(wl.n_cells * steps / wall / 1e6, 1), "map_ms": round(mp, 5),
+                        "collide_ms": round(sc, 5)}
+        del f
+        torch.cuda.empty_cache()
+    return out
+
+
+def rotor_box(steps=200):
+    """Rotor-heavy scenario: one 8-blade rotor of radius 120 filling a 256^3
+    box (s = 2), PSM + mapping every step, and the same lattice as plain LBM."""
+    import torch
+
+    import psm_inputs as pi
+    from paper_2502_20049_amd import sim
+
+    wl = pi.workload_rotor_box(steps=steps)
+    out = {"case": wl.name + f", {sum(len(b.shape.mesh.tris) for b in wl.bodies)} triangles, s=2"}
+    t0 = time.perf_counter()
+    f = sim.Field(wl)
+    out["setup_s"] = round(time.perf_counter() - t0, 2)
+    wall, t = time_field(f, steps, 20)
+    sc, mp = time_kernels(f, 100, t)
+    out["psm_mlups"] = round(wl.n_cells * steps / wall / 1e6, 1)
+    out["collide_ms"] = round(sc, 5)
+    out["map_ms"] = round(mp, 5)
+    out["map_share_unoverlapped"] = round(mp * steps / 1e3 / wall, 4)
+    del f
+    torch.cuda.empty_cache()
+    fl = sim.Field(wl, psm=False)
+    wall_l, _ = time_field(fl, steps, 20)
+    out["plain_lbm_mlups"] = round(wl.n_cells * steps / wall_l / 1e6, 1)
+    del fl
+    torch.cuda.empty_cache()
+    return out
+
+
+def adjoint_rate(steps=800, window=200):
+    """Torque-gradient sweep on the 128^3 4-blade rotor: J = mean axial torque
+    over the last 200 of 800 steps; forward (with checkpoints) and backward
+    (recompute + adjoint) wall times."""
+    import numpy as np
+    import torch
+
+    import psm_inputs as pi
+    from paper_2502_20049_amd import adjoint
+
+    wl = pi.workload_adjoint_rotor(steps=steps)
+    w = np.zeros(steps)
+    w[-window:] = 1.0 / window
+    obj = adjoint.TorqueAdjoint(wl, steps, w)
+    obj.forward()
+    obj.backward()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    J = obj.forward()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    _, gW, _ = obj.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    N = wl.n_cells
+    return {"case": f"{wl.name}, {steps} steps, window {window}, checkpoint segment {obj.L}",
+            "J": J, "dJ_dOmega": gW, "forward_s": round(t1 - t0, 4), "backward_s": round(t2 - t1, 4),
+            "backward_mcell_steps_per_s": round(N * steps / (t2 - t1) / 1e6, 1),
+            "backward_gbs_at_472B": round(472 * N * steps / (t2 - t1) / 1e9, 1)}
+
+
 def cpu_baseline(wl, nsteps=2):
     import oracle
 
@@ -184,6 +281,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip variants, copy probe and accuracy")
     ap.add_argument("--only-psm", action="store_true", help="time the PSM path only (for profiling)")
+    ap.add_argument("--copy-only", action="store_true",
+                    help="run only the device copy probe (1 GiB read + 1 GiB written per launch): the "
+                         "calibration for rocprofv3 FETCH_SIZE / WRITE_SIZE")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the PSM hot path here is single-GPU (no sharding or collectives); "
@@ -195,10 +295,16 @@ def main():
     from paper_2502_20049_amd import sim
 
     torch.cuda.set_device(0)
+    if args.copy_only:
+        bw = copy_probe(nbytes=1 << 30, reps=5)
+        print(json.dumps({"copy_probe_gbs": round(bw, 1), "bytes_read_per_launch": 1 << 30,
+                          "bytes_written_per_launch": 1 << 30}), flush=True)
+        return
     wl = workload(args.workload)
     storage = wl.storage
     f = sim.Field(wl)
-    wall, sc_ms, map_ms = time_field(f, args.steps, args.warmup)
+    wall, t_end = time_field(f, args.steps, args.warmup)
+    sc_ms, map_ms = time_kernels(f, min(args.steps, 300), t_end)
     N = wl.n_cells
     mlups = N * args.steps / wall / 1e6
     bpc = bytes_per_cell(wl.q, storage)
@@ -217,27 +323,39 @@ def main():
                      "traffic": None if traffic is None else round(traffic, 0),
                      "kernel": "psm_stream_collide", "algorithmic_bytes_per_cell": bpc,
                      "avg_launch_ms": round(sc_ms, 5)},
-        "kernels_ms": {"psm_stream_collide": round(sc_ms, 5), "geometry_map_step": round(map_ms, 5)},
+        "kernels_ms": {"psm_stream_collide": round(sc_ms, 5), "geometry_map_step": round(map_ms, 5),
+                       "note": "launch times from separate calls after the timed steps (which run psm_step)"},
     }
     del f
     torch.cuda.empty_cache()
     if not args.no_extras and not args.only_psm:
         extras = {}
         fl = sim.Field(wl, psm=False)
-        wall_l, sc_l, _ = time_field(fl, min(args.steps, 500), 20)
+        wall_l, tl = time_field(fl, min(args.steps, 500), 20)
+        sc_l, _ = time_kernels(fl, 100, tl)
         extras["plain_lbm_same_storage"] = {"mlups": round(N * min(args.steps, 500) / wall_l / 1e6, 1),
                                             "kernel_ms": round(sc_l, 5),
                                             "gbs": round(bytes_per_cell(wl.q, storage, False) * N / sc_l / 1e6, 1)}
         del fl
         torch.cuda.empty_cache()
+        sched = {}
+        for mode in (0, 1, 2):
+            fm = sim.Field(wl)
+            fm.set_option(3, mode)
+            wall_m, _ = time_field(fm, min(args.steps, 500), 20)
+            sched[str(mode)] = round(N * min(args.steps, 500) / wall_m / 1e6, 1)
+            del fm
+            torch.cuda.empty_cache()
+        extras["psm_step_schedule_mlups"] = sched
         fs = sim.Field(wl, remap_every_step=False)
-        wall_s, sc_s, _ = time_field(fs, min(args.steps, 500), 20)
+        wall_s, _ = time_field(fs, min(args.steps, 500), 20)
         extras["psm_static_geometry"] = {"mlups": round(N * min(args.steps, 500) / wall_s / 1e6, 1)}
         del fs
         torch.cuda.empty_cache()
         alt = "f16" if storage != "f16" else "f32"
         fa = sim.Field(wl, storage=alt)
-        wall_a, sc_a, _ = time_field(fa, min(args.steps, 500), 20)
+        wall_a, ta = time_field(fa, min(args.steps, 500), 20)
+        sc_a, _ = time_kernels(fa, 100, ta)
         extras[f"psm_{alt}_storage"] = {"mlups": round(N * min(args.steps, 500) / wall_a / 1e6, 1),
                                         "kernel_ms": round(sc_a, 5),
                                         "gbs": round(bytes_per_cell(wl.q, alt) * N / sc_a / 1e6, 1)}
@@ -247,6 +365,9 @@ def main():
         extras["copy_probe_gbs"] = round(bw, 1)
         extras["psm_frac_of_copy_bw"] = round(achieved / bw, 4)
         extras["accuracy_vs_fp64_oracle"] = accuracy_check()
+        extras["supersampling_sweep"] = s_sweep()
+        extras["rotor_box_256"] = rotor_box()
+        extras["adjoint_rotor_128"] = adjoint_rate()
         line["extras"] = extras
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(wl)

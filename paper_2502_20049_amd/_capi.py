@@ -27,6 +27,7 @@ EXPORTS = [
     "geometry_field_create", "geometry_field_create_analytic", "geometry_field_destroy", "geometry_map_step",
     "psm_stream_collide", "body_force_torque", "psm_mass_fp64", "psm_macroscopic", "psm_error_flags",
     "psm_set_option", "psm_stream_copy", "psm_set_fraction_offset", "psm_adjoint_step", "psm_adjoint_omega",
+    "psm_step",
 ]
 
 
@@ -75,6 +76,7 @@ def _load():
         "geometry_field_destroy": (C.c_int, [vp]),
         "geometry_map_step": (C.c_int, [vp, C.POINTER(psm_body), C.POINTER(vp), C.c_int, vp]),
         "psm_stream_collide": (C.c_int, [vp, C.POINTER(psm_body), C.c_int, i64, vp]),
+        "psm_step": (C.c_int, [vp, C.POINTER(psm_body), C.POINTER(psm_body), C.POINTER(vp), C.c_int, i64, vp, vp]),
         "body_force_torque": (C.c_int, [vp, C.c_int, vp, vp]),
         "psm_mass_fp64": (C.c_int, [vp, i64, vp, vp]),
         "psm_macroscopic": (C.c_int, [vp, i64, vp, vp, vp]),

@@ -57,10 +57,11 @@ class TorqueAdjoint:
         pu[0].W = (C.c_double * 3)(*[self.omega * a for a in self.body.motion.axis])
         return pm, pu
 
-    def _step(self, t):
+    def _step(self, t, ft=None):
         pm, pu = self._poses(t)
-        self.field.map(t, pm)
-        self.field.collide(t, pu)
+        f = self.field
+        check(lib.psm_step(f.handle, pm, pu, f._geom_ptrs, 1, int(t),
+                           C.c_void_p(ft.data_ptr()) if ft is not None else None, sim._stream()), "psm_step")
         return pu
 
     def _set_offset(self, dB):
@@ -80,8 +81,7 @@ class TorqueAdjoint:
         for t in range(self.steps):
             if t % self.L == 0:
                 self._ckpt[t] = self.field.pdf.clone()
-            self._step(t)
-            self.field.force_torque(out=self.ft[t:t + 1])
+            self._step(t, ft=self.ft[t])
         a = torch.tensor(list(self.body.motion.axis), dtype=torch.float64, device=self.device)
         w = torch.tensor(self.weights, dtype=torch.float64, device=self.device)
         return float((w * (self.ft[:, 3:] @ a)).sum().item())

@@ -9,9 +9,9 @@
 //
 // Cost control: a coarse map (one byte per 2^s-cube block of the geometry
 // lattice: all out / all in / mixed) classifies most cells exactly from the
-// <= 3x3x3 blocks their sub-samples can touch; only surface cells are sampled,
-// one cell at a time per wave64 with every lane taking sub-samples and a
-// ballot/popcount giving the count.
+// <= 3x3x3 blocks their sub-samples can touch; only surface cells are sampled:
+// for s >= 2 a wave64 takes several of its surface cells per round, every lane
+// taking sub-samples of each, and a ballot/popcount gives each count.
 #include "psm_internal.hpp"
 
 #pragma clang fp contract(off)
@@ -49,6 +49,71 @@ __device__ __forceinline__ int coarse_state(const MapBodyK &g, long long bx, lon
       (unsigned long long)jz >= (unsigned long long)g.cdims[2])
     return 0;
   return g.coarse[((size_t)jz * g.cdims[1] + (size_t)jy) * g.cdims[0] + (size_t)jx];
+}
+
+// Wave-cooperative sampling of the surface cells of a wave (s >= 2): the
+// (2^s)^3 = 64*NIT sub-samples of a cell are spread over the 64 lanes (NIT per
+// lane); NC cells are taken per round so that NC*NIT word loads per lane are
+// in flight before the ballots.  `mask` holds the lanes whose cell needs
+// sampling (wave-uniform); each such lane gets its count back.
+__device__ __forceinline__ long long lane_ll(long long v, int l) {
+  const int lo = __builtin_amdgcn_readlane((int)(unsigned long long)v, l);
+  const int hi = __builtin_amdgcn_readlane((int)((unsigned long long)v >> 32), l);
+  return (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
+template <int NIT, int NC>
+__device__ __forceinline__ int sample_cells(const MapBodyK &g, bool own_tab, const long long (*tab)[512],
+                                            unsigned long long mask, const long long P[3], int lane, int count) {
+  // this lane's rotated sub-sample offsets, fixed for the launch
+  long long D[NIT][3];
+#pragma unroll
+  for (int it = 0; it < NIT; ++it) {
+    const int k = it * 64 + lane;
+    if (own_tab) {
+      D[it][0] = tab[0][k];
+      D[it][1] = tab[1][k];
+      D[it][2] = tab[2][k];
+    } else {
+      sub_offset(g, k, D[it]);
+    }
+  }
+  while (mask) {
+    int ls[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      ls[c] = mask ? __ffsll((long long)mask) - 1 : -1;
+      mask &= mask - 1;
+    }
+    uint32_t word[NC][NIT];
+    int bit[NC][NIT];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const int l = ls[c] < 0 ? 0 : ls[c];
+      const long long Px = lane_ll(P[0], l), Py = lane_ll(P[1], l), Pz = lane_ll(P[2], l);
+#pragma unroll
+      for (int it = 0; it < NIT; ++it) {
+        word[c][it] = 0;
+        bit[c][it] = 0;
+        const long long jx = ((Px + D[it][0]) >> 32) - g.mmin[0], jy = ((Py + D[it][1]) >> 32) - g.mmin[1],
+                        jz = ((Pz + D[it][2]) >> 32) - g.mmin[2];
+        if (ls[c] >= 0 && (unsigned long long)jx < (unsigned long long)g.dims[0] &&
+            (unsigned long long)jy < (unsigned long long)g.dims[1] &&
+            (unsigned long long)jz < (unsigned long long)g.dims[2]) {
+          word[c][it] = g.bits[((size_t)jz * g.dims[1] + (size_t)jy) * g.wx + (size_t)(jx >> 5)];
+          bit[c][it] = (int)(jx & 31);
+        }
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      int n = 0;
+#pragma unroll
+      for (int it = 0; it < NIT; ++it) n += __popcll(__ballot((word[c][it] >> bit[c][it]) & 1u));
+      if (lane == ls[c]) count = n;
+    }
+  }
+  return count;
 }
 
 __device__ __forceinline__ bool in_box(const IBox &b, int x, int y, int z) {
@@ -139,46 +204,10 @@ __global__ __launch_bounds__(256) void k_map(const MapArgs a) {
         }
         count = c;
       }
+    } else if (s == 2) {
+      count = sample_cells<1, 16>(g, own_tab, tab, __ballot(state == 2), P, lane, count);
     } else {
-      unsigned long long mask = __ballot(state == 2);
-      const int nit = ns >> 6;  // 1 (s = 2) or 8 (s = 3) sub-samples per lane
-      while (mask) {
-        const int l = __ffsll((long long)mask) - 1;
-        mask &= mask - 1;
-        const long long Px = __shfl(P[0], l), Py = __shfl(P[1], l), Pz = __shfl(P[2], l);
-        // all of this lane's word loads first, then the ballots
-        uint32_t word[8];
-        int bit[8];
-#pragma unroll
-        for (int it = 0; it < 8; ++it) {
-          word[it] = 0;
-          bit[it] = 0;
-          if (it < nit) {
-            const int k = it * 64 + lane;
-            long long D[3];
-            if (own_tab) {
-              D[0] = tab[0][k];
-              D[1] = tab[1][k];
-              D[2] = tab[2][k];
-            } else {
-              sub_offset(g, k, D);
-            }
-            const long long jx = ((Px + D[0]) >> 32) - g.mmin[0], jy = ((Py + D[1]) >> 32) - g.mmin[1],
-                            jz = ((Pz + D[2]) >> 32) - g.mmin[2];
-            if ((unsigned long long)jx < (unsigned long long)g.dims[0] &&
-                (unsigned long long)jy < (unsigned long long)g.dims[1] &&
-                (unsigned long long)jz < (unsigned long long)g.dims[2]) {
-              word[it] = g.bits[((size_t)jz * g.dims[1] + (size_t)jy) * g.wx + (size_t)(jx >> 5)];
-              bit[it] = (int)(jx & 31);
-            }
-          }
-        }
-        int c = 0;
-#pragma unroll
-        for (int it = 0; it < 8; ++it)
-          if (it < nit) c += __popcll(__ballot((word[it] >> bit[it]) & 1u));
-        if (lane == l) count = c;
-      }
+      count = sample_cells<8, 4>(g, own_tab, tab, __ballot(state == 2), P, lane, count);
     }
     if (inb && count > 0) {
       float B;

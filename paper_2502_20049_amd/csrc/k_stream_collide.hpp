@@ -208,8 +208,12 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// Inlet term 6 w_k (c_k . u_in) of the velocity-inlet rule.  Not contracted
+// into the add that applies it, so every kernel (whatever its code shape)
+// rounds the face rule the same way.
 template <int Q, typename R>
 __device__ __forceinline__ R inlet_term(const SCArgs &a, int k) {
+#pragma clang fp contract(off)
   return R(6.0 * wt<Q>(k)) *
          (R(cx<Q>(k)) * (R)a.u_in_d[0] + R(cy<Q>(k)) * (R)a.u_in_d[1] + R(cz<Q>(k)) * (R)a.u_in_d[2]);
 }
@@ -261,9 +265,10 @@ __device__ __forceinline__ char *slot_general(const SCArgs &a, char *pdf, int k,
 }
 
 // Solid fraction of slot 0, plus the optional time-invariant offset field.
-__device__ __forceinline__ float solid_fraction(const SCArgs &a, uint64_t n) {
-  float b = a.B0[n];
-  if (a.dB) b += a.dB[n];
+template <typename R>
+__device__ __forceinline__ R solid_fraction(const SCArgs &a, uint64_t n) {
+  R b = (R)a.B0[n];
+  if (a.dB) b += (R)a.dB[n];
   return b;
 }
 
@@ -279,77 +284,131 @@ __device__ __forceinline__ bool boxes_touch(const SCArgs &a, int x0, int x1, int
 }
 
 // ---------------------------------------------------------------------------
-// Fluid cells of interior rows (1 <= y <= ny-2, 1 <= z <= nz-2).  Each
-// direction is one uniform 64-bit base plus a 32-bit lane offset chosen from
-// three (x-1, x, x+1, wrapped when x is periodic).  With a non-periodic x the
-// first and last cell of a row take the face rule for the five directions
-// whose source lies outside, in a divergent fix-up that only the two edge
-// waves of a row execute.  With PSM, cells whose B is nonzero are left to
-// the solid kernel.
+// Fluid cells (every row).  Each wave64 covers 64 consecutive x of one row,
+// so the row (y, z) is wave-uniform: every direction is one uniform 64-bit
+// row base plus a 32-bit lane offset chosen from three (x-1, x, x+1, wrapped
+// when x is periodic).  Rows inside the domain take the plain pattern; rows
+// on a y or z face (EDGE) wrap the source row and take the y/z face rules as
+// wave-uniform direction masks (selects, no branches).  Only the first and
+// last cell of a row with a non-periodic x take a per-lane fix-up for the x
+// faces.  With PSM, cells whose B is nonzero are left to the solid kernel.
 // ---------------------------------------------------------------------------
-template <int Q, typename T, int PAR, bool PSM, bool BIG>
-__global__ __launch_bounds__(256) void k_fluid(const SCArgs a) {
-  using R = typename Comp<T>::type;
-  using Off = typename std::conditional<BIG, uint64_t, uint32_t>::type;
-  constexpr Off S = sizeof(T);
-  const uint32_t tile = a.xcd_remap ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x;
-  const int tid = threadIdx.x;
-  const int txi = (int)(tile % (uint32_t)a.ntx);
-  const uint32_t rr = tile / (uint32_t)a.ntx;
-  const int tyi = (int)(rr % (uint32_t)a.nty_i);
-  const int z = 1 + (int)(rr / (uint32_t)a.nty_i);
-  const int x = txi * a.TX + (tid & (a.TX - 1));
-  const int y = 1 + tyi * a.TY + (tid >> a.lTX);
-  const int nx = a.nx, ny = a.ny;
-  bool active = (x < nx) && (y <= ny - 2);
-  const Off nxy = (Off)nx * (Off)ny;
-  const Off n = (Off)x + (Off)nx * (Off)y + nxy * (Off)z;
-  if constexpr (PSM) {
-    const int x0 = txi * a.TX, y0 = 1 + tyi * a.TY;
-    if (boxes_touch(a, x0, x0 + a.TX - 1, y0, y0 + a.TY - 1, z, z)) {
-      if (active && solid_fraction(a, n) != 0.0f) active = false;
-    }
+
+// Directions k with c_k[axis] == sgn (the directions whose source lies
+// outside the face on the -sgn side of that axis).
+template <int Q>
+__host__ __device__ constexpr uint32_t dirs_with(int axis, int sgn) {
+  uint32_t m = 0;
+  for (int k = 0; k < Q; ++k) {
+    const int c = axis == 0 ? cx<Q>(k) : (axis == 1 ? cy<Q>(k) : cz<Q>(k));
+    if (c == sgn) m |= 1u << k;
   }
-  if (!active) return;
+  return m;
+}
+
+// Face rules as direction masks: a face that is on adds its directions to the
+// mask of its kind.  Resolution (wall > inlet > outlet) happens in FaceMask.
+struct FaceAcc {
+  uint32_t w = 0, i = 0, o = 0;
+  __device__ __forceinline__ void add(bool on, int kind, uint32_t dirs) {
+    const uint32_t m = on ? dirs : 0u;
+    w |= kind == K_WALL ? m : 0u;
+    i |= kind == K_INLET ? m : 0u;
+    o |= kind == K_OUTLET ? m : 0u;
+  }
+  // own slot / inlet term / outlet rule, per direction
+  __device__ __forceinline__ uint32_t own() const { return w | i | o; }
+  __device__ __forceinline__ uint32_t inlet() const { return i & ~w; }
+  __device__ __forceinline__ uint32_t outlet() const { return o & ~(w | i); }
+};
+
+template <int Q, typename T, int PAR, bool EDGE>
+__device__ __forceinline__ void fluid_row_cell(const SCArgs &a, int x, int y, int z, size_t rowbase) {
+  using R = typename Comp<T>::type;
+  constexpr uint32_t S = sizeof(T);
+  const int nx = a.nx, ny = a.ny, nz = a.nz;
+  const size_t nxy = (size_t)nx * (size_t)ny;
   const bool xper = a.periodic[0] != 0;
-  const bool lo_face = !xper && x == 0;        // sources x-1 are outside (face -x)
-  const bool hi_face = !xper && x == nx - 1;   // sources x+1 are outside (face +x)
-  char *const A = a.pdf;
-  const size_t NS = (size_t)a.N * S;
-  const Off rb = n - (Off)x;
+  const bool lo_face = !xper && x == 0;       // sources x-1 are outside (face -x)
+  const bool hi_face = !xper && x == nx - 1;  // sources x+1 are outside (face +x)
+  const bool xface = lo_face || hi_face;
   int xm = x - 1, xp = x + 1;
   if (xm < 0) xm = xper ? xm + nx : 0;
   if (xp >= nx) xp = xper ? xp - nx : nx - 1;
-  const Off o0 = n * S, om = (rb + (Off)xm) * S, op = (rb + (Off)xp) * S;
-  auto addr = [&](auto K) -> char * {
+  uint32_t o0 = (uint32_t)x * S, om = (uint32_t)xm * S, op = (uint32_t)xp * S;
+  char *const A = a.pdf;
+  const size_t NS = (size_t)a.N * S;
+  char *const own_row = A + rowbase * S;
+  // y/z face rules of this row (wave-uniform)
+  FaceAcc yz;
+  if constexpr (EDGE) {
+    const bool py = a.periodic[1] != 0, pz = a.periodic[2] != 0;
+    yz.add(!py && y == 0, a.bc[2], dirs_with<Q>(1, 1));
+    yz.add(!py && y == ny - 1, a.bc[3], dirs_with<Q>(1, -1));
+    yz.add(!pz && z == 0, a.bc[4], dirs_with<Q>(2, 1));
+    yz.add(!pz && z == nz - 1, a.bc[5], dirs_with<Q>(2, -1));
+  }
+  const uint32_t own_m = yz.own(), in_m = yz.inlet(), out_m = yz.outlet();
+  auto own = [&](auto K) -> char * { return own_row + (size_t)(int)K * NS + o0; };
+  // odd parity, no face: slot kbar of the source cell x - c_k, as a
+  // wave-uniform row base and a 32-bit lane offset
+  auto src_base = [&](auto K) -> char * {
     constexpr int k = K;
-    if constexpr (PAR == 0) {
-      return A + (size_t)k * NS + (size_t)o0;
+    constexpr int ey = cy<Q>(k), ez = cz<Q>(k);
+    char *row;
+    if constexpr (!EDGE) {
+      row = own_row - ((long long)ey * nx + (long long)ez * (long long)nxy) * (long long)S;
     } else {
-      constexpr int ex = cx<Q>(k), ey = cy<Q>(k), ez = cz<Q>(k);
-      const long long rowoff = (long long)ey * nx + (long long)ez * (long long)nxy;
-      char *base = A + (size_t)opp<Q>(k) * NS - rowoff * (long long)S;
-      const Off lo = ex == 1 ? om : (ex == -1 ? op : o0);
-      return base + (size_t)lo;
+      int sy = y - ey, sz = z - ez;
+      if (sy < 0) sy += ny;
+      if (sy >= ny) sy -= ny;
+      if (sz < 0) sz += nz;
+      if (sz >= nz) sz -= nz;
+      row = A + ((size_t)nx * (size_t)sy + nxy * (size_t)sz) * S;
     }
+    return row + (size_t)opp<Q>(k) * NS;
   };
-  auto own = [&](auto K) -> char * { return A + (size_t)(int)K * NS + (size_t)o0; };
+  auto src_lane = [&](auto K) -> uint32_t {
+    constexpr int ex = cx<Q>(K);
+    return ex == 1 ? om : (ex == -1 ? op : o0);
+  };
+  // slot of direction k: own slot at even parity or where the face mask has
+  // k, else the source slot.  Base and lane offset are selected separately
+  // (both candidates formed first, so the choice is a select): with a
+  // wave-uniform mask the base stays scalar.
+  auto slot = [&](auto K, uint32_t ownmask) -> char * {
+    if constexpr (PAR == 0) return own(K);
+    char *const bo = own_row + (size_t)(int)K * NS;
+    char *const bs = src_base(K);
+    const uint32_t ls = src_lane(K);
+    const bool fc = (ownmask >> (int)K) & 1u;
+    return (fc ? bo : bs) + (fc ? o0 : ls);
+  };
+  auto inlet_if = [&](auto K, uint32_t inmask) -> R {
+    const R t = inlet_term<Q, R>(a, (int)K);
+    return ((inmask >> (int)K) & 1u) ? t : R(0);
+  };
   R f[Q];
-  sfor<Q>([&](auto K) { f[K] = ldv<T, R>(addr(K)); });
-  const bool xface = lo_face || hi_face;
-  int kind_lo = K_NONE, kind_hi = K_NONE;
+  sfor<Q>([&](auto K) {
+    constexpr int k = K;
+    R v = ldv<T, R>(slot(K, own_m));
+    if constexpr (PAR == 1 && EDGE) v += inlet_if(K, in_m);
+    f[k] = v;
+  });
+  FaceAcc all = yz;
   if (xface) {
-    kind_lo = lo_face ? a.bc[0] : K_NONE;
-    kind_hi = hi_face ? a.bc[1] : K_NONE;
+    all.add(lo_face, a.bc[0], dirs_with<Q>(0, 1));
+    all.add(hi_face, a.bc[1], dirs_with<Q>(0, -1));
     if constexpr (PAR == 1) {
-      // odd parity: incoming directions from outside read the cell's own slot
+      // odd parity: directions whose rule the x faces change re-read the
+      // cell's own slot
+      const uint32_t own_x = all.own(), in_x = all.inlet();
+      const uint32_t redo = (own_x ^ own_m) | (in_x ^ in_m);
       sfor<Q>([&](auto K) {
         constexpr int k = K;
-        constexpr int ex = cx<Q>(k);
-        const int kd = ex == 1 ? kind_lo : (ex == -1 ? kind_hi : K_NONE);
-        if (kd != K_NONE) {
+        if ((redo >> k) & 1u) {
           R v = ldv<T, R>(own(K));
-          if (kd == K_INLET) v += inlet_term<Q, R>(a, k);
+          if ((in_x >> k) & 1u) v += inlet_term<Q, R>(a, k);
           f[k] = v;
         }
       });
@@ -357,32 +416,75 @@ __global__ __launch_bounds__(256) void k_fluid(const SCArgs a) {
   }
   R z3[3] = {0, 0, 0}, m0[3] = {0, 0, 0}, m1[3] = {0, 0, 0};
   collide<Q, 1, 0, R>(f, a, R(0), z3, R(0), z3, m0, m1);
+  auto put = [&](auto K, uint32_t ownmask, uint32_t inmask, uint32_t outmask) {
+    constexpr int k = K;
+    R v = ((outmask >> k) & 1u) ? f[k] : f[opp<Q>(k)];
+    if constexpr (PAR == 1) v += inlet_if(K, inmask);
+    stv<T, R>(slot(K, ownmask), v);
+  };
   if (!xface) {
-    sfor<Q>([&](auto K) { stv<T, R>(addr(K), f[opp<Q>(K)]); });
+    // fresh lane offsets: the store addresses are formed again from the
+    // scalar bases (saddr form) instead of keeping the loads' 64-bit
+    // addresses live across the collision
+    uint32_t r0 = o0, rm = om, rp = op;
+    asm volatile("" : "+v"(r0), "+v"(rm), "+v"(rp));
+    o0 = r0;
+    om = rm;
+    op = rp;
+    sfor<Q>([&](auto K) { put(K, own_m, in_m, out_m); });
   } else {
-    sfor<Q>([&](auto K) {
-      constexpr int k = K;
-      constexpr int ex = cx<Q>(k);
-      const int kd = ex == 1 ? kind_lo : (ex == -1 ? kind_hi : K_NONE);
-      if (kd == K_NONE) {
-        stv<T, R>(addr(K), f[opp<Q>(k)]);
-      } else {
-        R v = kd == K_OUTLET ? f[k] : f[opp<Q>(k)];
-        if constexpr (PAR == 1) {
-          if (kd == K_INLET) v += inlet_term<Q, R>(a, k);
-        }
-        stv<T, R>(own(K), v);
-      }
-    });
+    const uint32_t own_x = all.own(), in_x = all.inlet(), out_x = all.outlet();
+    sfor<Q>([&](auto K) { put(K, own_x, in_x, out_x); });
   }
 }
 
-// ---------------------------------------------------------------------------
-// Fluid cells on the rows with y or z on a domain face (coalesced along x).
-// Full face handling.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ void face_row_yz(const SCArgs &a, int r, int &y, int &z) {
-  // planes z = 0 (and z = nz-1), then rows y = 0 (and y = ny-1) of the others
+// A wave's cell: skip lanes past the row end and, with PSM, cells whose B is
+// nonzero (those belong to the solid kernel).
+template <typename R, bool PSM>
+__device__ __forceinline__ bool fluid_lane(const SCArgs &a, int x, int y, int z, size_t rowbase) {
+  if (x >= a.nx) return false;
+  if constexpr (PSM) {
+    const int x0 = x & ~(a.TX - 1);
+    if (boxes_touch(a, x0, x0 + a.TX - 1, y, y, z, z) && solid_fraction<R>(a, rowbase + (size_t)x) != R(0))
+      return false;
+  }
+  return true;
+}
+
+// Interior rows (1 <= y <= ny-2, 1 <= z <= nz-2), TY rows of TX cells per block.
+template <int Q, typename T, int PAR, bool PSM>
+__global__ __launch_bounds__(256) void k_fluid(const SCArgs a) {
+  const int tid = threadIdx.x;
+  int txi, tyi, z;
+  if (a.fsel == 2) {  // grid = the near range
+    uint32_t b = blockIdx.x;
+    txi = a.near_lo[0] + (int)(b % (uint32_t)a.near_n[0]);
+    b /= (uint32_t)a.near_n[0];
+    tyi = a.near_lo[1] + (int)(b % (uint32_t)a.near_n[1]);
+    z = 1 + a.near_lo[2] + (int)(b / (uint32_t)a.near_n[1]);
+  } else {
+    const uint32_t tile = a.xcd_remap ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x;
+    txi = (int)(tile % (uint32_t)a.ntx);
+    const uint32_t rr = tile / (uint32_t)a.ntx;
+    tyi = (int)(rr % (uint32_t)a.nty_i);
+    z = 1 + (int)(rr / (uint32_t)a.nty_i);
+    if (a.fsel == 1 && (unsigned)(txi - a.near_lo[0]) < (unsigned)a.near_n[0] &&
+        (unsigned)(tyi - a.near_lo[1]) < (unsigned)a.near_n[1] &&
+        (unsigned)(z - 1 - a.near_lo[2]) < (unsigned)a.near_n[2])
+      return;
+  }
+  const int x = txi * a.TX + (tid & (a.TX - 1));
+  // TX >= 64: the row is the same over the wave
+  const int y = __builtin_amdgcn_readfirstlane(1 + tyi * a.TY + (tid >> a.lTX));
+  if (y > a.ny - 2) return;
+  const size_t rowbase = (size_t)a.nx * (size_t)y + (size_t)a.nx * (size_t)a.ny * (size_t)z;
+  if (!fluid_lane<typename Comp<T>::type, PSM>(a, x, y, z, rowbase)) return;
+  fluid_row_cell<Q, T, PAR, false>(a, x, y, z, rowbase);
+}
+
+// Row r of the rows on a y or z face: the planes z = 0 and z = nz-1, then the
+// rows y = 0 and y = ny-1 of the other planes (each row once).
+__device__ __forceinline__ void edge_row_yz(const SCArgs &a, int r, int &y, int &z) {
   const int ny = a.ny, nz = a.nz;
   const int nzp = nz >= 2 ? 2 : 1;
   if (r < nzp * ny) {
@@ -396,25 +498,36 @@ __device__ __forceinline__ void face_row_yz(const SCArgs &a, int r, int &y, int 
   y = (r2 % nyp) ? ny - 1 : 0;
 }
 
+// Rows on a y or z face, TY rows (of the list above) of TX cells per block.
 template <int Q, typename T, int PAR, bool PSM>
-__global__ __launch_bounds__(256) void k_fluid_face(const SCArgs a) {
+__global__ __launch_bounds__(256) void k_fluid_edge(const SCArgs a) {
+  const int tid = threadIdx.x;
+  const int txi = (int)(blockIdx.x % (uint32_t)a.ntx);
+  const int r = __builtin_amdgcn_readfirstlane((int)(blockIdx.x / (uint32_t)a.ntx) * a.TY + (tid >> a.lTX));
+  if (r >= a.nfrows) return;
+  int y, z;
+  edge_row_yz(a, r, y, z);
+  const int x = txi * a.TX + (tid & (a.TX - 1));
+  const size_t rowbase = (size_t)a.nx * (size_t)y + (size_t)a.nx * (size_t)a.ny * (size_t)z;
+  if (!fluid_lane<typename Comp<T>::type, PSM>(a, x, y, z, rowbase)) return;
+  fluid_row_cell<Q, T, PAR, true>(a, x, y, z, rowbase);
+}
+
+// ---------------------------------------------------------------------------
+// Fluid cells with the general per-lane face handling, one thread per cell in
+// linear order (the cross-check path of PSM_OPT_GENERAL_PATH).
+// ---------------------------------------------------------------------------
+template <int Q, typename T, int PAR, bool PSM>
+__global__ __launch_bounds__(256) void k_fluid_general(const SCArgs a) {
   using R = typename Comp<T>::type;
   const uint64_t i = (uint64_t)blockIdx.x * 256u + threadIdx.x;
-  if (i >= a.nface) return;
-  int x, y, z;
-  const uint64_t nrc = (uint64_t)a.nfrows * (uint64_t)a.nx;
-  if (a.face_all) {
-    x = (int)(i % (uint64_t)a.nx);
-    y = (int)((i / (uint64_t)a.nx) % (uint64_t)a.ny);
-    z = (int)(i / ((uint64_t)a.nx * (uint64_t)a.ny));
-  } else {
-    (void)nrc;
-    face_row_yz(a, (int)(i / (uint64_t)a.nx), y, z);
-    x = (int)(i % (uint64_t)a.nx);
-  }
+  if (i >= (uint64_t)a.N) return;
+  const int x = (int)(i % (uint64_t)a.nx);
+  const int y = (int)((i / (uint64_t)a.nx) % (uint64_t)a.ny);
+  const int z = (int)(i / ((uint64_t)a.nx * (uint64_t)a.ny));
   const uint64_t n = (uint64_t)x + (uint64_t)a.nx * ((uint64_t)y + (uint64_t)a.ny * (uint64_t)z);
   if constexpr (PSM) {
-    if (boxes_touch(a, x, x, y, y, z, z) && solid_fraction(a, n) != 0.0f) return;
+    if (boxes_touch(a, x, x, y, y, z, z) && solid_fraction<R>(a, n) != R(0)) return;
   }
   uint32_t bcm, outm, inm;
   classify<Q>(a, x, y, z, bcm, outm, inm);
@@ -473,7 +586,7 @@ __global__ __launch_bounds__(256) void k_solid(const SCArgs a) {
     int b0 = 0, b1 = 0;
     bool two = false;
     if (act) {
-      B0 = (R)solid_fraction(a, n);
+      B0 = solid_fraction<R>(a, n);
       act = B0 != R(0);
     }
     if (act) {

@@ -21,9 +21,9 @@ int hip_fail(hipError_t e, const char *what) {
 }
 
 hipError_t launch_adjoint(const psm_field &f, const AdjArgs &A, hipStream_t st);
-hipError_t launch_sc_f64(const psm_config &, const SCArgs &, int, bool, hipStream_t, int *);
-hipError_t launch_sc_f32(const psm_config &, const SCArgs &, int, bool, hipStream_t, int *);
-hipError_t launch_sc_f16(const psm_config &, const SCArgs &, int, bool, hipStream_t, int *);
+hipError_t launch_sc_f64(const psm_config &, const SCArgs &, int, int, hipStream_t, int *);
+hipError_t launch_sc_f32(const psm_config &, const SCArgs &, int, int, hipStream_t, int *);
+hipError_t launch_sc_f16(const psm_config &, const SCArgs &, int, int, hipStream_t, int *);
 
 static size_t storage_size(int st) { return st == PSM_F64 ? 8 : (st == PSM_F32 ? 4 : 2); }
 
@@ -112,9 +112,8 @@ SCArgs make_sc_args(const psm_field &f) {
   a.ntiles_i = interior ? (uint32_t)((int64_t)f.ntx * a.nty_i * (c.nz - 2)) : 0u;
   const int nzp = c.nz >= 2 ? 2 : 1, nyp = c.ny >= 2 ? 2 : 1;
   a.nfrows = nzp * c.ny + (c.nz > 2 ? (c.nz - 2) * nyp : 0);
-  a.nface = (uint64_t)a.nfrows * c.nx;
-  a.face_all = f.opt_general_path;
-  if (a.face_all) a.nface = (uint64_t)f.N;
+  a.ntiles_e = (uint32_t)((int64_t)f.ntx * ((a.nfrows + f.TY - 1) / f.TY));
+  a.general = f.opt_general_path;
   for (int i = 0; i < 6; ++i) a.bc[i] = c.bc[i];
   for (int d = 0; d < 3; ++d) {
     a.periodic[d] = c.bc[2 * d] == PSM_PERIODIC;
@@ -270,13 +269,31 @@ int pdf_field_create(const psm_config *cfg, void *pdf, size_t pdf_bytes, void *b
   f->ntiles = L.ntiles;
   for (int i = 0; i < PSM_MAX_BODIES; ++i) f->active[i] = empty_box();
   f->opt_xcd_remap = 0;
+  f->opt_overlap = 0;
   if (hipGetDevice(&f->device) != hipSuccess) f->device = -1;
+  if (cfg->psm) {
+    hipError_t e = hipStreamCreateWithFlags(&f->side, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&f->ev_prev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&f->ev_map, hipEventDisableTiming);
+    if (e != hipSuccess) {
+      if (f->ev_prev) (void)hipEventDestroy(f->ev_prev);
+      if (f->side) (void)hipStreamDestroy(f->side);
+      delete f;
+      return hip_fail(e, "pdf_field_create: stream/event");
+    }
+  }
   *out = f;
   return PSM_OK;
 }
 
 int pdf_field_destroy(psm_field *f) {
   if (!f) return set_error("null handle"), PSM_EINVAL;
+  if (f->side) {
+    (void)hipStreamSynchronize(f->side);
+    (void)hipStreamDestroy(f->side);
+  }
+  if (f->ev_prev) (void)hipEventDestroy(f->ev_prev);
+  if (f->ev_map) (void)hipEventDestroy(f->ev_map);
   delete f;
   return PSM_OK;
 }
@@ -452,14 +469,24 @@ static int check_bodies(const psm_field *f, const psm_body *bodies, int nb) {
   return PSM_OK;
 }
 
-int geometry_map_step(psm_field *f, const psm_body *bodies, const psm_geom *const *geoms, int nb, void *stream) {
+// Host side of the mapping: the swept region of every body at its pose (a
+// cell [i, i+1] meets [lo, hi] iff floor(lo) <= i < hi; one cell of margin)
+// and the kernel arguments.
+struct MapPlan {
+  MapArgs a;
+  uint32_t maxcells;
+  IBox now[PSM_MAX_BODIES];
+  int nb;
+};
+
+static int map_plan(psm_field *f, const psm_body *bodies, const psm_geom *const *geoms, int nb, MapPlan &P) {
   int r = check_bodies(f, bodies, nb);
   if (r) return r;
   if (!f->cfg.psm) return set_error("geometry_map_step on a plain-LBM field"), PSM_EINVAL;
   if (nb > 0 && !geoms) return set_error("null geometry list"), PSM_EINVAL;
   if (f->nb_mapped && nb != f->nb_mapped)
     return set_error("the number of bodies changed; reset the field first"), PSM_EINVAL;
-  MapArgs a;
+  MapArgs &a = P.a;
   memset(&a, 0, sizeof(a));
   a.B0 = f->B0;
   a.B1 = f->B1;
@@ -473,7 +500,7 @@ int geometry_map_step(psm_field *f, const psm_body *bodies, const psm_geom *cons
   a.b_form = f->cfg.b_form;
   a.tau = f->cfg.tau;
   uint32_t maxcells = 0;
-  IBox now[PSM_MAX_BODIES];
+  IBox *now = P.now;
   const int n3[3] = {f->cfg.nx, f->cfg.ny, f->cfg.nz};
   for (int b = 0; b < nb; ++b) {
     const psm_geom *g = geoms[b];
@@ -537,23 +564,26 @@ int geometry_map_step(psm_field *f, const psm_body *bodies, const psm_geom *cons
     }
     maxcells = std::max(maxcells, m.region_cells);
   }
-  hipError_t e = launch_map(a, maxcells, 0, (hipStream_t)stream);
-  if (e != hipSuccess) return hip_fail(e, "geometry_map_step launch");
-  for (int b = 0; b < nb; ++b) {
-    f->active[b] = now[b];
-    f->have_prev[b] = true;
-  }
-  f->nb_mapped = nb;
+  P.maxcells = maxcells;
+  P.nb = nb;
   return PSM_OK;
 }
 
-int psm_stream_collide(psm_field *f, const psm_body *bodies, int nb, int64_t step, void *stream) {
+static void map_commit(psm_field *f, const MapPlan &P) {
+  for (int b = 0; b < P.nb; ++b) {
+    f->active[b] = P.now[b];
+    f->have_prev[b] = true;
+  }
+  f->nb_mapped = P.nb;
+}
+
+// Host side of a stream-collide step: per-body kinematics, the boxes outside
+// which B is zero and the solid kernel's chunk offsets over them.
+static int sc_plan(psm_field *f, const psm_body *bodies, int nb, int64_t step, const IBox *boxes, SCArgs &a) {
   int r = check_bodies(f, bodies, nb);
   if (r) return r;
   if (step < 0) return set_error("negative step"), PSM_EINVAL;
-  if (f->cfg.psm && nb > 0 && nb != f->nb_mapped)
-    return set_error("psm_stream_collide: bodies do not match the mapped field"), PSM_EINVAL;
-  SCArgs a = make_sc_args(*f);
+  a = make_sc_args(*f);
   a.nb = f->cfg.psm ? nb : 0;
   uint32_t chunks = 0;
   for (int b = 0; b < a.nb; ++b) {
@@ -564,7 +594,7 @@ int psm_stream_collide(psm_field *f, const psm_body *bodies, int nb, int64_t ste
       k.W[d] = bodies[b].W[d];
     }
     // B is zero outside the mapped boxes; the solid kernel walks them
-    const IBox &B = f->active[b];
+    const IBox &B = boxes[b];
     a.box[b] = B;
     a.cprefix[b] = chunks;
     if (!box_empty(B)) {
@@ -591,17 +621,133 @@ int psm_stream_collide(psm_field *f, const psm_body *bodies, int nb, int64_t ste
     a.nchunks = whole;
   }
   a.xcd_remap = f->opt_xcd_remap;
+  return PSM_OK;
+}
+
+static int sc_launch(psm_field *f, const SCArgs &a, int64_t step, int phase, hipStream_t st) {
   const int parity = (int)(step & 1);
-  const bool big = (uint64_t)f->N * storage_size(f->cfg.storage) > 0xFFFFFFFFull;
   hipError_t e;
   int sb = 0;
   switch (f->cfg.storage) {
-    case PSM_F64: e = launch_sc_f64(f->cfg, a, parity, big, (hipStream_t)stream, &sb); break;
-    case PSM_F32: e = launch_sc_f32(f->cfg, a, parity, big, (hipStream_t)stream, &sb); break;
-    default: e = launch_sc_f16(f->cfg, a, parity, big, (hipStream_t)stream, &sb); break;
+    case PSM_F64: e = launch_sc_f64(f->cfg, a, parity, phase, st, &sb); break;
+    case PSM_F32: e = launch_sc_f32(f->cfg, a, parity, phase, st, &sb); break;
+    default: e = launch_sc_f16(f->cfg, a, parity, phase, st, &sb); break;
   }
   if (e != hipSuccess) return hip_fail(e, "psm_stream_collide launch");
-  f->solid_blocks = sb;
+  if (phase != 1) f->solid_blocks = sb;
+  return PSM_OK;
+}
+
+// Interior tiles (tile x, tile row, z-1) that touch any body box: their
+// bounding range.  Tiles outside it never read B.
+static void near_range(const psm_field &f, SCArgs &a) {
+  int lo[3] = {INT32_MAX, INT32_MAX, INT32_MAX}, hi[3] = {-1, -1, -1};
+  bool any = false;
+  for (int b = 0; b < a.nbox; ++b) {
+    const IBox &B = a.box[b];
+    if (box_empty(B)) continue;
+    const int ylo = std::max(B.lo[1], 1), yhi = std::min(B.hi[1], f.cfg.ny - 2);
+    const int zlo = std::max(B.lo[2], 1), zhi = std::min(B.hi[2], f.cfg.nz - 2);
+    if (ylo > yhi || zlo > zhi) continue;
+    any = true;
+    lo[0] = std::min(lo[0], B.lo[0] / f.TX);
+    hi[0] = std::max(hi[0], B.hi[0] / f.TX);
+    lo[1] = std::min(lo[1], (ylo - 1) / f.TY);
+    hi[1] = std::max(hi[1], (yhi - 1) / f.TY);
+    lo[2] = std::min(lo[2], zlo - 1);
+    hi[2] = std::max(hi[2], zhi - 1);
+  }
+  if (!any) {
+    for (int d = 0; d < 3; ++d) a.near_lo[d] = a.near_n[d] = 0;
+    a.near_tiles = 0;
+    return;
+  }
+  for (int d = 0; d < 3; ++d) {
+    a.near_lo[d] = lo[d];
+    a.near_n[d] = hi[d] - lo[d] + 1;
+  }
+  a.near_tiles = (uint32_t)a.near_n[0] * (uint32_t)a.near_n[1] * (uint32_t)a.near_n[2];
+}
+
+int geometry_map_step(psm_field *f, const psm_body *bodies, const psm_geom *const *geoms, int nb, void *stream) {
+  MapPlan P;
+  int r = map_plan(f, bodies, geoms, nb, P);
+  if (r) return r;
+  hipError_t e = launch_map(P.a, P.maxcells, 0, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "geometry_map_step launch");
+  map_commit(f, P);
+  return PSM_OK;
+}
+
+int psm_stream_collide(psm_field *f, const psm_body *bodies, int nb, int64_t step, void *stream) {
+  if (!f) return set_error("null handle"), PSM_EINVAL;
+  if (f->cfg.psm && nb > 0 && nb != f->nb_mapped)
+    return set_error("psm_stream_collide: bodies do not match the mapped field"), PSM_EINVAL;
+  SCArgs a;
+  int r = sc_plan(f, bodies, nb, step, f->active, a);
+  if (r) return r;
+  return sc_launch(f, a, step, 0, (hipStream_t)stream);
+}
+
+int psm_step(psm_field *f, const psm_body *map_poses, const psm_body *bodies, const psm_geom *const *geoms, int nb,
+             int64_t step, double *ft_dev, void *stream) {
+  if (!f) return set_error("null handle"), PSM_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  if (!f->cfg.psm || nb == 0) {
+    if (ft_dev) return set_error("psm_step: force/torque needs bodies"), PSM_EINVAL;
+    return psm_stream_collide(f, bodies, nb, step, stream);
+  }
+  if (!map_poses) map_poses = bodies;
+  if (f->opt_general_path || f->opt_whole_domain || !f->side) {
+    int r = geometry_map_step(f, map_poses, geoms, nb, stream);
+    if (!r) r = psm_stream_collide(f, bodies, nb, step, stream);
+    if (!r && ft_dev) r = body_force_torque(f, nb, ft_dev, stream);
+    return r;
+  }
+  MapPlan P;
+  int r = map_plan(f, map_poses, geoms, nb, P);
+  if (r) return r;
+  SCArgs a;
+  r = sc_plan(f, bodies, nb, step, P.now, a);
+  if (r) return r;
+  near_range(*f, a);
+  hipError_t e = hipSuccess;
+  if (f->opt_overlap == 1) {
+    // the mapping follows the previous step directly on the caller's stream,
+    // so its workgroups are resident first; the tiles that need no B run on
+    // the field's stream after an event that marks the end of the previous
+    // step (which still reads B)
+    e = hipEventRecord(f->ev_prev, st);
+    if (e == hipSuccess) e = hipStreamWaitEvent(f->side, f->ev_prev, 0);
+    if (e != hipSuccess) return hip_fail(e, "psm_step: event");
+    r = sc_launch(f, a, step, 1, f->side);
+    if (r) return r;
+    e = hipEventRecord(f->ev_map, f->side);
+    if (e == hipSuccess) e = launch_map(P.a, P.maxcells, 0, st);
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, f->ev_map, 0);
+  } else if (f->opt_overlap == 2) {
+    // the other way round: the mapping on the field's stream
+    e = hipEventRecord(f->ev_prev, st);
+    if (e != hipSuccess) return hip_fail(e, "psm_step: event");
+    r = sc_launch(f, a, step, 1, st);
+    if (r) return r;
+    e = hipStreamWaitEvent(f->side, f->ev_prev, 0);
+    if (e == hipSuccess) e = launch_map(P.a, P.maxcells, 0, f->side);
+    if (e == hipSuccess) e = hipEventRecord(f->ev_map, f->side);
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, f->ev_map, 0);
+  } else {
+    // no overlap: mapping, then the tiles away from the bodies
+    e = launch_map(P.a, P.maxcells, 0, st);
+    if (e == hipSuccess) {
+      r = sc_launch(f, a, step, 1, st);
+      if (r) return r;
+    }
+  }
+  if (e != hipSuccess) return hip_fail(e, "psm_step: mapping");
+  map_commit(f, P);
+  r = sc_launch(f, a, step, 2, st);
+  if (r) return r;
+  if (ft_dev) return body_force_torque(f, nb, ft_dev, stream);
   return PSM_OK;
 }
 
@@ -634,6 +780,10 @@ int psm_set_option(psm_field *f, int option, int value) {
   switch (option) {
     case PSM_OPT_GENERAL_PATH: f->opt_general_path = value ? 1 : 0; return PSM_OK;
     case PSM_OPT_XCD_REMAP: f->opt_xcd_remap = value ? 1 : 0; return PSM_OK;
+    case PSM_OPT_OVERLAP:
+      if (value < 0 || value > 2) return set_error("PSM_OPT_OVERLAP takes 0, 1 or 2"), PSM_EINVAL;
+      f->opt_overlap = value;
+      return PSM_OK;
   }
   return set_error("unknown option"), PSM_EINVAL;
 }

@@ -405,6 +405,16 @@ def workload_cror(nx=768, ny=384, nz=384, storage="f32", steps=1000, radius=120.
                     1, 0, 1, steps, bodies)
 
 
+def workload_rotor_box(n=256, storage="f32", steps=1000, radius=120.0, s=2, n_chord=60, n_span=60):
+    """One 8-blade rotor of radius 120 filling an n^3 box (the rotor-heavy
+    scenario beside the small-body channel), D3Q19, inflow 0.05 along x."""
+    c = n / 2
+    bodies = cror_rotors(radius, 8, 0.42 * radius, n_chord, n_span, 3, [(c, c, c)], [2e-3], s=s)
+    return Workload(f"rotor_box_{n}^3_d3q19", n, n, n, 19, storage, 0.8, 3 / 16, (0, 0, 0),
+                    ("inlet", "outlet", "periodic", "periodic", "periodic", "periodic"), (0.05, 0, 0),
+                    1, 0, 1, steps, bodies)
+
+
 def workload_adjoint_rotor(n=128, steps=800, radius=40.0, s=2, n_chord=50, n_span=50, storage="f32"):
     """Single 4-blade rotor in an n^3 box, inflow 0.04 along x, periodic y, z."""
     c = n / 2

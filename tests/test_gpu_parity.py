@@ -137,6 +137,40 @@ def test_fast_path_bitwise_equals_general_path(orc, sim, gc, storage):
     assert torch.equal(res[0], res[1])
 
 
+@pytest.mark.parametrize("case", ["two_bodies_mixed", "channel_96", "plain_static"])
+def test_psm_step_equals_separate_calls(sim, gc, case):
+    """psm_step (mapping on the field's second stream beside the tiles away
+    from the bodies) against geometry_map_step + psm_stream_collide +
+    body_force_torque in order: bit-identical PDFs, fractions and F/T."""
+    import torch
+
+    _say(f"[psm_step] {case}")
+    if case == "two_bodies_mixed":
+        wl, steps = _workload(19, "f32", "mixed", two=True, nx=96, ny=40, nz=36), 6
+    elif case == "channel_96":
+        wl, steps = pi.workload_ellipsoid_channel(n=96, storage="f32", steps=8, scale=0.4, s=2), 8
+        wl.bodies[0].motion.omega = 0.02
+    else:
+        wl, steps = pi.workload_sphere32(storage="f32"), 4
+    res = []
+    for mode in (None, 0, 1, 2):  # None: separate calls; else the psm_step schedule
+        f = sim.Field(wl, overlap=mode is not None, remap_every_step=case != "plain_static")
+        if mode is not None:
+            f.set_option(3, mode)
+        gc.load_random_state(f, 11)
+        fts = []
+        for t in range(steps):
+            ft = torch.zeros((max(1, f.nb), 6), dtype=torch.float64, device="cuda")
+            f.step(t, ft=ft)
+            fts.append(ft)
+        torch.cuda.synchronize()
+        B, meta = f.b_view()
+        res.append((f.pdf_view().clone(), B.clone(), meta.clone(), torch.stack(fts)))
+    for other in res[1:]:
+        for a, b in zip(res[0], other):
+            assert torch.equal(a, b)
+
+
 def test_xcd_remap_bitwise_identical(sim, gc):
     import torch
 
