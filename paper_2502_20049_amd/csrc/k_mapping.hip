@@ -65,19 +65,31 @@ __device__ __forceinline__ long long lane_ll(long long v, int l) {
 template <int NIT, int NC>
 __device__ __forceinline__ int sample_cells(const MapBodyK &g, bool own_tab, const long long (*tab)[512],
                                             unsigned long long mask, const long long P[3], int lane, int count) {
-  // this lane's rotated sub-sample offsets, fixed for the launch
-  long long D[NIT][3];
+  // This lane's rotated sub-sample offsets, fixed for the launch, split into
+  // a signed high word and an unsigned low word: with P = Ph 2^32 + Pl, the
+  // lattice index floor((P + D) / 2^32) is Ph + Dh + carry(Pl + Dl), exact in
+  // 32-bit arithmetic (indices are far below 2^31).
+  int Dh[NIT][3];
+  uint32_t Dl[NIT][3];
 #pragma unroll
   for (int it = 0; it < NIT; ++it) {
     const int k = it * 64 + lane;
+    long long D[3];
     if (own_tab) {
-      D[it][0] = tab[0][k];
-      D[it][1] = tab[1][k];
-      D[it][2] = tab[2][k];
+      D[0] = tab[0][k];
+      D[1] = tab[1][k];
+      D[2] = tab[2][k];
     } else {
-      sub_offset(g, k, D[it]);
+      sub_offset(g, k, D);
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      Dh[it][c] = (int)(D[c] >> 32);
+      Dl[it][c] = (uint32_t)(unsigned long long)D[c];
     }
   }
+  const int m0 = (int)g.mmin[0], m1 = (int)g.mmin[1], m2 = (int)g.mmin[2];
+  const uint32_t d0 = (uint32_t)g.dims[0], d1 = (uint32_t)g.dims[1], d2 = (uint32_t)g.dims[2];
   while (mask) {
     int ls[NC];
 #pragma unroll
@@ -86,23 +98,24 @@ __device__ __forceinline__ int sample_cells(const MapBodyK &g, bool own_tab, con
       mask &= mask - 1;
     }
     uint32_t word[NC][NIT];
-    int bit[NC][NIT];
+    uint32_t bit[NC][NIT];
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       const int l = ls[c] < 0 ? 0 : ls[c];
+      // the cell's centre in the body frame (wave-uniform)
       const long long Px = lane_ll(P[0], l), Py = lane_ll(P[1], l), Pz = lane_ll(P[2], l);
+      const int ph0 = (int)(Px >> 32) - m0, ph1 = (int)(Py >> 32) - m1, ph2 = (int)(Pz >> 32) - m2;
+      const uint32_t pl0 = (uint32_t)(unsigned long long)Px, pl1 = (uint32_t)(unsigned long long)Py,
+                     pl2 = (uint32_t)(unsigned long long)Pz;
 #pragma unroll
       for (int it = 0; it < NIT; ++it) {
+        const uint32_t jx = (uint32_t)(ph0 + Dh[it][0] + (int)(pl0 + Dl[it][0] < pl0));
+        const uint32_t jy = (uint32_t)(ph1 + Dh[it][1] + (int)(pl1 + Dl[it][1] < pl1));
+        const uint32_t jz = (uint32_t)(ph2 + Dh[it][2] + (int)(pl2 + Dl[it][2] < pl2));
         word[c][it] = 0;
-        bit[c][it] = 0;
-        const long long jx = ((Px + D[it][0]) >> 32) - g.mmin[0], jy = ((Py + D[it][1]) >> 32) - g.mmin[1],
-                        jz = ((Pz + D[it][2]) >> 32) - g.mmin[2];
-        if (ls[c] >= 0 && (unsigned long long)jx < (unsigned long long)g.dims[0] &&
-            (unsigned long long)jy < (unsigned long long)g.dims[1] &&
-            (unsigned long long)jz < (unsigned long long)g.dims[2]) {
-          word[c][it] = g.bits[((size_t)jz * g.dims[1] + (size_t)jy) * g.wx + (size_t)(jx >> 5)];
-          bit[c][it] = (int)(jx & 31);
-        }
+        bit[c][it] = jx & 31u;
+        if (ls[c] >= 0 && jx < d0 && jy < d1 && jz < d2)
+          word[c][it] = g.bits[((size_t)jz * d1 + jy) * (size_t)g.wx + (jx >> 5)];
       }
     }
 #pragma unroll
@@ -205,9 +218,9 @@ __global__ __launch_bounds__(256) void k_map(const MapArgs a) {
         count = c;
       }
     } else if (s == 2) {
-      count = sample_cells<1, 16>(g, own_tab, tab, __ballot(state == 2), P, lane, count);
+      count = sample_cells<1, 4>(g, own_tab, tab, __ballot(state == 2), P, lane, count);
     } else {
-      count = sample_cells<8, 4>(g, own_tab, tab, __ballot(state == 2), P, lane, count);
+      count = sample_cells<8, 2>(g, own_tab, tab, __ballot(state == 2), P, lane, count);
     }
     if (inb && count > 0) {
       float B;

@@ -335,7 +335,7 @@ __device__ __forceinline__ void fluid_row_cell(const SCArgs &a, int x, int y, in
   int xm = x - 1, xp = x + 1;
   if (xm < 0) xm = xper ? xm + nx : 0;
   if (xp >= nx) xp = xper ? xp - nx : nx - 1;
-  uint32_t o0 = (uint32_t)x * S, om = (uint32_t)xm * S, op = (uint32_t)xp * S;
+  const uint32_t o0 = (uint32_t)x * S, om = (uint32_t)xm * S, op = (uint32_t)xp * S;
   char *const A = a.pdf;
   const size_t NS = (size_t)a.N * S;
   char *const own_row = A + rowbase * S;
@@ -423,14 +423,6 @@ __device__ __forceinline__ void fluid_row_cell(const SCArgs &a, int x, int y, in
     stv<T, R>(slot(K, ownmask), v);
   };
   if (!xface) {
-    // fresh lane offsets: the store addresses are formed again from the
-    // scalar bases (saddr form) instead of keeping the loads' 64-bit
-    // addresses live across the collision
-    uint32_t r0 = o0, rm = om, rp = op;
-    asm volatile("" : "+v"(r0), "+v"(rm), "+v"(rp));
-    o0 = r0;
-    om = rm;
-    op = rp;
     sfor<Q>([&](auto K) { put(K, own_m, in_m, out_m); });
   } else {
     const uint32_t own_x = all.own(), in_x = all.inlet(), out_x = all.outlet();

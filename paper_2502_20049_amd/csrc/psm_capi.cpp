@@ -736,12 +736,14 @@ int psm_step(psm_field *f, const psm_body *map_poses, const psm_body *bodies, co
     if (e == hipSuccess) e = hipEventRecord(f->ev_map, f->side);
     if (e == hipSuccess) e = hipStreamWaitEvent(st, f->ev_map, 0);
   } else {
-    // no overlap: mapping, then the tiles away from the bodies
+    // no overlap: the mapping, then the whole stream-collide
     e = launch_map(P.a, P.maxcells, 0, st);
-    if (e == hipSuccess) {
-      r = sc_launch(f, a, step, 1, st);
-      if (r) return r;
-    }
+    if (e != hipSuccess) return hip_fail(e, "psm_step: mapping");
+    map_commit(f, P);
+    r = sc_launch(f, a, step, 0, st);
+    if (r) return r;
+    if (ft_dev) return body_force_torque(f, nb, ft_dev, stream);
+    return PSM_OK;
   }
   if (e != hipSuccess) return hip_fail(e, "psm_step: mapping");
   map_commit(f, P);
