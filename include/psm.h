@@ -124,7 +124,8 @@ const char *psm_last_error(void);
  *   PDF  q*N*sizeof(storage)
  *   B    psm ? N*4*slots + N (FP32 fraction per slot + one body-id byte) : 0
  *   WORK flags + force/torque partials (max_bodies*6 doubles per solid-kernel
- *        workgroup, 2048 of them) + reduction scratch
+ *        workgroup, 2048 of them) + reduction scratch + the mapping's lists
+ *        of surface cells (psm ? max_bodies * 2^21 * 4 bytes : 0)
  *   ADJOINT  one adjoint PDF buffer of psm_adjoint_step: q*N values in the
  *        adjoint precision (FP64 for PSM_F64 fields, else FP32)
  *   GRAD_B   the dJ/dB accumulator of psm_adjoint_step: N adjoint-precision
@@ -144,8 +145,9 @@ int psm_body_pose(const psm_motion *m, int64_t step, psm_body *out);
 
 /* ---- field lifetime -------------------------------------------------------- */
 /* Validates cfg and the caller buffers (sizes from psm_required_bytes; the
- * B buffer may be NULL when cfg->psm == 0) and records them.  Does not touch
- * device memory; call psm_field_reset before the first step. */
+ * B buffer may be NULL when cfg->psm == 0) and records them.  Clears the
+ * first 256 bytes of the work buffer (flags, counters) on `stream`; the PDFs
+ * and B are not touched: call psm_field_reset before the first step. */
 int pdf_field_create(const psm_config *cfg, void *pdf_dev, size_t pdf_bytes, void *b_dev,
                      size_t b_bytes, void *work_dev, size_t work_bytes, void *stream,
                      psm_field **out);
@@ -219,11 +221,11 @@ int body_force_torque(psm_field *f, int n_bodies, double *ft_dev, void *stream);
 
 /* One whole step: geometry_map_step(map_poses) + psm_stream_collide(bodies,
  * step) + (ft_dev != NULL) body_force_torque, with results bitwise identical
- * to those three calls in order.  The mapping of this step runs beside the
- * stream-collide of the interior tiles that touch no body box (those read no
- * B), one of them on the field's own second stream (PSM_OPT_OVERLAP); the
- * rest of the step waits for both.  Everything stays ordered on `stream` as seen by the caller: later work
- * on `stream` runs after the whole step.  map_poses may be NULL (= bodies);
+ * to those three calls in order.  With PSM_OPT_OVERLAP set, the mapping runs
+ * beside the stream-collide of the interior tiles that touch no body box
+ * (those read no B), one of the two on the field's own second stream, and the
+ * rest of the step waits for both.  Everything stays ordered on `stream` as
+ * seen by the caller: later work on `stream` runs after the whole step.  map_poses may be NULL (= bodies);
  * it differs from bodies only when the velocity used by the solid collision
  * differs from the motion that places the geometry (sensitivity runs).  With
  * PSM_OPT_GENERAL_PATH or an offset field set, the three calls run in order
@@ -278,8 +280,13 @@ int psm_error_flags(psm_field *f, int32_t *out_dev, void *stream);
  *                             whole stream-collide, on `stream`; 1 the mapping
  *                             on `stream` beside the B-free tiles on the
  *                             field's stream; 2 the same with the streams
- *                             swapped.  Results are identical. */
-enum { PSM_OPT_GENERAL_PATH = 1, PSM_OPT_XCD_REMAP = 2, PSM_OPT_OVERLAP = 3 };
+ *                             swapped.  Results are identical.
+ *   PSM_OPT_MAP_LIST  [2^21]  entries per body of the list of surface cells
+ *                             (s = 3 bodies) that geometry_map_step samples in
+ *                             a second kernel (one wave per cell); cells beyond it,
+ *                             and every cell with 0, are sampled in the
+ *                             classification kernel.  Results are identical. */
+enum { PSM_OPT_GENERAL_PATH = 1, PSM_OPT_XCD_REMAP = 2, PSM_OPT_OVERLAP = 3, PSM_OPT_MAP_LIST = 4 };
 int psm_set_option(psm_field *f, int option, int value);
 /* Device-to-device copy kernel (measured-bandwidth probe); 16-byte aligned
  * src and dst. */

@@ -129,15 +129,26 @@ __device__ __forceinline__ int sample_cells(const MapBodyK &g, bool own_tab, con
   return count;
 }
 
-__device__ __forceinline__ bool in_box(const IBox &b, int x, int y, int z) {
-  return x >= b.lo[0] && x <= b.hi[0] && y >= b.lo[1] && y <= b.hi[1] && z >= b.lo[2] && z <= b.hi[2];
+// Solid fraction from the inside count: eq. (5) (B = eps) or eq. (6).
+__device__ __forceinline__ float fraction_of(const MapArgs &a, int count, int ns) {
+  const double eps = (double)count / (double)ns;
+  if (a.b_form == 0) return (float)eps;
+  const double th = a.tau - 0.5;
+  const double num = eps * th;
+  const double den = (1.0 - eps) + th;
+  return (float)(num / den);
 }
 
-__global__ __launch_bounds__(256) void k_map(const MapArgs a) {
-  const int rb = blockIdx.y;
-  const MapBodyK &G = a.body[rb];
-  if (blockIdx.x * 256u >= G.region_cells) return;  // whole workgroup idle
-  __shared__ long long tab[3][512];
+// The cell centre in the body frame, fixed point (same operations in both
+// mapping kernels, so both see the same P).
+__device__ __forceinline__ void body_point(const MapBodyK &g, int x, int y, int z, long long P[3]) {
+  const double d0 = (x + 0.5) - g.X[0], d1 = (y + 0.5) - g.X[1], d2 = (z + 0.5) - g.X[2];
+  const double sc = (double)(1ull << (g.s + 32));
+#pragma unroll
+  for (int c = 0; c < 3; ++c) P[c] = __double2ll_rn(rt_comp(g.R, c, d0, d1, d2) * sc);
+}
+
+__device__ __forceinline__ void fill_table(const MapBodyK &G, long long (*tab)[512]) {
   const int nsr = 1 << (3 * G.s);
   for (int k = threadIdx.x; k < nsr; k += 256) {
     long long D[3];
@@ -147,6 +158,18 @@ __global__ __launch_bounds__(256) void k_map(const MapArgs a) {
     tab[2][k] = D[2];
   }
   __syncthreads();
+}
+
+__device__ __forceinline__ bool in_box(const IBox &b, int x, int y, int z) {
+  return x >= b.lo[0] && x <= b.hi[0] && y >= b.lo[1] && y <= b.hi[1] && z >= b.lo[2] && z <= b.hi[2];
+}
+
+__global__ __launch_bounds__(256) void k_map(const MapArgs a) {
+  const int rb = blockIdx.y;
+  const MapBodyK &G = a.body[rb];
+  if (blockIdx.x * 256u >= G.region_cells) return;  // whole workgroup idle
+  __shared__ long long tab[3][512];
+  fill_table(G, tab);
 
   const int lane = threadIdx.x & 63;
   const uint32_t idx = blockIdx.x * 256u + threadIdx.x;
@@ -157,6 +180,11 @@ __global__ __launch_bounds__(256) void k_map(const MapArgs a) {
   const int z = G.region.lo[2] + (int)(idx / ((uint32_t)rx * (uint32_t)ry));
   for (int b = 0; b < rb; ++b)
     if (in_box(a.body[b].region, x, y, z)) active = false;  // written by an earlier region
+  const size_t n = (size_t)x + (size_t)a.nx * ((size_t)y + (size_t)a.ny * (size_t)z);
+  // bodies that can touch the cell: a surface cell of a single body may be
+  // left to the sampling kernel (its B does not combine with another body's)
+  int nin = 0;
+  for (int bb = 0; bb < a.nb; ++bb) nin += (active && in_box(a.body[bb].active, x, y, z)) ? 1 : 0;
 
   float Bv[2] = {0.f, 0.f};
   int id[2] = {0, 0};
@@ -171,10 +199,7 @@ __global__ __launch_bounds__(256) void k_map(const MapArgs a) {
     long long P[3] = {0, 0, 0};
     int state = 0;  // 0 all out, 1 all in, 2 sample
     if (inb) {
-      const double d0 = (x + 0.5) - g.X[0], d1 = (y + 0.5) - g.X[1], d2 = (z + 0.5) - g.X[2];
-      const double sc = (double)(1ull << (s + 32));
-#pragma unroll
-      for (int c = 0; c < 3; ++c) P[c] = __double2ll_rn(rt_comp(g.R, c, d0, d1, d2) * sc);
+      body_point(g, x, y, z, P);
       if (s == 0) {
         state = 2;
       } else {
@@ -217,22 +242,35 @@ __global__ __launch_bounds__(256) void k_map(const MapArgs a) {
         }
         count = c;
       }
-    } else if (s == 2) {
-      count = sample_cells<1, 4>(g, own_tab, tab, __ballot(state == 2), P, lane, count);
     } else {
-      count = sample_cells<8, 2>(g, own_tab, tab, __ballot(state == 2), P, lane, count);
+      // at s = 3 (512 sub-samples) surface cells of a single body go to the
+      // sampling list (one wave per cell there); the rest, and any beyond the
+      // list's capacity, are sampled here.  At s = 2 (64 sub-samples, one
+      // per lane) sampling here, several cells per round, is faster.
+      bool listed = false;
+      if (a.list && s == 3) {
+        const bool cand = inb && state == 2 && nin == 1;
+        const unsigned long long cm = __ballot(cand);
+        if (cm) {
+          const int leader = __ffsll((long long)cm) - 1;
+          uint32_t base = 0;
+          if (lane == leader) base = atomicAdd(&a.count[bb], (uint32_t)__popcll(cm));
+          base = __shfl(base, leader);
+          const uint32_t pos = base + (uint32_t)__popcll(cm & ((1ull << lane) - 1ull));
+          if (cand && pos < a.cap) {
+            a.list[(size_t)bb * a.cap + pos] = (uint32_t)n;
+            listed = true;
+          }
+        }
+      }
+      const unsigned long long sm = __ballot(state == 2 && !listed);
+      if (s == 2)
+        count = sample_cells<1, 4>(g, own_tab, tab, sm, P, lane, count);
+      else
+        count = sample_cells<8, 2>(g, own_tab, tab, sm, P, lane, count);
     }
     if (inb && count > 0) {
-      float B;
-      const double eps = (double)count / (double)ns;
-      if (a.b_form == 0) {
-        B = (float)eps;
-      } else {
-        const double th = a.tau - 0.5;
-        const double num = eps * th;
-        const double den = (1.0 - eps) + th;
-        B = (float)(num / den);
-      }
+      const float B = fraction_of(a, count, ns);
       if (used < a.slots) {
         Bv[used] = B;
         id[used] = bb;
@@ -243,7 +281,6 @@ __global__ __launch_bounds__(256) void k_map(const MapArgs a) {
     }
   }
   if (active) {
-    const size_t n = (size_t)x + (size_t)a.nx * ((size_t)y + (size_t)a.ny * (size_t)z);
     a.B0[n] = Bv[0];
     uint8_t m = (uint8_t)(id[0] & 15);
     if (a.slots == 2) {
@@ -255,11 +292,46 @@ __global__ __launch_bounds__(256) void k_map(const MapArgs a) {
   }
 }
 
+// Listed surface cells (s = 3): one wave per cell, 8 sub-samples per lane, B
+// and the body id written for cells with a nonzero count (the classification
+// kernel already wrote zeros).  Also clears the counters the
+// next mapping call appends to.
+__global__ __launch_bounds__(256) void k_map_sample(const MapArgs a) {
+  const int bb = blockIdx.y;
+  const MapBodyK &G = a.body[bb];
+  if (blockIdx.x == 0 && threadIdx.x == 0) a.count_next[bb] = 0u;
+  if (G.s != 3) return;
+  const uint32_t total = min(a.count[bb], a.cap);
+  if (blockIdx.x * 4u >= total) return;  // whole workgroup idle
+  __shared__ long long tab[3][512];
+  fill_table(G, tab);
+  const int lane = threadIdx.x & 63;
+  const int ns = 1 << (3 * G.s);
+  for (uint32_t e = blockIdx.x * 4u + (threadIdx.x >> 6); e < total; e += gridDim.x * 4u) {
+    const uint32_t n = a.list[(size_t)bb * a.cap + e];
+    const int x = (int)(n % (uint32_t)a.nx);
+    const int y = (int)((n / (uint32_t)a.nx) % (uint32_t)a.ny);
+    const int z = (int)(n / ((uint32_t)a.nx * (uint32_t)a.ny));
+    long long P[3];
+    body_point(G, x, y, z, P);
+    const int c = sample_cells<8, 1>(G, true, tab, 1ull, P, lane, 0);
+    if (lane == 0 && c > 0) {
+      a.B0[n] = fraction_of(a, c, ns);
+      a.meta[n] = (uint8_t)(bb & 15);
+    }
+  }
+}
+
 hipError_t launch_map(const MapArgs &a, uint32_t max_region_cells, int any_s_max, hipStream_t st) {
   (void)any_s_max;
   if (a.nb == 0 || max_region_cells == 0) return hipSuccess;
   dim3 grid((max_region_cells + 255) / 256, a.nb), block(256);
   hipLaunchKernelGGL(k_map, grid, block, 0, st, a);
+  if (a.list) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_map_sample, dim3(MAP_SAMPLE_BLOCKS, a.nb), block, 0, st, a);
+  }
   return hipGetLastError();
 }
 

@@ -44,9 +44,14 @@ static void tile_shape(int nx, int &TX, int &lTX) {
 struct Layout {
   int TX, TY, lTX, ntx, nty;
   int64_t ntiles, N;
-  size_t off_ftp, off_red, work_bytes;
+  size_t off_ftp, off_red, off_list, work_bytes;
   uint32_t red_count;
 };
+
+// work buffer: [0, 256) error flags (offset 0) and the mapping's per-body
+// list counters (offset 64, two sets); then F/T partials, reduction scratch
+// and the mapping's surface-cell lists
+constexpr size_t OFF_MAP_COUNT = 64;
 
 static Layout layout_of(const psm_config &c) {
   Layout L{};
@@ -60,7 +65,8 @@ static Layout layout_of(const psm_config &c) {
   L.off_ftp = 256;
   L.off_red = L.off_ftp + (size_t)SOLID_BLOCKS * mb * 6 * sizeof(double);
   L.red_count = (uint32_t)((L.N + 255) / 256);
-  L.work_bytes = L.off_red + (size_t)L.red_count * sizeof(double) + 64;
+  L.off_list = ((L.off_red + (size_t)L.red_count * sizeof(double) + 64 + 255) / 256) * 256;
+  L.work_bytes = L.off_list + (size_t)mb * MAP_LIST_CAP * sizeof(uint32_t);
   return L;
 }
 
@@ -226,7 +232,6 @@ int psm_body_pose(const psm_motion *m, int64_t step, psm_body *out) {
 
 int pdf_field_create(const psm_config *cfg, void *pdf, size_t pdf_bytes, void *b, size_t b_bytes, void *work,
                      size_t work_bytes, void *stream, psm_field **out) {
-  (void)stream;
   int r = check_config(cfg);
   if (r) return r;
   if (!out) return set_error("null output handle"), PSM_EINVAL;
@@ -261,6 +266,10 @@ int pdf_field_create(const psm_config *cfg, void *pdf, size_t pdf_bytes, void *b
   f->ftp = (double *)((char *)work + L.off_ftp);
   f->red = (double *)((char *)work + L.off_red);
   f->red_count = L.red_count;
+  if (cfg->psm) {
+    f->map_list = (uint32_t *)((char *)work + L.off_list);
+    f->map_count = (uint32_t *)((char *)work + OFF_MAP_COUNT);
+  }
   f->TX = L.TX;
   f->TY = L.TY;
   f->lTX = L.lTX;
@@ -270,7 +279,16 @@ int pdf_field_create(const psm_config *cfg, void *pdf, size_t pdf_bytes, void *b
   for (int i = 0; i < PSM_MAX_BODIES; ++i) f->active[i] = empty_box();
   f->opt_xcd_remap = 0;
   f->opt_overlap = 0;
+  f->map_list_cap = cfg->psm ? (int)MAP_LIST_CAP : 0;
   if (hipGetDevice(&f->device) != hipSuccess) f->device = -1;
+  {
+    // error flags and mapping counters start at zero
+    hipError_t e = launch_fill_zero(work, 256, (hipStream_t)stream);
+    if (e != hipSuccess) {
+      delete f;
+      return hip_fail(e, "pdf_field_create: clear");
+    }
+  }
   if (cfg->psm) {
     hipError_t e = hipStreamCreateWithFlags(&f->side, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&f->ev_prev, hipEventDisableTiming);
@@ -311,6 +329,7 @@ int psm_field_reset(psm_field *f, void *stream) {
   if (e == hipSuccess) e = launch_fill_zero(f->work, 256, st);
   if (e != hipSuccess) return hip_fail(e, "psm_field_reset");
   f->nb_mapped = 0;
+  f->map_parity = 0;
   for (int i = 0; i < PSM_MAX_BODIES; ++i) {
     f->have_prev[i] = false;
     f->active[i] = empty_box();
@@ -488,6 +507,10 @@ static int map_plan(psm_field *f, const psm_body *bodies, const psm_geom *const 
     return set_error("the number of bodies changed; reset the field first"), PSM_EINVAL;
   MapArgs &a = P.a;
   memset(&a, 0, sizeof(a));
+  a.list = f->map_list_cap > 0 ? f->map_list : nullptr;
+  a.count = f->map_count + (size_t)f->map_parity * PSM_MAX_BODIES;
+  a.count_next = f->map_count + (size_t)(f->map_parity ^ 1) * PSM_MAX_BODIES;
+  a.cap = (uint32_t)f->map_list_cap;
   a.B0 = f->B0;
   a.B1 = f->B1;
   a.meta = f->meta;
@@ -566,10 +589,15 @@ static int map_plan(psm_field *f, const psm_body *bodies, const psm_geom *const 
   }
   P.maxcells = maxcells;
   P.nb = nb;
+  // the surface-cell list serves s = 3 bodies only
+  bool any3 = false;
+  for (int b = 0; b < nb; ++b) any3 = any3 || geoms[b]->s == 3;
+  if (!any3) a.list = nullptr;
   return PSM_OK;
 }
 
 static void map_commit(psm_field *f, const MapPlan &P) {
+  if (P.a.list && P.maxcells > 0 && P.nb > 0) f->map_parity ^= 1;  // one counter set used, the other cleared
   for (int b = 0; b < P.nb; ++b) {
     f->active[b] = P.now[b];
     f->have_prev[b] = true;
@@ -782,6 +810,11 @@ int psm_set_option(psm_field *f, int option, int value) {
   switch (option) {
     case PSM_OPT_GENERAL_PATH: f->opt_general_path = value ? 1 : 0; return PSM_OK;
     case PSM_OPT_XCD_REMAP: f->opt_xcd_remap = value ? 1 : 0; return PSM_OK;
+    case PSM_OPT_MAP_LIST:
+      if (value < 0 || (uint32_t)value > MAP_LIST_CAP)
+        return set_error("PSM_OPT_MAP_LIST takes 0 .. the list capacity"), PSM_EINVAL;
+      f->map_list_cap = value;
+      return PSM_OK;
     case PSM_OPT_OVERLAP:
       if (value < 0 || value > 2) return set_error("PSM_OPT_OVERLAP takes 0, 1 or 2"), PSM_EINVAL;
       f->opt_overlap = value;

@@ -156,11 +156,19 @@ struct MapBodyK {
   uint32_t region_cells;
 };
 
+// capacity of a body's list of surface cells left to the sampling kernel
+constexpr uint32_t MAP_LIST_CAP = 1u << 21;
+constexpr uint32_t MAP_SAMPLE_BLOCKS = 1024;
+
 struct MapArgs {
   float *B0;
   float *B1;
   uint8_t *meta;
   int32_t *err;
+  uint32_t *list;        // [body][cap] cell indices, or null (no list)
+  uint32_t *count;       // [body] appended this call
+  uint32_t *count_next;  // [body] cleared for the next call
+  uint32_t cap;
   int nx, ny, nz;
   int nb;
   int slots;
@@ -187,6 +195,10 @@ struct psm_field {
   int32_t *err;
   double *ftp;
   double *red;  // reduction scratch
+  uint32_t *map_list;   // surface-cell lists of the mapping (null: none)
+  uint32_t *map_count;  // two sets of per-body counters, used in turn
+  int map_parity;
+  int map_list_cap;     // entries per body actually used (PSM_OPT_MAP_LIST)
   size_t red_count;
   int64_t N;
   int TX, TY, lTX, ntx, nty;

@@ -188,12 +188,14 @@ def test_xcd_remap_bitwise_identical(sim, gc):
     assert torch.equal(res[0][0], res[1][0]) and torch.equal(res[0][1], res[1][1])
 
 
-@pytest.mark.parametrize("s", [0, 1, 2, 3])
-def test_mapping_bit_exact(orc, sim, gc, s):
-    """B(t) of rotating analytic and mesh bodies, two slots, random poses."""
+@pytest.mark.parametrize("s,cap", [(0, None), (1, None), (2, None), (3, None), (2, 0), (3, 0), (2, 5), (3, 5)])
+def test_mapping_bit_exact(orc, sim, gc, s, cap):
+    """B(t) of rotating analytic and mesh bodies, two slots, random poses.
+    cap: capacity of the surface-cell list sampled by the second mapping
+    kernel (None: the default; 0: no list; 5: most cells overflow it)."""
     import torch
 
-    _say(f"[mapping] s={s}")
+    _say(f"[mapping] s={s} list cap={cap}")
     rotor = pi.rotor_mesh(pi.RotorSpec(n_blades=3, radius=7.0, hub_radius=1.75, hub_length=3.1, chord_root=2.1,
                                        chord_tip=1.05, n_chord=8, n_span=6, n_hub=16, seed=7))
     bodies = [pi.Body(pi.Shape("mesh", (), rotor), pi.Motion(axis=(1, 0, 0), theta0=0.2, omega=0.37,
@@ -205,6 +207,8 @@ def test_mapping_bit_exact(orc, sim, gc, s):
     wl = pi.Workload("map", 33, 30, 28, 19, "f32", 0.8, 3 / 16, (0, 0, 0), ("periodic",) * 6, (0, 0, 0), 1, 0, 2, 3,
                      bodies)
     f = sim.Field(wl, max_bodies=3)
+    if cap is not None:
+        f.set_option(4, cap)
     run = orc.Run(wl)
     for t in (0, 1, 2, 5):
         f.map(t)
