@@ -443,37 +443,6 @@ __device__ __forceinline__ bool fluid_lane(const SCArgs &a, int x, int y, int z,
   return true;
 }
 
-// Interior rows (1 <= y <= ny-2, 1 <= z <= nz-2), TY rows of TX cells per block.
-template <int Q, typename T, int PAR, bool PSM>
-__global__ __launch_bounds__(256) void k_fluid(const SCArgs a) {
-  const int tid = threadIdx.x;
-  int txi, tyi, z;
-  if (a.fsel == 2) {  // grid = the near range
-    uint32_t b = blockIdx.x;
-    txi = a.near_lo[0] + (int)(b % (uint32_t)a.near_n[0]);
-    b /= (uint32_t)a.near_n[0];
-    tyi = a.near_lo[1] + (int)(b % (uint32_t)a.near_n[1]);
-    z = 1 + a.near_lo[2] + (int)(b / (uint32_t)a.near_n[1]);
-  } else {
-    const uint32_t tile = a.xcd_remap ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x;
-    txi = (int)(tile % (uint32_t)a.ntx);
-    const uint32_t rr = tile / (uint32_t)a.ntx;
-    tyi = (int)(rr % (uint32_t)a.nty_i);
-    z = 1 + (int)(rr / (uint32_t)a.nty_i);
-    if (a.fsel == 1 && (unsigned)(txi - a.near_lo[0]) < (unsigned)a.near_n[0] &&
-        (unsigned)(tyi - a.near_lo[1]) < (unsigned)a.near_n[1] &&
-        (unsigned)(z - 1 - a.near_lo[2]) < (unsigned)a.near_n[2])
-      return;
-  }
-  const int x = txi * a.TX + (tid & (a.TX - 1));
-  // TX >= 64: the row is the same over the wave
-  const int y = __builtin_amdgcn_readfirstlane(1 + tyi * a.TY + (tid >> a.lTX));
-  if (y > a.ny - 2) return;
-  const size_t rowbase = (size_t)a.nx * (size_t)y + (size_t)a.nx * (size_t)a.ny * (size_t)z;
-  if (!fluid_lane<typename Comp<T>::type, PSM>(a, x, y, z, rowbase)) return;
-  fluid_row_cell<Q, T, PAR, false>(a, x, y, z, rowbase);
-}
-
 // Row r of the rows on a y or z face: the planes z = 0 and z = nz-1, then the
 // rows y = 0 and y = ny-1 of the other planes (each row once).
 __device__ __forceinline__ void edge_row_yz(const SCArgs &a, int r, int &y, int &z) {
@@ -492,10 +461,10 @@ __device__ __forceinline__ void edge_row_yz(const SCArgs &a, int r, int &y, int 
 
 // Rows on a y or z face, TY rows (of the list above) of TX cells per block.
 template <int Q, typename T, int PAR, bool PSM>
-__global__ __launch_bounds__(256) void k_fluid_edge(const SCArgs a) {
+__device__ __forceinline__ void edge_block(const SCArgs &a, uint32_t bid) {
   const int tid = threadIdx.x;
-  const int txi = (int)(blockIdx.x % (uint32_t)a.ntx);
-  const int r = __builtin_amdgcn_readfirstlane((int)(blockIdx.x / (uint32_t)a.ntx) * a.TY + (tid >> a.lTX));
+  const int txi = (int)(bid % (uint32_t)a.ntx);
+  const int r = __builtin_amdgcn_readfirstlane((int)(bid / (uint32_t)a.ntx) * a.TY + (tid >> a.lTX));
   if (r >= a.nfrows) return;
   int y, z;
   edge_row_yz(a, r, y, z);
@@ -503,6 +472,50 @@ __global__ __launch_bounds__(256) void k_fluid_edge(const SCArgs a) {
   const size_t rowbase = (size_t)a.nx * (size_t)y + (size_t)a.nx * (size_t)a.ny * (size_t)z;
   if (!fluid_lane<typename Comp<T>::type, PSM>(a, x, y, z, rowbase)) return;
   fluid_row_cell<Q, T, PAR, true>(a, x, y, z, rowbase);
+}
+
+// Interior rows (1 <= y <= ny-2, 1 <= z <= nz-2), TY rows of TX cells per block.
+template <int Q, typename T, int PAR, bool PSM>
+__global__ __launch_bounds__(256) void k_fluid(const SCArgs a) {
+  const int tid = threadIdx.x;
+  if constexpr (PAR == 0 && Q == 19) {
+    // even D3Q19 steps: the rows on the y/z faces ride along as extra blocks
+    // (there the edge path needs no more registers than the interior one)
+    if (a.fsel == 0 && blockIdx.x >= a.ntiles_i) {
+      edge_block<Q, T, PAR, PSM>(a, blockIdx.x - a.ntiles_i);
+      return;
+    }
+  }
+  int txi, tyi, z;
+  if (a.fsel == 2) {  // grid = the near range
+    uint32_t b = blockIdx.x;
+    txi = a.near_lo[0] + (int)(b % (uint32_t)a.near_n[0]);
+    b /= (uint32_t)a.near_n[0];
+    tyi = a.near_lo[1] + (int)(b % (uint32_t)a.near_n[1]);
+    z = 1 + a.near_lo[2] + (int)(b / (uint32_t)a.near_n[1]);
+  } else {
+    const uint32_t tile = a.xcd_remap ? xcd_remap(blockIdx.x, a.ntiles_i) : blockIdx.x;
+    txi = (int)(tile % (uint32_t)a.ntx);
+    const uint32_t rr = tile / (uint32_t)a.ntx;
+    tyi = (int)(rr % (uint32_t)a.nty_i);
+    z = 1 + (int)(rr / (uint32_t)a.nty_i);
+    if (a.fsel == 1 && (unsigned)(txi - a.near_lo[0]) < (unsigned)a.near_n[0] &&
+        (unsigned)(tyi - a.near_lo[1]) < (unsigned)a.near_n[1] &&
+        (unsigned)(z - 1 - a.near_lo[2]) < (unsigned)a.near_n[2])
+      return;
+  }
+  const int x = txi * a.TX + (tid & (a.TX - 1));
+  // TX >= 64: the row is the same over the wave
+  const int y = __builtin_amdgcn_readfirstlane(1 + tyi * a.TY + (tid >> a.lTX));
+  if (y > a.ny - 2) return;
+  const size_t rowbase = (size_t)a.nx * (size_t)y + (size_t)a.nx * (size_t)a.ny * (size_t)z;
+  if (!fluid_lane<typename Comp<T>::type, PSM>(a, x, y, z, rowbase)) return;
+  fluid_row_cell<Q, T, PAR, false>(a, x, y, z, rowbase);
+}
+
+template <int Q, typename T, int PAR, bool PSM>
+__global__ __launch_bounds__(256) void k_fluid_edge(const SCArgs a) {
+  edge_block<Q, T, PAR, PSM>(a, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
