@@ -59,8 +59,8 @@ def bytes_per_cell(q, storage, psm=True):
 
 
 def run_steps(field, t0, n, events=None, map_events=None, fused=True):
-    """Steps t0 .. t0+n-1.  fused: one psm_step per step (mapping overlapped
-    with the bulk of the update, F/T summed); else the separate calls
+    """Steps t0 .. t0+n-1.  fused: one psm_step per step (mapping,
+    stream-collide and F/T sum in one call); else the separate calls
     geometry_map_step / psm_stream_collide / body_force_torque, with HIP
     events on the launch stream around the first two when given."""
     for i in range(n):
@@ -216,7 +216,7 @@ def rotor_box(steps=200):
     out["psm_mlups"] = round(wl.n_cells * steps / wall / 1e6, 1)
     out["collide_ms"] = round(sc, 5)
     out["map_ms"] = round(mp, 5)
-    out["map_share_unoverlapped"] = round(mp * steps / 1e3 / wall, 4)
+    out["map_share"] = round(mp * steps / 1e3 / wall, 4)
     del f
     torch.cuda.empty_cache()
     fl = sim.Field(wl, psm=False)
@@ -278,6 +278,8 @@ def main():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="ellipsoid_channel_256")
+    ap.add_argument("--storage", choices=["f64", "f32", "f16"], default=None,
+                    help="PDF storage type (default: the workload's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip variants, copy probe and accuracy")
     ap.add_argument("--only-psm", action="store_true", help="time the PSM path only (for profiling)")
@@ -301,6 +303,8 @@ def main():
                           "bytes_written_per_launch": 1 << 30}), flush=True)
         return
     wl = workload(args.workload)
+    if args.storage:
+        wl.storage = args.storage
     storage = wl.storage
     f = sim.Field(wl)
     wall, t_end = time_field(f, args.steps, args.warmup)
@@ -309,7 +313,7 @@ def main():
     mlups = N * args.steps / wall / 1e6
     bpc = bytes_per_cell(wl.q, storage)
     achieved = bpc * N / (sc_ms / 1e3) / 1e9
-    traffic = traffic_record("psm_stream_collide", args.workload)
+    traffic = traffic_record("psm_stream_collide", args.workload + (f"_{storage}" if args.storage else ""))
     line = {
         "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(wall / args.steps * 1e3, 4), "higher_is_better": True,
@@ -338,15 +342,6 @@ def main():
                                             "gbs": round(bytes_per_cell(wl.q, storage, False) * N / sc_l / 1e6, 1)}
         del fl
         torch.cuda.empty_cache()
-        sched = {}
-        for mode in (0, 1, 2):
-            fm = sim.Field(wl)
-            fm.set_option(3, mode)
-            wall_m, _ = time_field(fm, min(args.steps, 500), 20)
-            sched[str(mode)] = round(N * min(args.steps, 500) / wall_m / 1e6, 1)
-            del fm
-            torch.cuda.empty_cache()
-        extras["psm_step_schedule_mlups"] = sched
         fs = sim.Field(wl, remap_every_step=False)
         wall_s, _ = time_field(fs, min(args.steps, 500), 20)
         extras["psm_static_geometry"] = {"mlups": round(N * min(args.steps, 500) / wall_s / 1e6, 1)}

@@ -18,9 +18,7 @@
  * Conventions shared by every entry point
  *   - Memory ownership: every device buffer is allocated and freed by the
  *     caller (e.g. torch tensors) and passed as pointer + byte count.  Handles
- *     own host-side metadata only (a PSM field also owns one HIP stream and
- *     two events for psm_step, created with it and released by
- *     pdf_field_destroy).  No per-step call allocates anything.
+ *     own host-side metadata only.  No per-step call allocates anything.
  *   - Streams: `stream` is a hipStream_t (NULL = default stream).  Calls are
  *     asynchronous on it; results are valid after the stream is synchronised.
  *   - Errors: 0 on success, a negative PSM_E* code otherwise; psm_last_error()
@@ -219,18 +217,12 @@ int psm_stream_collide(psm_field *f, const psm_body *bodies, int n_bodies, int64
  * units. */
 int body_force_torque(psm_field *f, int n_bodies, double *ft_dev, void *stream);
 
-/* One whole step: geometry_map_step(map_poses) + psm_stream_collide(bodies,
- * step) + (ft_dev != NULL) body_force_torque, with results bitwise identical
- * to those three calls in order.  With PSM_OPT_OVERLAP set, the mapping runs
- * beside the stream-collide of the interior tiles that touch no body box
- * (those read no B), one of the two on the field's own second stream, and the
- * rest of the step waits for both.  Everything stays ordered on `stream` as
- * seen by the caller: later work on `stream` runs after the whole step.  map_poses may be NULL (= bodies);
- * it differs from bodies only when the velocity used by the solid collision
- * differs from the motion that places the geometry (sensitivity runs).  With
- * PSM_OPT_GENERAL_PATH or an offset field set, the three calls run in order
- * on `stream`.  A plain-LBM field (or n_bodies = 0) takes one
- * psm_stream_collide.  Calls on one field must not overlap. */
+/* One whole step in one call: geometry_map_step(map_poses) +
+ * psm_stream_collide(bodies, step) + (ft_dev != NULL) body_force_torque, in
+ * that order on `stream`.  map_poses may be NULL (= bodies); it differs from
+ * bodies only when the velocity used by the solid collision differs from the
+ * motion that places the geometry (sensitivity runs).  A plain-LBM field (or
+ * n_bodies = 0) takes one psm_stream_collide. */
 int psm_step(psm_field *f, const psm_body *map_poses, const psm_body *bodies, const psm_geom *const *geoms,
              int n_bodies, int64_t step, double *ft_dev, void *stream);
 
@@ -276,17 +268,12 @@ int psm_error_flags(psm_field *f, int32_t *out_dev, void *stream);
  *                             bitwise identical, used to cross-check the fast path
  *   PSM_OPT_XCD_REMAP    [0]  1: workgroup ids are remapped so each of the 8
  *                             XCDs walks a contiguous range of tiles
- *   PSM_OPT_OVERLAP      [0]  psm_step schedule: 0 the mapping, then the
- *                             whole stream-collide, on `stream`; 1 the mapping
- *                             on `stream` beside the B-free tiles on the
- *                             field's stream; 2 the same with the streams
- *                             swapped.  Results are identical.
  *   PSM_OPT_MAP_LIST  [2^21]  entries per body of the list of surface cells
  *                             (s = 3 bodies) that geometry_map_step samples in
  *                             a second kernel (one wave per cell); cells beyond it,
  *                             and every cell with 0, are sampled in the
  *                             classification kernel.  Results are identical. */
-enum { PSM_OPT_GENERAL_PATH = 1, PSM_OPT_XCD_REMAP = 2, PSM_OPT_OVERLAP = 3, PSM_OPT_MAP_LIST = 4 };
+enum { PSM_OPT_GENERAL_PATH = 1, PSM_OPT_XCD_REMAP = 2, PSM_OPT_MAP_LIST = 4 };
 int psm_set_option(psm_field *f, int option, int value);
 /* Device-to-device copy kernel (measured-bandwidth probe); 16-byte aligned
  * src and dst. */

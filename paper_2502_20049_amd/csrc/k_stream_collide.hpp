@@ -323,111 +323,186 @@ struct FaceAcc {
 };
 
 template <int Q, typename T, int PAR, bool EDGE>
-__device__ __forceinline__ void fluid_row_cell(const SCArgs &a, int x, int y, int z, size_t rowbase) {
+struct RowCell {
   using R = typename Comp<T>::type;
-  constexpr uint32_t S = sizeof(T);
-  const int nx = a.nx, ny = a.ny, nz = a.nz;
-  const size_t nxy = (size_t)nx * (size_t)ny;
-  const bool xper = a.periodic[0] != 0;
-  const bool lo_face = !xper && x == 0;       // sources x-1 are outside (face -x)
-  const bool hi_face = !xper && x == nx - 1;  // sources x+1 are outside (face +x)
-  const bool xface = lo_face || hi_face;
-  int xm = x - 1, xp = x + 1;
-  if (xm < 0) xm = xper ? xm + nx : 0;
-  if (xp >= nx) xp = xper ? xp - nx : nx - 1;
-  const uint32_t o0 = (uint32_t)x * S, om = (uint32_t)xm * S, op = (uint32_t)xp * S;
-  char *const A = a.pdf;
-  const size_t NS = (size_t)a.N * S;
-  char *const own_row = A + rowbase * S;
-  // y/z face rules of this row (wave-uniform)
-  FaceAcc yz;
-  if constexpr (EDGE) {
-    const bool py = a.periodic[1] != 0, pz = a.periodic[2] != 0;
-    yz.add(!py && y == 0, a.bc[2], dirs_with<Q>(1, 1));
-    yz.add(!py && y == ny - 1, a.bc[3], dirs_with<Q>(1, -1));
-    yz.add(!pz && z == 0, a.bc[4], dirs_with<Q>(2, 1));
-    yz.add(!pz && z == nz - 1, a.bc[5], dirs_with<Q>(2, -1));
+  static constexpr uint32_t S = sizeof(T);
+  const SCArgs &a;
+  int y, z;
+  bool lo_face, hi_face, xface;
+  uint32_t o0, om, op;
+  size_t NS, nxy;
+  char *own_row;
+  uint32_t own_m, in_m, out_m;
+  FaceAcc yz, all;
+
+  __device__ __forceinline__ RowCell(const SCArgs &args, int x, int y_, int z_, size_t rowbase)
+      : a(args), y(y_), z(z_) {
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    nxy = (size_t)nx * (size_t)ny;
+    const bool xper = a.periodic[0] != 0;
+    lo_face = !xper && x == 0;       // sources x-1 are outside (face -x)
+    hi_face = !xper && x == nx - 1;  // sources x+1 are outside (face +x)
+    xface = lo_face || hi_face;
+    int xm = x - 1, xp = x + 1;
+    if (xm < 0) xm = xper ? xm + nx : 0;
+    if (xp >= nx) xp = xper ? xp - nx : nx - 1;
+    o0 = (uint32_t)x * S;
+    om = (uint32_t)xm * S;
+    op = (uint32_t)xp * S;
+    NS = (size_t)a.N * S;
+    own_row = a.pdf + rowbase * S;
+    // y/z face rules of this row (wave-uniform)
+    if constexpr (EDGE) {
+      const bool py = a.periodic[1] != 0, pz = a.periodic[2] != 0;
+      yz.add(!py && y == 0, a.bc[2], dirs_with<Q>(1, 1));
+      yz.add(!py && y == ny - 1, a.bc[3], dirs_with<Q>(1, -1));
+      yz.add(!pz && z == 0, a.bc[4], dirs_with<Q>(2, 1));
+      yz.add(!pz && z == nz - 1, a.bc[5], dirs_with<Q>(2, -1));
+    }
+    own_m = yz.own();
+    in_m = yz.inlet();
+    out_m = yz.outlet();
+    all = yz;
+    if (xface) {
+      all.add(lo_face, a.bc[0], dirs_with<Q>(0, 1));
+      all.add(hi_face, a.bc[1], dirs_with<Q>(0, -1));
+    }
   }
-  const uint32_t own_m = yz.own(), in_m = yz.inlet(), out_m = yz.outlet();
-  auto own = [&](auto K) -> char * { return own_row + (size_t)(int)K * NS + o0; };
+
+  template <typename K>
+  __device__ __forceinline__ char *own(K) const {
+    return own_row + (size_t)(int)K::value * NS + o0;
+  }
   // odd parity, no face: slot kbar of the source cell x - c_k, as a
   // wave-uniform row base and a 32-bit lane offset
-  auto src_base = [&](auto K) -> char * {
-    constexpr int k = K;
+  template <typename K>
+  __device__ __forceinline__ char *src_base(K) const {
+    constexpr int k = K::value;
     constexpr int ey = cy<Q>(k), ez = cz<Q>(k);
     char *row;
     if constexpr (!EDGE) {
-      row = own_row - ((long long)ey * nx + (long long)ez * (long long)nxy) * (long long)S;
+      row = own_row - ((long long)ey * a.nx + (long long)ez * (long long)nxy) * (long long)S;
     } else {
       int sy = y - ey, sz = z - ez;
-      if (sy < 0) sy += ny;
-      if (sy >= ny) sy -= ny;
-      if (sz < 0) sz += nz;
-      if (sz >= nz) sz -= nz;
-      row = A + ((size_t)nx * (size_t)sy + nxy * (size_t)sz) * S;
+      if (sy < 0) sy += a.ny;
+      if (sy >= a.ny) sy -= a.ny;
+      if (sz < 0) sz += a.nz;
+      if (sz >= a.nz) sz -= a.nz;
+      row = a.pdf + ((size_t)a.nx * (size_t)sy + nxy * (size_t)sz) * S;
     }
     return row + (size_t)opp<Q>(k) * NS;
-  };
-  auto src_lane = [&](auto K) -> uint32_t {
-    constexpr int ex = cx<Q>(K);
+  }
+  template <typename K>
+  __device__ __forceinline__ uint32_t src_lane(K) const {
+    constexpr int ex = cx<Q>(K::value);
     return ex == 1 ? om : (ex == -1 ? op : o0);
-  };
+  }
   // slot of direction k: own slot at even parity or where the face mask has
   // k, else the source slot.  Base and lane offset are selected separately
   // (both candidates formed first, so the choice is a select): with a
   // wave-uniform mask the base stays scalar.
-  auto slot = [&](auto K, uint32_t ownmask) -> char * {
-    if constexpr (PAR == 0) return own(K);
-    char *const bo = own_row + (size_t)(int)K * NS;
-    char *const bs = src_base(K);
-    const uint32_t ls = src_lane(K);
-    const bool fc = (ownmask >> (int)K) & 1u;
-    return (fc ? bo : bs) + (fc ? o0 : ls);
-  };
-  auto inlet_if = [&](auto K, uint32_t inmask) -> R {
-    const R t = inlet_term<Q, R>(a, (int)K);
-    return ((inmask >> (int)K) & 1u) ? t : R(0);
-  };
-  R f[Q];
-  sfor<Q>([&](auto K) {
-    constexpr int k = K;
-    R v = ldv<T, R>(slot(K, own_m));
-    if constexpr (PAR == 1 && EDGE) v += inlet_if(K, in_m);
-    f[k] = v;
-  });
-  FaceAcc all = yz;
-  if (xface) {
-    all.add(lo_face, a.bc[0], dirs_with<Q>(0, 1));
-    all.add(hi_face, a.bc[1], dirs_with<Q>(0, -1));
+  template <typename K>
+  __device__ __forceinline__ char *slot(K kk, uint32_t ownmask) const {
+    if constexpr (PAR == 0) {
+      return own(kk);
+    } else {
+      char *const ps = src_base(kk) + src_lane(kk);
+      if constexpr (!EDGE) {
+        return ps;  // interior rows have no y/z face directions
+      } else {
+        // both addresses formed first: the choice is between values (a
+        // choice between two members would keep the object in private memory)
+        char *const po = own(kk);
+        return ((ownmask >> (int)K::value) & 1u) ? po : ps;
+      }
+    }
+  }
+  template <typename K>
+  __device__ __forceinline__ R inlet_if(K, uint32_t inmask) const {
+    const R t = inlet_term<Q, R>(a, (int)K::value);
+    return ((inmask >> (int)K::value) & 1u) ? t : R(0);
+  }
+
+  // incoming populations f_k of the cell: the row's pattern (load_row),
+  // then the x-face corrections of the row's first and last cell (load_fix)
+  __device__ __forceinline__ void load(R f[Q]) const {
+    load_row(f);
+    load_fix(f);
+  }
+  __device__ __forceinline__ void load_row(R f[Q]) const {
+    sfor<Q>([&](auto K) {
+      constexpr int k = K;
+      R v = ldv<T, R>(slot(K, own_m));
+      if constexpr (PAR == 1 && EDGE) v += inlet_if(K, in_m);
+      f[k] = v;
+    });
+  }
+  __device__ __forceinline__ void load_fix(R f[Q]) const {
     if constexpr (PAR == 1) {
-      // odd parity: directions whose rule the x faces change re-read the
-      // cell's own slot
-      const uint32_t own_x = all.own(), in_x = all.inlet();
-      const uint32_t redo = (own_x ^ own_m) | (in_x ^ in_m);
+      if (xface) {
+        // odd parity: directions whose rule the x faces change re-read the
+        // cell's own slot
+        const uint32_t own_x = all.own(), in_x = all.inlet();
+        const uint32_t redo = (own_x ^ own_m) | (in_x ^ in_m);
+        sfor<Q>([&](auto K) {
+          constexpr int k = K;
+          if ((redo >> k) & 1u) {
+            R v = ldv<T, R>(own(K));
+            if ((in_x >> k) & 1u) v += inlet_term<Q, R>(a, k);
+            f[k] = v;
+          }
+        });
+      }
+    }
+  }
+
+  // post-collision populations back, with the face rules
+  __device__ __forceinline__ void store(const R f[Q]) const {
+    auto put = [&](auto K, uint32_t ownmask, uint32_t inmask, uint32_t outmask) {
+      constexpr int k = K;
+      R v = ((outmask >> k) & 1u) ? f[k] : f[opp<Q>(k)];
+      if constexpr (PAR == 1) v += inlet_if(K, inmask);
+      stv<T, R>(slot(K, ownmask), v);
+    };
+    if (!xface) {
+      sfor<Q>([&](auto K) { put(K, own_m, in_m, out_m); });
+    } else {
+      // first or last cell of a row with a non-periodic x: a direction whose
+      // source lies beyond the x face takes the merged rule, in its own
+      // slot.  (Written with branches, unlike the row's path, so that the
+      // compiler keeps the two paths apart instead of turning the row's
+      // stores into per-lane selects.)
+      const uint32_t own_x = all.own(), in_x = all.inlet(), out_x = all.outlet();
+      const uint32_t changed = (own_x ^ own_m) | (in_x ^ in_m) | (out_x ^ out_m);
       sfor<Q>([&](auto K) {
         constexpr int k = K;
-        if ((redo >> k) & 1u) {
-          R v = ldv<T, R>(own(K));
-          if ((in_x >> k) & 1u) v += inlet_term<Q, R>(a, k);
-          f[k] = v;
+        if constexpr (cx<Q>(k) == 0) {
+          put(K, own_m, in_m, out_m);
+        } else {
+          if ((changed >> k) & 1u) {
+            R v = ((out_x >> k) & 1u) ? f[k] : f[opp<Q>(k)];
+            if constexpr (PAR == 1) {
+              if ((in_x >> k) & 1u) v += inlet_term<Q, R>(a, k);
+            }
+            stv<T, R>(own(K), v);
+          } else {
+            put(K, own_m, in_m, out_m);
+          }
         }
       });
     }
   }
+};
+
+template <int Q, typename T, int PAR, bool EDGE>
+__device__ __forceinline__ void fluid_row_cell(const SCArgs &a, int x, int y, int z, size_t rowbase) {
+  using R = typename Comp<T>::type;
+  const RowCell<Q, T, PAR, EDGE> c(a, x, y, z, rowbase);
+  R f[Q];
+  c.load(f);
   R z3[3] = {0, 0, 0}, m0[3] = {0, 0, 0}, m1[3] = {0, 0, 0};
   collide<Q, 1, 0, R>(f, a, R(0), z3, R(0), z3, m0, m1);
-  auto put = [&](auto K, uint32_t ownmask, uint32_t inmask, uint32_t outmask) {
-    constexpr int k = K;
-    R v = ((outmask >> k) & 1u) ? f[k] : f[opp<Q>(k)];
-    if constexpr (PAR == 1) v += inlet_if(K, inmask);
-    stv<T, R>(slot(K, ownmask), v);
-  };
-  if (!xface) {
-    sfor<Q>([&](auto K) { put(K, own_m, in_m, out_m); });
-  } else {
-    const uint32_t own_x = all.own(), in_x = all.inlet(), out_x = all.outlet();
-    sfor<Q>([&](auto K) { put(K, own_x, in_x, out_x); });
-  }
+  c.store(f);
 }
 
 // A wave's cell: skip lanes past the row end and, with PSM, cells whose B is
@@ -474,44 +549,34 @@ __device__ __forceinline__ void edge_block(const SCArgs &a, uint32_t bid) {
   fluid_row_cell<Q, T, PAR, true>(a, x, y, z, rowbase);
 }
 
-// Interior rows (1 <= y <= ny-2, 1 <= z <= nz-2), TY rows of TX cells per block.
+// Interior rows (1 <= y <= ny-2, 1 <= z <= nz-2), TY rows of TX cells per
+// workgroup.
 template <int Q, typename T, int PAR, bool PSM>
 __global__ __launch_bounds__(256) void k_fluid(const SCArgs a) {
+  using R = typename Comp<T>::type;
   const int tid = threadIdx.x;
   if constexpr (PAR == 0 && Q == 19) {
     // even D3Q19 steps: the rows on the y/z faces ride along as extra blocks
     // (there the edge path needs no more registers than the interior one)
-    if (a.fsel == 0 && blockIdx.x >= a.ntiles_i) {
+    if (blockIdx.x >= a.ntiles_i) {
       edge_block<Q, T, PAR, PSM>(a, blockIdx.x - a.ntiles_i);
       return;
     }
   }
-  int txi, tyi, z;
-  if (a.fsel == 2) {  // grid = the near range
-    uint32_t b = blockIdx.x;
-    txi = a.near_lo[0] + (int)(b % (uint32_t)a.near_n[0]);
-    b /= (uint32_t)a.near_n[0];
-    tyi = a.near_lo[1] + (int)(b % (uint32_t)a.near_n[1]);
-    z = 1 + a.near_lo[2] + (int)(b / (uint32_t)a.near_n[1]);
-  } else {
-    const uint32_t tile = a.xcd_remap ? xcd_remap(blockIdx.x, a.ntiles_i) : blockIdx.x;
-    txi = (int)(tile % (uint32_t)a.ntx);
-    const uint32_t rr = tile / (uint32_t)a.ntx;
-    tyi = (int)(rr % (uint32_t)a.nty_i);
-    z = 1 + (int)(rr / (uint32_t)a.nty_i);
-    if (a.fsel == 1 && (unsigned)(txi - a.near_lo[0]) < (unsigned)a.near_n[0] &&
-        (unsigned)(tyi - a.near_lo[1]) < (unsigned)a.near_n[1] &&
-        (unsigned)(z - 1 - a.near_lo[2]) < (unsigned)a.near_n[2])
-      return;
-  }
+  const uint32_t tile = a.xcd_remap ? xcd_remap(blockIdx.x, a.ntiles_i) : blockIdx.x;
+  const int txi = (int)(tile % (uint32_t)a.ntx);
+  const uint32_t rr = tile / (uint32_t)a.ntx;
+  const int tyi = (int)(rr % (uint32_t)a.nty_i);
+  const int z = 1 + (int)(rr / (uint32_t)a.nty_i);
   const int x = txi * a.TX + (tid & (a.TX - 1));
   // TX >= 64: the row is the same over the wave
   const int y = __builtin_amdgcn_readfirstlane(1 + tyi * a.TY + (tid >> a.lTX));
   if (y > a.ny - 2) return;
   const size_t rowbase = (size_t)a.nx * (size_t)y + (size_t)a.nx * (size_t)a.ny * (size_t)z;
-  if (!fluid_lane<typename Comp<T>::type, PSM>(a, x, y, z, rowbase)) return;
+  if (!fluid_lane<R, PSM>(a, x, y, z, rowbase)) return;
   fluid_row_cell<Q, T, PAR, false>(a, x, y, z, rowbase);
 }
+
 
 template <int Q, typename T, int PAR, bool PSM>
 __global__ __launch_bounds__(256) void k_fluid_edge(const SCArgs a) {

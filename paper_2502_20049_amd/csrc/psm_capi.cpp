@@ -21,9 +21,9 @@ int hip_fail(hipError_t e, const char *what) {
 }
 
 hipError_t launch_adjoint(const psm_field &f, const AdjArgs &A, hipStream_t st);
-hipError_t launch_sc_f64(const psm_config &, const SCArgs &, int, int, hipStream_t, int *);
-hipError_t launch_sc_f32(const psm_config &, const SCArgs &, int, int, hipStream_t, int *);
-hipError_t launch_sc_f16(const psm_config &, const SCArgs &, int, int, hipStream_t, int *);
+hipError_t launch_sc_f64(const psm_config &, const SCArgs &, int, hipStream_t, int *);
+hipError_t launch_sc_f32(const psm_config &, const SCArgs &, int, hipStream_t, int *);
+hipError_t launch_sc_f16(const psm_config &, const SCArgs &, int, hipStream_t, int *);
 
 static size_t storage_size(int st) { return st == PSM_F64 ? 8 : (st == PSM_F32 ? 4 : 2); }
 
@@ -278,7 +278,6 @@ int pdf_field_create(const psm_config *cfg, void *pdf, size_t pdf_bytes, void *b
   f->ntiles = L.ntiles;
   for (int i = 0; i < PSM_MAX_BODIES; ++i) f->active[i] = empty_box();
   f->opt_xcd_remap = 0;
-  f->opt_overlap = 0;
   f->map_list_cap = cfg->psm ? (int)MAP_LIST_CAP : 0;
   if (hipGetDevice(&f->device) != hipSuccess) f->device = -1;
   {
@@ -289,29 +288,12 @@ int pdf_field_create(const psm_config *cfg, void *pdf, size_t pdf_bytes, void *b
       return hip_fail(e, "pdf_field_create: clear");
     }
   }
-  if (cfg->psm) {
-    hipError_t e = hipStreamCreateWithFlags(&f->side, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&f->ev_prev, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&f->ev_map, hipEventDisableTiming);
-    if (e != hipSuccess) {
-      if (f->ev_prev) (void)hipEventDestroy(f->ev_prev);
-      if (f->side) (void)hipStreamDestroy(f->side);
-      delete f;
-      return hip_fail(e, "pdf_field_create: stream/event");
-    }
-  }
   *out = f;
   return PSM_OK;
 }
 
 int pdf_field_destroy(psm_field *f) {
   if (!f) return set_error("null handle"), PSM_EINVAL;
-  if (f->side) {
-    (void)hipStreamSynchronize(f->side);
-    (void)hipStreamDestroy(f->side);
-  }
-  if (f->ev_prev) (void)hipEventDestroy(f->ev_prev);
-  if (f->ev_map) (void)hipEventDestroy(f->ev_map);
   delete f;
   return PSM_OK;
 }
@@ -652,49 +634,18 @@ static int sc_plan(psm_field *f, const psm_body *bodies, int nb, int64_t step, c
   return PSM_OK;
 }
 
-static int sc_launch(psm_field *f, const SCArgs &a, int64_t step, int phase, hipStream_t st) {
+static int sc_launch(psm_field *f, const SCArgs &a, int64_t step, hipStream_t st) {
   const int parity = (int)(step & 1);
   hipError_t e;
   int sb = 0;
   switch (f->cfg.storage) {
-    case PSM_F64: e = launch_sc_f64(f->cfg, a, parity, phase, st, &sb); break;
-    case PSM_F32: e = launch_sc_f32(f->cfg, a, parity, phase, st, &sb); break;
-    default: e = launch_sc_f16(f->cfg, a, parity, phase, st, &sb); break;
+    case PSM_F64: e = launch_sc_f64(f->cfg, a, parity, st, &sb); break;
+    case PSM_F32: e = launch_sc_f32(f->cfg, a, parity, st, &sb); break;
+    default: e = launch_sc_f16(f->cfg, a, parity, st, &sb); break;
   }
   if (e != hipSuccess) return hip_fail(e, "psm_stream_collide launch");
-  if (phase != 1) f->solid_blocks = sb;
+  f->solid_blocks = sb;
   return PSM_OK;
-}
-
-// Interior tiles (tile x, tile row, z-1) that touch any body box: their
-// bounding range.  Tiles outside it never read B.
-static void near_range(const psm_field &f, SCArgs &a) {
-  int lo[3] = {INT32_MAX, INT32_MAX, INT32_MAX}, hi[3] = {-1, -1, -1};
-  bool any = false;
-  for (int b = 0; b < a.nbox; ++b) {
-    const IBox &B = a.box[b];
-    if (box_empty(B)) continue;
-    const int ylo = std::max(B.lo[1], 1), yhi = std::min(B.hi[1], f.cfg.ny - 2);
-    const int zlo = std::max(B.lo[2], 1), zhi = std::min(B.hi[2], f.cfg.nz - 2);
-    if (ylo > yhi || zlo > zhi) continue;
-    any = true;
-    lo[0] = std::min(lo[0], B.lo[0] / f.TX);
-    hi[0] = std::max(hi[0], B.hi[0] / f.TX);
-    lo[1] = std::min(lo[1], (ylo - 1) / f.TY);
-    hi[1] = std::max(hi[1], (yhi - 1) / f.TY);
-    lo[2] = std::min(lo[2], zlo - 1);
-    hi[2] = std::max(hi[2], zhi - 1);
-  }
-  if (!any) {
-    for (int d = 0; d < 3; ++d) a.near_lo[d] = a.near_n[d] = 0;
-    a.near_tiles = 0;
-    return;
-  }
-  for (int d = 0; d < 3; ++d) {
-    a.near_lo[d] = lo[d];
-    a.near_n[d] = hi[d] - lo[d] + 1;
-  }
-  a.near_tiles = (uint32_t)a.near_n[0] * (uint32_t)a.near_n[1] * (uint32_t)a.near_n[2];
 }
 
 int geometry_map_step(psm_field *f, const psm_body *bodies, const psm_geom *const *geoms, int nb, void *stream) {
@@ -714,71 +665,21 @@ int psm_stream_collide(psm_field *f, const psm_body *bodies, int nb, int64_t ste
   SCArgs a;
   int r = sc_plan(f, bodies, nb, step, f->active, a);
   if (r) return r;
-  return sc_launch(f, a, step, 0, (hipStream_t)stream);
+  return sc_launch(f, a, step, (hipStream_t)stream);
 }
 
 int psm_step(psm_field *f, const psm_body *map_poses, const psm_body *bodies, const psm_geom *const *geoms, int nb,
              int64_t step, double *ft_dev, void *stream) {
   if (!f) return set_error("null handle"), PSM_EINVAL;
-  hipStream_t st = (hipStream_t)stream;
   if (!f->cfg.psm || nb == 0) {
     if (ft_dev) return set_error("psm_step: force/torque needs bodies"), PSM_EINVAL;
     return psm_stream_collide(f, bodies, nb, step, stream);
   }
   if (!map_poses) map_poses = bodies;
-  if (f->opt_general_path || f->opt_whole_domain || !f->side) {
-    int r = geometry_map_step(f, map_poses, geoms, nb, stream);
-    if (!r) r = psm_stream_collide(f, bodies, nb, step, stream);
-    if (!r && ft_dev) r = body_force_torque(f, nb, ft_dev, stream);
-    return r;
-  }
-  MapPlan P;
-  int r = map_plan(f, map_poses, geoms, nb, P);
-  if (r) return r;
-  SCArgs a;
-  r = sc_plan(f, bodies, nb, step, P.now, a);
-  if (r) return r;
-  near_range(*f, a);
-  hipError_t e = hipSuccess;
-  if (f->opt_overlap == 1) {
-    // the mapping follows the previous step directly on the caller's stream,
-    // so its workgroups are resident first; the tiles that need no B run on
-    // the field's stream after an event that marks the end of the previous
-    // step (which still reads B)
-    e = hipEventRecord(f->ev_prev, st);
-    if (e == hipSuccess) e = hipStreamWaitEvent(f->side, f->ev_prev, 0);
-    if (e != hipSuccess) return hip_fail(e, "psm_step: event");
-    r = sc_launch(f, a, step, 1, f->side);
-    if (r) return r;
-    e = hipEventRecord(f->ev_map, f->side);
-    if (e == hipSuccess) e = launch_map(P.a, P.maxcells, 0, st);
-    if (e == hipSuccess) e = hipStreamWaitEvent(st, f->ev_map, 0);
-  } else if (f->opt_overlap == 2) {
-    // the other way round: the mapping on the field's stream
-    e = hipEventRecord(f->ev_prev, st);
-    if (e != hipSuccess) return hip_fail(e, "psm_step: event");
-    r = sc_launch(f, a, step, 1, st);
-    if (r) return r;
-    e = hipStreamWaitEvent(f->side, f->ev_prev, 0);
-    if (e == hipSuccess) e = launch_map(P.a, P.maxcells, 0, f->side);
-    if (e == hipSuccess) e = hipEventRecord(f->ev_map, f->side);
-    if (e == hipSuccess) e = hipStreamWaitEvent(st, f->ev_map, 0);
-  } else {
-    // no overlap: the mapping, then the whole stream-collide
-    e = launch_map(P.a, P.maxcells, 0, st);
-    if (e != hipSuccess) return hip_fail(e, "psm_step: mapping");
-    map_commit(f, P);
-    r = sc_launch(f, a, step, 0, st);
-    if (r) return r;
-    if (ft_dev) return body_force_torque(f, nb, ft_dev, stream);
-    return PSM_OK;
-  }
-  if (e != hipSuccess) return hip_fail(e, "psm_step: mapping");
-  map_commit(f, P);
-  r = sc_launch(f, a, step, 2, st);
-  if (r) return r;
-  if (ft_dev) return body_force_torque(f, nb, ft_dev, stream);
-  return PSM_OK;
+  int r = geometry_map_step(f, map_poses, geoms, nb, stream);
+  if (!r) r = psm_stream_collide(f, bodies, nb, step, stream);
+  if (!r && ft_dev) r = body_force_torque(f, nb, ft_dev, stream);
+  return r;
 }
 
 int body_force_torque(psm_field *f, int nb, double *ft, void *stream) {
@@ -814,10 +715,6 @@ int psm_set_option(psm_field *f, int option, int value) {
       if (value < 0 || (uint32_t)value > MAP_LIST_CAP)
         return set_error("PSM_OPT_MAP_LIST takes 0 .. the list capacity"), PSM_EINVAL;
       f->map_list_cap = value;
-      return PSM_OK;
-    case PSM_OPT_OVERLAP:
-      if (value < 0 || value > 2) return set_error("PSM_OPT_OVERLAP takes 0, 1 or 2"), PSM_EINVAL;
-      f->opt_overlap = value;
       return PSM_OK;
   }
   return set_error("unknown option"), PSM_EINVAL;

@@ -104,13 +104,6 @@ struct SCArgs {
   int nfrows;         // rows with y or z on a face
   uint32_t ntiles_e;  // ntx * ceil(nfrows / TY): blocks of the edge kernel
   int general;        // PSM_OPT_GENERAL_PATH: every cell through the general kernel
-  // interior-tile selection: 0 every tile; 1 tiles outside the near range
-  // only; 2 tiles inside it only (grid = its tile count).  The near range
-  // (tile x, tile row, z-1; start and count) covers every tile that touches
-  // a body box, so tiles outside it never read B.
-  int fsel;
-  int near_lo[3], near_n[3];
-  uint32_t near_tiles;
   int bc[6];
   int periodic[3];
   double u_in_d[3];
@@ -210,13 +203,8 @@ struct psm_field {
   int device;
   int opt_general_path;
   int opt_xcd_remap;
-  int opt_overlap;       // psm_step schedule (PSM_OPT_OVERLAP)
   int opt_whole_domain;  // B may be nonzero anywhere (offset field set)
   const float *dB;       // caller-owned offset added to the slot-0 fraction
-  // psm_step: a second stream on which the mapping overlaps the bulk of the
-  // stream-collide, and the two events that order it
-  hipStream_t side;
-  hipEvent_t ev_prev, ev_map;
 };
 
 struct psm_geom {

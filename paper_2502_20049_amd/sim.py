@@ -110,7 +110,7 @@ class Field:
     """One lattice on the current device; ``wl`` is a psm_inputs.Workload."""
 
     def __init__(self, wl, storage=None, psm=True, slots=None, max_bodies=None, device="cuda", remap_every_step=True,
-                 overlap=True):
+                 fused=True):
         self.wl = wl
         self.storage = storage or wl.storage
         self.cfg = make_config(wl, self.storage, psm, slots, max_bodies)
@@ -134,7 +134,7 @@ class Field:
         self._geom_ptrs = (C.c_void_p * max(1, len(self.geoms)))(*[g.handle.value for g in self.geoms])
         self.nb = len(self.bodies)
         self.remap_every_step = remap_every_step
-        self.overlap = overlap  # one psm_step call per step (mapping beside the bulk update)
+        self.fused = fused  # one psm_step call per step
         self._mapped_once = False
         self.ft = torch.zeros((max(1, self.nb), 6), dtype=torch.float64, device=device)
         self.reset()
@@ -179,7 +179,7 @@ class Field:
         to t+1; with ``ft`` (a (n_bodies, 6) float64 device tensor) also sum the
         force/torque of the step into it."""
         poses = poses if poses is not None else (self.poses(t) if self.nb else None)
-        if self.nb and self.overlap and (self.remap_every_step or not self._mapped_once):
+        if self.nb and self.fused and (self.remap_every_step or not self._mapped_once):
             check(lib.psm_step(self.handle, poses, poses, self._geom_ptrs, self.nb, int(t),
                                C.c_void_p(ft.data_ptr()) if ft is not None else None, _stream()), "psm_step")
             self._mapped_once = True

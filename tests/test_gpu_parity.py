@@ -139,9 +139,9 @@ def test_fast_path_bitwise_equals_general_path(orc, sim, gc, storage):
 
 @pytest.mark.parametrize("case", ["two_bodies_mixed", "channel_96", "plain_static"])
 def test_psm_step_equals_separate_calls(sim, gc, case):
-    """psm_step (mapping on the field's second stream beside the tiles away
-    from the bodies) against geometry_map_step + psm_stream_collide +
-    body_force_torque in order: bit-identical PDFs, fractions and F/T."""
+    """psm_step against geometry_map_step + psm_stream_collide +
+    body_force_torque called one by one: bit-identical PDFs, fractions and
+    F/T."""
     import torch
 
     _say(f"[psm_step] {case}")
@@ -153,10 +153,8 @@ def test_psm_step_equals_separate_calls(sim, gc, case):
     else:
         wl, steps = pi.workload_sphere32(storage="f32"), 4
     res = []
-    for mode in (None, 0, 1, 2):  # None: separate calls; else the psm_step schedule
-        f = sim.Field(wl, overlap=mode is not None, remap_every_step=case != "plain_static")
-        if mode is not None:
-            f.set_option(3, mode)
+    for fused in (False, True):
+        f = sim.Field(wl, fused=fused, remap_every_step=case != "plain_static")
         gc.load_random_state(f, 11)
         fts = []
         for t in range(steps):
