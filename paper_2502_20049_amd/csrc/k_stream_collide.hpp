@@ -64,6 +64,22 @@ __device__ __forceinline__ void stv(char *p, R v) {
   *(T *)p = (T)v;
 }
 
+// Whole-wave lane shifts (DPP wave_shr:1 / wave_shl:1): lane i receives lane
+// i-1 (shr) or lane i+1 (shl); the lane without a source gets 0.  Every lane
+// of the wave must be active.
+__device__ __forceinline__ float wave_shr1(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float wave_shl1(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, false));
+}
+__device__ __forceinline__ bool wave_shr1(bool b) {
+  return __builtin_amdgcn_update_dpp(0, b ? 1 : 0, 0x138, 0xf, 0xf, false) != 0;
+}
+__device__ __forceinline__ bool wave_shl1(bool b) {
+  return __builtin_amdgcn_update_dpp(0, b ? 1 : 0, 0x130, 0xf, 0xf, false) != 0;
+}
+
 // Per-cell collision: TRT + Guo fluid collision blended with NS solid slots.
 // f holds deviations delta f; on return f holds the post-collision deviations.
 template <int Q, int SC, int NS, typename R>
@@ -547,6 +563,155 @@ __device__ __forceinline__ void edge_block(const SCArgs &a, uint32_t bid) {
   const size_t rowbase = (size_t)a.nx * (size_t)y + (size_t)a.nx * (size_t)a.ny * (size_t)z;
   if (!fluid_lane<typename Comp<T>::type, PSM>(a, x, y, z, rowbase)) return;
   fluid_row_cell<Q, T, PAR, true>(a, x, y, z, rowbase);
+}
+
+// Odd step, 16-bit storage, interior rows: a wave takes 128 consecutive
+// cells of a row, two per lane (xa = x0 + 2 lane, xb = xa + 1), so every
+// slot access is a 4-byte pair (2-byte accesses to y/z-shifted rows run at
+// ~3 TB/s, 4-byte ones at ~5 TB/s on this chip).  The directions with
+// c_kx != 0 need the pair shifted by one cell: the missing half comes from the
+// neighbouring lane by DPP, and the wave's two edge elements (x0 - 1 and
+// x0 + 128) are read and written one element each.  Every lane of the wave
+// must be active; only active cells (fluid, in the row) store, and a value is
+// stored only if its own cell is active.
+template <int Q, bool PSM>
+__device__ __forceinline__ void fluid_seg_h2(const SCArgs &a, int x0, int y, int z, size_t rowbase) {
+  using T = _Float16;
+  using R = float;
+  typedef _Float16 H2 __attribute__((ext_vector_type(2)));
+  auto shr_pair = [](H2 v) {  // lane i <- lane i-1
+    return __builtin_bit_cast(H2, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x138, 0xf, 0xf, false));
+  };
+  auto shl_pair = [](H2 v) {  // lane i <- lane i+1
+    return __builtin_bit_cast(H2, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x130, 0xf, 0xf, false));
+  };
+  const int lane = threadIdx.x & 63;
+  const int xa = x0 + 2 * lane, xb = xa + 1;
+  const bool acta = fluid_lane<R, PSM>(a, xa, y, z, rowbase);
+  const bool actb = fluid_lane<R, PSM>(a, xb, y, z, rowbase);
+  const RowCell<Q, T, 1, false> ca(a, xa, y, z, rowbase), cb(a, xb, y, z, rowbase);
+  const uint32_t oa = ca.o0;                                      // byte offset of the pair
+  const uint32_t om0 = __builtin_amdgcn_readfirstlane(ca.om);     // element x0 - 1 (wrapped / clamped)
+  const uint32_t op63 = __builtin_amdgcn_readlane(cb.op, 63);     // element x0 + 128
+  // the aligned source pairs, and the wave's edge elements (kept in storage
+  // precision until each cell needs them)
+  H2 p[Q];
+  T e[Q];
+  sfor<Q>([&](auto K) {
+    constexpr int k = K;
+    constexpr int ex = cx<Q>(k);
+    char *const rowk = ca.src_base(K);
+    p[k] = *(const H2 *)(rowk + oa);
+    if constexpr (ex != 0) e[k] = *(const T *)(rowk + (ex == 1 ? om0 : op63));
+  });
+  auto changed_of = [&](const RowCell<Q, T, 1, false> &c) -> uint32_t {
+    return c.xface ? (c.all.own() ^ c.own_m) | (c.all.inlet() ^ c.in_m) | (c.all.outlet() ^ c.out_m) : 0u;
+  };
+  // first or last cell of a row with a non-periodic x: the directions the x
+  // face changes take the merged rule in the cell's own slot
+  auto face_store = [&](const RowCell<Q, T, 1, false> &c, const R *f, uint32_t ch) {
+    const uint32_t in_x = c.all.inlet(), out_x = c.all.outlet();
+    sfor<Q>([&](auto K) {
+      constexpr int k = K;
+      if constexpr (cx<Q>(k) != 0) {
+        if ((ch >> k) & 1u) {
+          R v = ((out_x >> k) & 1u) ? f[k] : f[opp<Q>(k)];
+          if ((in_x >> k) & 1u) v += inlet_term<Q, R>(a, k);
+          stv<T, R>(c.own(K), v);
+        }
+      }
+    });
+  };
+  const uint32_t cha = changed_of(ca), chb = changed_of(cb);
+  R z3[3] = {0, 0, 0}, m0[3] = {0, 0, 0}, m1[3] = {0, 0, 0};
+  H2 o[Q];  // post-collision values to store: .x cell a, .y cell b
+  {
+    R f[Q];
+    sfor<Q>([&](auto K) {
+      constexpr int k = K;
+      constexpr int ex = cx<Q>(k);
+      if constexpr (ex == 0) {
+        f[k] = (R)p[k].x;  // source xa
+      } else if constexpr (ex == 1) {
+        const H2 sh = shr_pair(p[k]);  // source xa - 1: high half of the previous pair
+        f[k] = (R)(lane == 0 ? e[k] : sh.y);
+      } else {
+        f[k] = (R)p[k].y;  // source xa + 1
+      }
+    });
+    ca.load_fix(f);
+    collide<Q, 1, 0, R>(f, a, R(0), z3, R(0), z3, m0, m1);
+    sfor<Q>([&](auto K) { o[(int)K].x = (T)f[opp<Q>((int)K)]; });
+    if (ca.xface && acta) face_store(ca, f, cha);
+  }
+  {
+    R f[Q];
+    sfor<Q>([&](auto K) {
+      constexpr int k = K;
+      constexpr int ex = cx<Q>(k);
+      if constexpr (ex == 0) {
+        f[k] = (R)p[k].y;  // source xb
+      } else if constexpr (ex == 1) {
+        f[k] = (R)p[k].x;  // source xb - 1 = xa
+      } else {
+        const H2 sh = shl_pair(p[k]);  // source xb + 1: low half of the next pair
+        f[k] = (R)(lane == 63 ? e[k] : sh.x);
+      }
+    });
+    cb.load_fix(f);
+    collide<Q, 1, 0, R>(f, a, R(0), z3, R(0), z3, m0, m1);
+    sfor<Q>([&](auto K) { o[(int)K].y = (T)f[opp<Q>((int)K)]; });
+    if (cb.xface && actb) face_store(cb, f, chb);
+  }
+  const bool acta_n = wave_shl1(acta), actb_p = wave_shr1(actb);
+  auto put2 = [&](char *q, T lo, bool lo_ok, T hi, bool hi_ok) {
+    if (lo_ok && hi_ok) {
+      H2 v;
+      v.x = lo;
+      v.y = hi;
+      *(H2 *)q = v;
+    } else {
+      if (lo_ok) *(T *)q = lo;
+      if (hi_ok) *(T *)(q + sizeof(T)) = hi;
+    }
+  };
+  sfor<Q>([&](auto K) {
+    constexpr int k = K;
+    constexpr int ex = cx<Q>(k);
+    char *const rowk = ca.src_base(K);
+    if constexpr (ex == 0) {
+      put2(rowk + oa, o[k].x, acta, o[k].y, actb);
+    } else if constexpr (ex == 1) {
+      // element xa <- cell b, element xa + 1 <- cell a of the next lane,
+      // element x0 - 1 <- cell a of lane 0
+      const H2 nx_ = shl_pair(o[k]);
+      put2(rowk + oa, o[k].y, actb, nx_.x, lane < 63 && acta_n);
+      if (lane == 0 && acta && !((cha >> k) & 1u)) *(T *)(rowk + om0) = o[k].x;
+    } else {
+      // element xa <- cell b of the previous lane, element xa + 1 <- cell a,
+      // element x0 + 128 <- cell b of lane 63
+      const H2 pv = shr_pair(o[k]);
+      put2(rowk + oa, pv.y, lane > 0 && actb_p, o[k].x, acta);
+      if (lane == 63 && actb && !((chb >> k) & 1u)) *(T *)(rowk + op63) = o[k].y;
+    }
+  });
+}
+
+// Odd steps with 16-bit storage and rows of a multiple of 128 cells:
+// interior rows in segments of 128 cells, one segment per wave
+// (fluid_seg_h2).  Other row lengths take k_fluid.
+template <int Q, bool PSM>
+__global__ __launch_bounds__(256) void k_fluid_h2odd(const SCArgs a) {
+  const int nsx = a.nx / 128;
+  const uint32_t seg = blockIdx.x * 4u + (threadIdx.x >> 6);
+  const uint32_t nseg = (uint32_t)nsx * (uint32_t)(a.ny - 2) * (uint32_t)(a.nz - 2);
+  if (seg >= nseg) return;  // wave-uniform
+  const int sx = (int)(seg % (uint32_t)nsx);
+  const uint32_t r = seg / (uint32_t)nsx;
+  const int y = 1 + (int)(r % (uint32_t)(a.ny - 2));
+  const int z = 1 + (int)(r / (uint32_t)(a.ny - 2));
+  const size_t rowbase = (size_t)a.nx * (size_t)y + (size_t)a.nx * (size_t)a.ny * (size_t)z;
+  fluid_seg_h2<Q, PSM>(a, sx * 128, y, z, rowbase);
 }
 
 // Interior rows (1 <= y <= ny-2, 1 <= z <= nz-2), TY rows of TX cells per

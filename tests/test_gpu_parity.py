@@ -169,6 +169,33 @@ def test_psm_step_equals_separate_calls(sim, gc, case):
             assert torch.equal(a, b)
 
 
+@pytest.mark.parametrize("nx", [256, 300])
+@pytest.mark.parametrize("bc", ["channel", "periodic"])
+@pytest.mark.parametrize("storage", ["f16", "f32"])
+def test_wide_rows(orc, sim, gc, nx, bc, storage):
+    """Rows of full 64/128-cell segments (and a partial one at nx = 300), with
+    a body in the row: two steps against the oracle, then four steps of the
+    fast path against the general path bit for bit."""
+    import torch
+
+    _say(f"[wide rows] nx={nx} {bc} {storage}")
+    body = pi.Body(pi.Shape("ellipsoid", (9.0, 4.0, 3.0)),
+                   pi.Motion(axis=(0.0, 0.6, 0.8), theta0=0.3, omega=0.05, x0=(130.0, 5.0, 4.0)), s=2)
+    wl = pi.Workload(f"wide_{nx}_{bc}_{storage}", nx, 10, 8, 19, storage, 0.8, 3 / 16, (1e-5, 0, 0), BCS[bc],
+                     (0.04, 0.01, -0.02), 1, 0, 1, 2, [body])
+    _two_step_compare(orc, sim, gc, wl)
+    res = []
+    for general in (False, True):
+        f = sim.Field(wl)
+        f.set_option(1, 1 if general else 0)
+        gc.load_random_state(f, 13)
+        for t in range(4):
+            f.step(t)
+        torch.cuda.synchronize()
+        res.append(f.pdf_view().clone())
+    assert torch.equal(res[0], res[1])
+
+
 def test_xcd_remap_bitwise_identical(sim, gc):
     import torch
 
