@@ -254,8 +254,7 @@ def adjoint_rate(steps=800, window=200):
     N = wl.n_cells
     return {"case": f"{wl.name}, {steps} steps, window {window}, checkpoint segment {obj.L}",
             "J": J, "dJ_dOmega": gW, "forward_s": round(t1 - t0, 4), "backward_s": round(t2 - t1, 4),
-            "backward_mcell_steps_per_s": round(N * steps / (t2 - t1) / 1e6, 1),
-            "backward_gbs_at_472B": round(472 * N * steps / (t2 - t1) / 1e9, 1)}
+            "backward_mcell_steps_per_s": round(N * steps / (t2 - t1) / 1e6, 1)}
 
 
 def cpu_baseline(wl, nsteps=2):
@@ -283,6 +282,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip variants, copy probe and accuracy")
     ap.add_argument("--only-psm", action="store_true", help="time the PSM path only (for profiling)")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="run only the torque-gradient sweep on the 128^3 rotor (for profiling)")
     ap.add_argument("--copy-only", action="store_true",
                     help="run only the device copy probe (1 GiB read + 1 GiB written per launch): the "
                          "calibration for rocprofv3 FETCH_SIZE / WRITE_SIZE")
@@ -297,6 +298,9 @@ def main():
     from paper_2502_20049_amd import sim
 
     torch.cuda.set_device(0)
+    if args.adjoint_only:
+        print(json.dumps(adjoint_rate()), flush=True)
+        return
     if args.copy_only:
         bw = copy_probe(nbytes=1 << 30, reps=5)
         print(json.dumps({"copy_probe_gbs": round(bw, 1), "bytes_read_per_launch": 1 << 30,

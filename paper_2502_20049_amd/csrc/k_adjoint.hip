@@ -20,151 +20,208 @@ namespace psm {
 
 
 
-template <int Q, typename T>
+// c . v for a lattice direction with compile-time components in {-1, 0, 1}
+// (adds and subtracts only: a product by 0 or +-1 is not folded otherwise).
+template <int EX, int EY, int EZ, typename R>
+__device__ __forceinline__ R cdot(R vx, R vy, R vz) {
+  constexpr int nz = (EX != 0) + (EY != 0) + (EZ != 0);
+  static_assert(nz > 0, "rest direction has no dot product");
+  R s;
+  bool have = false;
+  auto add = [&](int e, R v) {
+    const R t = e > 0 ? v : -v;
+    s = have ? s + t : t;
+    have = true;
+  };
+  if constexpr (EX != 0) add(EX, vx);
+  if constexpr (EY != 0) add(EY, vy);
+  if constexpr (EZ != 0) add(EZ, vz);
+  return s;
+}
+
+// v += k c for a lattice direction c
+template <int EX, int EY, int EZ, typename R>
+__device__ __forceinline__ void cacc(R &vx, R &vy, R &vz, R k) {
+  if constexpr (EX == 1) vx += k;
+  if constexpr (EX == -1) vx -= k;
+  if constexpr (EY == 1) vy += k;
+  if constexpr (EY == -1) vy -= k;
+  if constexpr (EZ == 1) vz += k;
+  if constexpr (EZ == -1) vz -= k;
+}
+
+// Index of the neighbour n + e (periodic wrap; w holds the per-cell wrap
+// corrections for +x, -x, +y, -y, +z, -z, zero away from the faces).  uint32
+// arithmetic: every field has fewer than 2^32 cells.
+template <int EX, int EY, int EZ>
+__device__ __forceinline__ uint32_t nbr(uint32_t n, uint32_t nx, uint32_t nxy, const uint32_t (&w)[6]) {
+  uint32_t m = n;
+  if constexpr (EX == 1) m += 1u + w[0];
+  if constexpr (EX == -1) m += w[1] - 1u;
+  if constexpr (EY == 1) m += nx + w[2];
+  if constexpr (EY == -1) m += w[3] - nx;
+  if constexpr (EZ == 1) m += nxy + w[4];
+  if constexpr (EZ == -1) m += w[5] - nxy;
+  return m;
+}
+
+// The step is written over opposite pairs (i, ib): for any per-direction
+// vectors a, b, a_i b_i + a_ib b_ib = 2 (a+ b+ + a- b-) with a+- = (a_i +- a_ib)/2,
+// and feq, the Guo term and their u-derivatives split into even and odd parts
+// with c_ib = -c_i.  With phi_i = feq_i / rho, for any v:
+//   sum_i v_i phi_i          = (1 - 3/2 u^2) W(v) + sum_pairs w [9 v+ cu^2 + 6 v- cu]
+//   sum_i v_i dfeq_i/du / rho = sum_pairs w (6 v- + 18 v+ cu) c - 3 u W(v)
+// where W(v) = sum_i w_i v_i and cu = c.u over the pair's first direction.  The
+// fluid part takes v = b (b+ = le g+, b- = lo g-), the solid part v_i = sh_ib
+// (v+ = sh+, v- = -sh-) at u and v = sh at u_s, the Guo derivative
+// dS_i/du = w (-3 F + 9 (c.F) c) is even.  Collecting terms,
+//   fhat_j = gh_j - (1 - B) b_j + (sh_jb - sh_j) + C0 + V . c_j
+// with one scalar C0 and one vector V per cell, both sums over the pairs.
+template <int Q, typename T, int PAR>
 __global__ __launch_bounds__(256) void k_adjoint(const AdjArgs A) {
   using R = typename Comp<T>::type;
+  constexpr int H = Lat<Q>::H;
   const SCArgs &a = A.s;
-  const uint64_t n = (uint64_t)blockIdx.x * 256u + threadIdx.x;
-  const bool act = n < (uint64_t)a.N;
+  const uint64_t n64 = (uint64_t)blockIdx.x * 256u + threadIdx.x;
   double dom = 0.0;
-  if (act) {
-    const int x = (int)(n % (uint64_t)a.nx);
-    const int y = (int)((n / (uint64_t)a.nx) % (uint64_t)a.ny);
-    const int z = (int)(n / ((uint64_t)a.nx * (uint64_t)a.ny));
-    const uint64_t N = a.N;
+  if (n64 < (uint64_t)a.N) {
+    const uint32_t n = (uint32_t)n64, N = (uint32_t)a.N;
+    const uint32_t nx = (uint32_t)a.nx, ny = (uint32_t)a.ny, nz = (uint32_t)a.nz, nxy = nx * ny;
+    const uint32_t zz = n / nxy, rr = n - zz * nxy, yy = rr / nx, xx = rr - yy * nx;
+    const int x = (int)xx, y = (int)yy, z = (int)zz;
+    const uint32_t w[6] = {xx == nx - 1 ? 0u - nx : 0u, xx == 0 ? nx : 0u, yy == ny - 1 ? 0u - nxy : 0u,
+                           yy == 0 ? nxy : 0u,          zz == nz - 1 ? 0u - N : 0u, zz == 0 ? N : 0u};
     uint32_t bcm, outm, inm;
     classify<Q>(a, x, y, z, bcm, outm, inm);
-    // forward state f(t) (full values f = w + delta f)
-    char *fwd = (char *)A.fwd;
-    R f[Q];
-    sfor<Q>([&](auto K) {
-      constexpr int k = K;
-      R v = (A.parity == 0) ? ldv<T, R>(slot_general<Q, T, 0>(a, fwd, k, x, y, z, n, bcm))
-                            : ldv<T, R>(slot_general<Q, T, 1>(a, fwd, k, x, y, z, n, bcm));
-      if (A.parity == 1 && ((inm >> k) & 1u)) v += inlet_term<Q, R>(a, k);
-      f[k] = v + R(wt<Q>(k));
-    });
-    // adjoint of the post-collision values: transpose of the streaming
+    // forward state before the step, as deviations d_k = f_k - w_k, and the
+    // adjoint gh of the post-collision values (transpose of the streaming)
+    const T *fwd = (const T *)A.fwd;
     const R *ain = (const R *)A.ain;
-    R gh[Q];
-    sfor<Q>([&](auto K) {
-      constexpr int i = K;
-      constexpr int ib = opp<Q>(i);
-      R g = 0;
-      // f*_i(x) streams to x + c_i unless that neighbour's source (x) is
-      // outside for it, i.e. unless direction ib is a face direction here
-      if (!((bcm >> ib) & 1u)) {
-        int px = x + cx<Q>(i), py = y + cy<Q>(i), pz = z + cz<Q>(i);
-        if (px < 0) px += a.nx;
-        if (px >= a.nx) px -= a.nx;
-        if (py < 0) py += a.ny;
-        if (py >= a.ny) py -= a.ny;
-        if (pz < 0) pz += a.nz;
-        if (pz >= a.nz) pz -= a.nz;
-        const uint64_t m = (uint64_t)px + (uint64_t)a.nx * ((uint64_t)py + (uint64_t)a.ny * (uint64_t)pz);
-        g += ain[(uint64_t)i * N + m];
-      } else if (!((outm >> ib) & 1u)) {
-        g += ain[(uint64_t)ib * N + n];  // bounced back by a wall / inlet into direction ib
-      }
-      if ((outm >> i) & 1u) g += ain[(uint64_t)i * N + n];  // outlet: f_i(x) = f*_i(x)
-      gh[i] = g;
+    R d[Q], gh[Q];
+    if (bcm == 0) {  // no face direction: plain pulls / pushes with periodic wrap
+      sfor<Q>([&](auto K) {
+        constexpr int k = K;
+        if constexpr (PAR == 0 || k == 0) d[k] = (R)fwd[(size_t)k * N + n];
+        else d[k] = (R)fwd[(size_t)opp<Q>(k) * N + nbr<-cx<Q>(k), -cy<Q>(k), -cz<Q>(k)>(n, nx, nxy, w)];
+        if constexpr (k == 0) gh[k] = ain[n];
+        else gh[k] = ain[(size_t)k * N + nbr<cx<Q>(k), cy<Q>(k), cz<Q>(k)>(n, nx, nxy, w)];
+      });
+    } else {
+      sfor<Q>([&](auto K) {
+        constexpr int k = K;
+        const T *own = fwd + (size_t)k * N + n;
+        R v;
+        if constexpr (PAR == 0 || k == 0) {
+          v = (R)*own;
+        } else {
+          const uint32_t src = nbr<-cx<Q>(k), -cy<Q>(k), -cz<Q>(k)>(n, nx, nxy, w);
+          const T *p = ((bcm >> k) & 1u) ? own : fwd + (size_t)opp<Q>(k) * N + src;
+          v = (R)*p;
+          if ((inm >> k) & 1u) v += inlet_term<Q, R>(a, k);
+        }
+        d[k] = v;
+      });
+      sfor<Q>([&](auto K) {
+        constexpr int i = K;
+        constexpr int ib = opp<Q>(i);
+        const R *ai = ain + (size_t)i * N;
+        R g = 0;
+        if constexpr (i == 0) {
+          g = ai[n];
+        } else {
+          // f*_i(x) streams to x + c_i unless that neighbour's source (x) is
+          // outside for it, i.e. unless direction ib is a face direction here
+          if (!((bcm >> ib) & 1u)) g += ai[nbr<cx<Q>(i), cy<Q>(i), cz<Q>(i)>(n, nx, nxy, w)];
+          else if (!((outm >> ib) & 1u)) g += ain[(size_t)ib * N + n];  // bounced back into direction ib
+          if ((outm >> i) & 1u) g += ai[n];                             // outlet: f_i(x) = f*_i(x)
+        }
+        gh[i] = g;
+      });
+    }
+    // forward recompute: rho, u, and the per-cell constants
+    R drho = d[0], jx = 0, jy = 0, jz = 0;
+    sfor<H>([&](auto P) {
+      constexpr int i = P + 1, ib = opp<Q>(i);
+      drho += d[i] + d[ib];
+      cacc<cx<Q>(i), cy<Q>(i), cz<Q>(i)>(jx, jy, jz, d[i] - d[ib]);
     });
-    // forward recompute
-    R rho = 0, jx = 0, jy = 0, jz = 0;
-    sfor<Q>([&](auto K) {
-      constexpr int k = K;
-      rho += f[k];
-      jx += R(cx<Q>(k)) * f[k];
-      jy += R(cy<Q>(k)) * f[k];
-      jz += R(cz<Q>(k)) * f[k];
-    });
+    const R rho = R(1) + drho, ir = R(1) / rho;
     const R Fx = (R)a.force[0], Fy = (R)a.force[1], Fz = (R)a.force[2];
-    const R ux = (jx + R(0.5) * Fx) / rho, uy = (jy + R(0.5) * Fy) / rho, uz = (jz + R(0.5) * Fz) / rho;
-    const R usq = ux * ux + uy * uy + uz * uz;
-    R B = a.B0 ? (R)a.B0[n] : R(0);
-    if (a.dB) B += (R)a.dB[n];
+    const R ux = (jx + R(0.5) * Fx) * ir, uy = (jy + R(0.5) * Fy) * ir, uz = (jz + R(0.5) * Fz) * ir;
+    const R Frx = Fx * ir, Fry = Fy * ir, Frz = Fz * ir;
+    const R usq = ux * ux + uy * uy + uz * uz, uF = ux * Fx + uy * Fy + uz * Fz;
+    const R B = solid_fraction<R>(a, n), fl = R(1) - B;
     const double rx = x + 0.5 - A.X[0], ry = y + 0.5 - A.X[1], rz = z + 0.5 - A.X[2];
     const R usx = (R)(A.V[0] + (A.W[1] * rz - A.W[2] * ry));
     const R usy = (R)(A.V[1] + (A.W[2] * rx - A.W[0] * rz));
     const R usz = (R)(A.V[2] + (A.W[0] * ry - A.W[1] * rx));
     const R uss = usx * usx + usy * usy + usz * usz;
-    // a x r (torque lever per unit force along c_i)
+    // a x r: torque lever per unit force along c_i
     const R arx = (R)(A.axis[1] * rz - A.axis[2] * ry), ary = (R)(A.axis[2] * rx - A.axis[0] * rz),
             arz = (R)(A.axis[0] * ry - A.axis[1] * rx);
     const R wtt = (R)A.wt;
     const R le = (R)a.lam_e, lo = (R)a.lam_o;
     const R ge = R(1) - R(0.5) * le, go = R(1) - R(0.5) * lo;
-    R feq[Q], feqs[Q], S[Q];
-    sfor<Q>([&](auto K) {
-      constexpr int i = K;
-      const R w = (R)wt<Q>(i);
-      const R cu = R(cx<Q>(i)) * ux + R(cy<Q>(i)) * uy + R(cz<Q>(i)) * uz;
-      const R cs = R(cx<Q>(i)) * usx + R(cy<Q>(i)) * usy + R(cz<Q>(i)) * usz;
-      feq[i] = w * rho * (R(1) + R(3) * cu + R(4.5) * cu * cu - R(1.5) * usq);
-      feqs[i] = w * rho * (R(1) + R(3) * cs + R(4.5) * cs * cs - R(1.5) * uss);
-      const R cF = R(cx<Q>(i)) * Fx + R(cy<Q>(i)) * Fy + R(cz<Q>(i)) * Fz;
-      const R uF = ux * Fx + uy * Fy + uz * Fz;
-      S[i] = w * (R(3) * (cF - uF) + R(9) * cu * cF);
-    });
-    R dJdB = 0;
-    R sh[Q];
-    sfor<Q>([&](auto K) {
-      constexpr int i = K;
-      constexpr int ib = opp<Q>(i);
-      const R fp = R(0.5) * (f[i] + f[ib]), fm = R(0.5) * (f[i] - f[ib]);
-      const R ep = R(0.5) * (feq[i] + feq[ib]), em = R(0.5) * (feq[i] - feq[ib]);
-      const R sp = R(0.5) * (S[i] + S[ib]), sm = R(0.5) * (S[i] - S[ib]);
-      const R omF = -le * (fp - ep) - lo * (fm - em) + ge * sp + go * sm;
-      const R omS = (f[ib] - feq[ib]) - (f[i] - feqs[i]);
-      const R mi = R(cx<Q>(i)) * arx + R(cy<Q>(i)) * ary + R(cz<Q>(i)) * arz;
-      dJdB += (gh[i] - wtt * mi) * omS - gh[i] * omF;
-      sh[i] = B * (gh[i] - wtt * mi);
-    });
-    // fluid part: b_i, d_i from the even / odd parts of gh
-    R Grho = 0, Gux = 0, Guy = 0, Guz = 0;
-    R Hrho = 0, Hux = 0, Huy = 0, Huz = 0, Krho = 0, Kx = 0, Ky = 0, Kz = 0;
-    sfor<Q>([&](auto K) {
-      constexpr int i = K;
-      constexpr int ib = opp<Q>(i);
+    const R dus = R(1.5) * (uss - usq);
+    // rest direction
+    R Wg, dJ;
+    {
+      const R w0 = (R)wt<Q>(0);
+      const R fe = d[0] - w0 * (drho - rho * R(1.5) * usq);
+      const R OF = -le * fe - ge * R(3) * w0 * uF;
+      const R OS = -w0 * rho * dus;
+      Wg = w0 * gh[0];
+      dJ = R(0.5) * gh[0] * (OS - OF);
+    }
+    R Vx = 0, Vy = 0, Vz = 0, C0 = 0, dS = 0, Wg2 = 0;
+    sfor<H>([&](auto P) {
+      constexpr int i = P + 1, ib = opp<Q>(i);
       constexpr int ex = cx<Q>(i), ey = cy<Q>(i), ez = cz<Q>(i);
-      const R w = (R)wt<Q>(i);
+      const R wi = (R)wt<Q>(i);
       const R gp = R(0.5) * (gh[i] + gh[ib]), gm = R(0.5) * (gh[i] - gh[ib]);
-      const R b = le * gp + lo * gm, d = ge * gp + go * gm;
-      const R cu = R(ex) * ux + R(ey) * uy + R(ez) * uz;
-      const R cs = R(ex) * usx + R(ey) * usy + R(ez) * usz;
-      const R cF = R(ex) * Fx + R(ey) * Fy + R(ez) * Fz;
-      // dfeq_i/du = w rho [3 c + 9 (c.u) c - 3 u]
-      const R t1 = w * rho * R(3), t9 = w * rho * R(9) * cu;
-      Grho += b * feq[i] / rho;
-      Gux += b * (t1 * R(ex) + t9 * R(ex) - t1 * ux) + d * w * (R(-3) * Fx + R(9) * cF * R(ex));
-      Guy += b * (t1 * R(ey) + t9 * R(ey) - t1 * uy) + d * w * (R(-3) * Fy + R(9) * cF * R(ey));
-      Guz += b * (t1 * R(ez) + t9 * R(ez) - t1 * uz) + d * w * (R(-3) * Fz + R(9) * cF * R(ez));
-      // solid part (SC1): sum_i sh_ib feq_i(u) and sum_i sh_i feq_i(u_s)
-      const R sb = sh[ib];
-      Hrho += sb * feq[i] / rho;
-      Hux += sb * (t1 * R(ex) + t9 * R(ex) - t1 * ux);
-      Huy += sb * (t1 * R(ey) + t9 * R(ey) - t1 * uy);
-      Huz += sb * (t1 * R(ez) + t9 * R(ez) - t1 * uz);
-      Krho += sh[i] * feqs[i] / rho;
-      const R s9 = w * rho * R(9) * cs;
-      Kx += sh[i] * (t1 * R(ex) + s9 * R(ex) - t1 * usx);
-      Ky += sh[i] * (t1 * R(ey) + s9 * R(ey) - t1 * usy);
-      Kz += sh[i] * (t1 * R(ez) + s9 * R(ez) - t1 * usz);
+      const R dp = R(0.5) * (d[i] + d[ib]), dm = R(0.5) * (d[i] - d[ib]);
+      const R cu = cdot<ex, ey, ez>(ux, uy, uz), cs = cdot<ex, ey, ez>(usx, usy, usz);
+      const R cF = cdot<ex, ey, ez>(Fx, Fy, Fz), cFr = cdot<ex, ey, ez>(Frx, Fry, Frz);
+      const R m = cdot<ex, ey, ez>(arx, ary, arz);
+      const R cu2 = cu * cu, cs2 = cs * cs;
+      // TRT + Guo (even / odd parts) and SC1 collision of the pair
+      const R fpe = dp - wi * (drho + rho * (R(4.5) * cu2 - R(1.5) * usq));
+      const R fme = dm - R(3) * wi * rho * cu;
+      const R OFp = -le * fpe + ge * wi * (R(9) * cu * cF - R(3) * uF);
+      const R OFm = -lo * fme + go * R(3) * wi * cF;
+      const R OSp = wi * rho * (R(4.5) * (cs2 - cu2) - dus);
+      const R OSm = R(-2) * dm + R(3) * wi * rho * (cu + cs);
+      const R qm = gm - wtt * m;
+      dJ += gp * (OSp - OFp) + qm * OSm - gm * OFm;
+      const R shp = B * gp, shm = B * qm;
+      const R kap = wi * (fl * (R(6) * lo * gm + R(18) * gp * (le * cu + ge * cFr)) + R(6) * shm - R(18) * shp * cu);
+      cacc<ex, ey, ez>(Vx, Vy, Vz, kap);
+      C0 += wi * (R(9) * shp * (cu2 + cs2) + R(6) * shm * cs - fl * gp * cu * (R(9) * le * cu + R(18) * ge * cFr));
+      dS += wi * (R(6) * shm + R(18) * shp * cs) * m;
+      Wg2 += wi * gp;
     });
-    const R fl = R(1) - B;
+    Wg += R(2) * Wg2;
+    const R Ws = B * Wg;
+    C0 += fl * Wg * (le * (R(1) + R(1.5) * usq) + R(3) * ge * (Frx * ux + Fry * uy + Frz * uz)) -
+          R(1.5) * (usq + uss) * Ws;
+    Vx -= R(3) * (fl * Wg * (le * ux + ge * Frx) - ux * Ws);
+    Vy -= R(3) * (fl * Wg * (le * uy + ge * Fry) - uy * Ws);
+    Vz -= R(3) * (fl * Wg * (le * uz + ge * Frz) - uz * Ws);
     R *aout = (R *)A.aout;
-    sfor<Q>([&](auto K) {
-      constexpr int j = K;
-      constexpr int jb = opp<Q>(j);
-      const R cux = (R(cx<Q>(j)) - ux) / rho, cuy = (R(cy<Q>(j)) - uy) / rho, cuz = (R(cz<Q>(j)) - uz) / rho;
-      const R gp = R(0.5) * (gh[j] + gh[jb]), gm = R(0.5) * (gh[j] - gh[jb]);
-      const R vF = -le * gp - lo * gm + Grho + Gux * cux + Guy * cuy + Guz * cuz;
-      const R vS = (sh[jb] - sh[j]) - (Hrho + Hux * cux + Huy * cuy + Huz * cuz) + Krho;
-      aout[(uint64_t)j * N + n] = gh[j] + fl * vF + vS;
+    aout[n] = gh[0] - fl * le * gh[0] + C0;
+    sfor<H>([&](auto P) {
+      constexpr int i = P + 1, ib = opp<Q>(i);
+      constexpr int ex = cx<Q>(i), ey = cy<Q>(i), ez = cz<Q>(i);
+      const R gp = R(0.5) * (gh[i] + gh[ib]), gm = R(0.5) * (gh[i] - gh[ib]);
+      const R shm = B * (gm - wtt * cdot<ex, ey, ez>(arx, ary, arz));
+      const R vc = cdot<ex, ey, ez>(Vx, Vy, Vz);
+      const R bp = le * gp, bm = lo * gm;
+      aout[(size_t)i * N + n] = gh[i] - fl * (bp + bm) - R(2) * shm + C0 + vc;
+      aout[(size_t)ib * N + n] = gh[ib] - fl * (bp - bm) + R(2) * shm + C0 - vc;
     });
     R *gB = (R *)A.dJdB;
-    gB[n] += dJdB;
-    dom = (double)(arx * Kx + ary * Ky + arz * Kz);
+    gB[n] += R(2) * dJ;
+    dom = (double)(rho * (dS - R(3) * (arx * usx + ary * usy + arz * usz) * Ws));
   }
   __shared__ double sh4[4];
   double v = wave_sum(dom);
@@ -173,15 +230,21 @@ __global__ __launch_bounds__(256) void k_adjoint(const AdjArgs A) {
   if (threadIdx.x == 0) A.part[blockIdx.x] = ((sh4[0] + sh4[1]) + sh4[2]) + sh4[3];
 }
 
+template <int Q, typename T>
+static void go_adjoint(const AdjArgs &A, dim3 g, hipStream_t st) {
+  if (A.parity == 0) hipLaunchKernelGGL((k_adjoint<Q, T, 0>), g, dim3(256), 0, st, A);
+  else hipLaunchKernelGGL((k_adjoint<Q, T, 1>), g, dim3(256), 0, st, A);
+}
+
 hipError_t launch_adjoint(const psm_field &f, const AdjArgs &A, hipStream_t st) {
-  const dim3 g((unsigned)((f.N + 255) / 256)), b(256);
+  const dim3 g((unsigned)((f.N + 255) / 256));
   const int q = f.cfg.q, sto = f.cfg.storage;
-  if (q == 19 && sto == PSM_F64) hipLaunchKernelGGL((k_adjoint<19, double>), g, b, 0, st, A);
-  else if (q == 19 && sto == PSM_F32) hipLaunchKernelGGL((k_adjoint<19, float>), g, b, 0, st, A);
-  else if (q == 19) hipLaunchKernelGGL((k_adjoint<19, _Float16>), g, b, 0, st, A);
-  else if (sto == PSM_F64) hipLaunchKernelGGL((k_adjoint<27, double>), g, b, 0, st, A);
-  else if (sto == PSM_F32) hipLaunchKernelGGL((k_adjoint<27, float>), g, b, 0, st, A);
-  else hipLaunchKernelGGL((k_adjoint<27, _Float16>), g, b, 0, st, A);
+  if (q == 19 && sto == PSM_F64) go_adjoint<19, double>(A, g, st);
+  else if (q == 19 && sto == PSM_F32) go_adjoint<19, float>(A, g, st);
+  else if (q == 19) go_adjoint<19, _Float16>(A, g, st);
+  else if (sto == PSM_F64) go_adjoint<27, double>(A, g, st);
+  else if (sto == PSM_F32) go_adjoint<27, float>(A, g, st);
+  else go_adjoint<27, _Float16>(A, g, st);
   return hipGetLastError();
 }
 

@@ -238,27 +238,40 @@ __device__ __forceinline__ bool box_has(const IBox &b, int x, int y, int z) {
   return x >= b.lo[0] && x <= b.hi[0] && y >= b.lo[1] && y <= b.hi[1] && z >= b.lo[2] && z <= b.hi[2];
 }
 
+// Directions whose source x - c_k lies beyond face f (f = -x,+x,-y,+y,-z,+z):
+// those with c_k along the face's inward normal.
+template <int Q>
+__host__ __device__ constexpr uint32_t face_dirs(int f) {
+  uint32_t m = 0;
+  for (int k = 0; k < Q; ++k) {
+    const int e = f < 2 ? cx<Q>(k) : (f < 4 ? cy<Q>(k) : cz<Q>(k));
+    if (e == ((f & 1) ? -1 : 1)) m |= 1u << k;
+  }
+  return m;
+}
+
 // Face kinds of every incoming direction of cell (x,y,z) (source x - c_k):
 // bit k of bcm set when the source is outside a non-periodic face; outm / inm
 // mark the outlet / inlet kinds (after the wall > inlet > outlet precedence).
+// Per face: the cell's flag selects the face's direction set into the mask of
+// the face's (uniform) kind; precedence is applied to the three masks.
 template <int Q>
 __device__ __forceinline__ void classify(const SCArgs &a, int x, int y, int z, uint32_t &bcm, uint32_t &outm,
                                          uint32_t &inm) {
-  bcm = outm = inm = 0;
-  sfor<Q>([&](auto K) {
-    constexpr int k = K;
-    constexpr int ex = cx<Q>(k), ey = cy<Q>(k), ez = cz<Q>(k);
-    int kd = K_NONE;
-    if constexpr (ex == 1) if (x == 0 && !a.periodic[0]) kd = face_merge(kd, a.bc[0]);
-    if constexpr (ex == -1) if (x == a.nx - 1 && !a.periodic[0]) kd = face_merge(kd, a.bc[1]);
-    if constexpr (ey == 1) if (y == 0 && !a.periodic[1]) kd = face_merge(kd, a.bc[2]);
-    if constexpr (ey == -1) if (y == a.ny - 1 && !a.periodic[1]) kd = face_merge(kd, a.bc[3]);
-    if constexpr (ez == 1) if (z == 0 && !a.periodic[2]) kd = face_merge(kd, a.bc[4]);
-    if constexpr (ez == -1) if (z == a.nz - 1 && !a.periodic[2]) kd = face_merge(kd, a.bc[5]);
-    if (kd != K_NONE) bcm |= 1u << k;
-    if (kd == K_OUTLET) outm |= 1u << k;
-    if (kd == K_INLET) inm |= 1u << k;
+  const bool on[6] = {x == 0, x == a.nx - 1, y == 0, y == a.ny - 1, z == 0, z == a.nz - 1};
+  uint32_t mw = 0, mi = 0, mo = 0;
+  sfor<6>([&](auto F) {
+    constexpr int f = F;
+    constexpr uint32_t dm = face_dirs<Q>(f);
+    const int kd = a.periodic[f >> 1] ? K_NONE : a.bc[f];
+    const uint32_t sel = on[f] ? dm : 0u;
+    mw |= sel & (kd == K_WALL ? ~0u : 0u);
+    mi |= sel & (kd == K_INLET ? ~0u : 0u);
+    mo |= sel & (kd == K_OUTLET ? ~0u : 0u);
   });
+  bcm = mw | mi | mo;
+  inm = mi & ~mw;
+  outm = mo & ~(mw | mi);
 }
 
 // Slot of direction k for cell (x,y,z) with full face handling (face cells,
