@@ -64,6 +64,7 @@ def lib():
         L.or_pose_at.restype = None
         L.or_collide_cell.argtypes = [C.POINTER(Config), dp, C.c_int, dp, dp, dp, dp]
         L.or_step.argtypes = [C.POINTER(Config), dp, dp, C.c_int, dp, C.POINTER(Pose), dp]
+        L.or_step_obstacle.argtypes = [C.POINTER(Config), dp, dp, C.POINTER(C.c_ubyte)]
         L.or_macro.argtypes = [C.POINTER(Config), dp, dp, dp]
         L.or_macro.restype = None
         L.or_mass.argtypes = [C.POINTER(Config), dp]
@@ -170,6 +171,19 @@ def step(cfg: Config, f: np.ndarray, B: np.ndarray | None, poses) -> np.ndarray:
     if r != 0:
         raise RuntimeError(f"or_step failed ({r})")
     return ft[:nb]
+
+
+def step_obstacle(cfg: Config, f: np.ndarray, solid: np.ndarray) -> None:
+    """Advance f (q, N) in place by one plain-LBM step with static no-slip
+    obstacle cells (solid[n] != 0): halfway bounce-back on every link from a
+    fluid cell into an obstacle cell; obstacle cells keep their values (the
+    LBM variant of the paper's node-level benchmark, section V)."""
+    fpost = np.empty_like(f)
+    sm = np.ascontiguousarray(solid, dtype=np.uint8)
+    assert sm.size == f.shape[1]
+    r = lib().or_step_obstacle(C.byref(cfg), _dp(f), _dp(fpost), sm.ctypes.data_as(C.POINTER(C.c_ubyte)))
+    if r != 0:
+        raise RuntimeError(f"or_step_obstacle failed ({r})")
 
 
 def macro(cfg: Config, f: np.ndarray):

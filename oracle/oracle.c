@@ -219,8 +219,8 @@ static int classify(const or_config *cfg, int x, int y, int z, const int *c, int
  *   outlet : f_k(y) = f*_k(y)                              (zero gradient)
  * B is dense per body, B[b*N + n].  ft[b*6..] = (F, T) on body b, summed per
  * z-slab then over slabs in z order. */
-int or_step(const or_config *cfg, double *f, double *fpost, int nb, const double *B,
-            const or_pose *poses, double *ft) {
+static int step_impl(const or_config *cfg, double *f, double *fpost, int nb, const double *B,
+                     const or_pose *poses, double *ft, const unsigned char *solid) {
   lat_t L;
   if (lat_get(cfg->q, &L) != 0) return -1;
   for (int a = 0; a < 3; ++a)
@@ -236,6 +236,10 @@ int or_step(const or_config *cfg, double *f, double *fpost, int nb, const double
         long long n = x + (long long)nx * (y + (long long)ny * z);
         double fin[OR_MAXQ], fo[OR_MAXQ], Bs[2], us[6], dF[6];
         int bid[2], ns = 0;
+        if (solid && solid[n]) { /* obstacle cell: not updated */
+          for (int i = 0; i < q; ++i) fpost[i * N + n] = f[i * N + n];
+          continue;
+        }
         for (int i = 0; i < q; ++i) fin[i] = f[i * N + n];
         if (cfg->psm)
           for (int b = 0; b < nb; ++b) {
@@ -283,12 +287,15 @@ int or_step(const or_config *cfg, double *f, double *fpost, int nb, const double
     for (int y = 0; y < ny; ++y)
       for (int x = 0; x < nx; ++x) {
         long long n = x + (long long)nx * (y + (long long)ny * z);
+        if (solid && solid[n]) continue;
         for (int k = 0; k < q; ++k) {
           long long src;
           {
             int s32;
             int kind = classify(cfg, x, y, z, &L.c[3 * k], &s32);
             src = s32;
+            /* a source inside an obstacle cell: halfway bounce-back, the wall rule */
+            if (kind == 0 && solid && solid[src]) kind = OR_WALL;
             double v;
             if (kind == 0) {
               v = fpost[k * N + src];
@@ -305,6 +312,22 @@ int or_step(const or_config *cfg, double *f, double *fpost, int nb, const double
         }
       }
   return 0;
+}
+
+int or_step(const or_config *cfg, double *f, double *fpost, int nb, const double *B,
+            const or_pose *poses, double *ft) {
+  return step_impl(cfg, f, fpost, nb, B, poses, ft, NULL);
+}
+
+/* Plain LBM with a static no-slip obstacle: the LBM variant of the paper's
+ * node-level benchmark (section V, an LBM kernel plus the no-slip treatment of
+ * a stationary geometry).  solid[n] != 0 marks obstacle cells; every link from
+ * a fluid cell whose source is an obstacle cell takes halfway bounce-back,
+ * f_k(y) = f*_{kbar}(y), the wall rule above; obstacle cells are not updated.
+ * Needs cfg->psm == 0. */
+int or_step_obstacle(const or_config *cfg, double *f, double *fpost, const unsigned char *solid) {
+  if (cfg->psm) return -4;
+  return step_impl(cfg, f, fpost, 0, NULL, NULL, NULL, solid);
 }
 
 /* density and (Guo-shifted) velocity u = (sum c f + F/2)/rho per cell */

@@ -20,6 +20,8 @@
  *     section III (supersampled body-frame lookup of every sub-sample)
  *   - generalised winding number voxelisation, divergence-theorem volume
  *   - FP64 discrete adjoint of one step (explicit per-cell Jacobian)
+ *   - plain LBM with halfway bounce-back on static obstacle cells (the LBM
+ *     variant of the node-level benchmark, section V)
  *
  * Readings of ambiguous passages are listed in the design notes of the
  * repository; each function below names the equation it follows.
@@ -82,6 +84,8 @@ int or_collide_cell(const or_config *cfg, const double *fin, int nslot, const do
 
 int or_step(const or_config *cfg, double *f, double *fpost, int nb, const double *B,
             const or_pose *poses, double *ft);
+/* plain LBM (cfg->psm == 0) with static no-slip obstacle cells solid[n] != 0 */
+int or_step_obstacle(const or_config *cfg, double *f, double *fpost, const unsigned char *solid);
 
 void or_macro(const or_config *cfg, const double *f, double *rho, double *u);
 double or_mass(const or_config *cfg, const double *f);

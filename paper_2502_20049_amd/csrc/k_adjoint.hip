@@ -248,18 +248,31 @@ hipError_t launch_adjoint(const psm_field &f, const AdjArgs &A, hipStream_t st) 
   return hipGetLastError();
 }
 
-__global__ __launch_bounds__(256) void k_sum_accumulate(const double *p, uint32_t n, double *out) {
-  double acc = 0.0;
-  for (uint32_t i = threadIdx.x; i < n; i += 256) acc += p[i];
-  __shared__ double sh[4];
-  acc = wave_sum(acc);
-  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+// out[0] += sum of p[0..n) in a fixed order (1024 strided partial sums, then
+// a fixed wave / workgroup tree).
+__global__ __launch_bounds__(1024) void k_sum_accumulate(const double *p, uint32_t n, double *out) {
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  uint32_t i = threadIdx.x;
+  for (; i + 3 * 1024 < n; i += 4 * 1024) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc[u] += p[i + u * 1024];
+  }
+  if (i < n) acc[0] += p[i];  // at most three strides remain
+  if (i + 1024 < n) acc[1] += p[i + 1024];
+  if (i + 2048 < n) acc[2] += p[i + 2048];
+  double v = wave_sum((acc[0] + acc[1]) + (acc[2] + acc[3]));
+  __shared__ double sh[16];
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
   __syncthreads();
-  if (threadIdx.x == 0) out[0] += ((sh[0] + sh[1]) + sh[2]) + sh[3];
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int w = 0; w < 16; ++w) s += sh[w];
+    out[0] += s;
+  }
 }
 
 hipError_t launch_sum_accumulate(const double *p, uint32_t n, double *out, hipStream_t st) {
-  hipLaunchKernelGGL(k_sum_accumulate, dim3(1), dim3(256), 0, st, p, n, out);
+  hipLaunchKernelGGL(k_sum_accumulate, dim3(1), dim3(1024), 0, st, p, n, out);
   return hipGetLastError();
 }
 

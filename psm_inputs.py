@@ -129,6 +129,12 @@ def random_fractions(seed: int, n_cells: int, levels: int = 64, p_zero=0.35, p_o
     return b
 
 
+def random_obstacle(seed: int, n_cells: int, p_solid: float = 0.2, stream=4):
+    """uint8 obstacle flags (1 = obstacle cell) with probability p_solid."""
+    h = counter_u32(seed, stream, np.arange(n_cells, dtype=np.int64)).astype(np.float64) / 2.0**32
+    return (h < p_solid).astype(np.uint8)
+
+
 def random_unit(seed: int, n: int, stream=3):
     """n uniform doubles in [0,1) (multiples of 2^-32)."""
     return counter_u32(seed, stream, np.arange(n, dtype=np.int64)).astype(np.float64) / 2.0**32

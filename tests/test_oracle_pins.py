@@ -459,3 +459,101 @@ def test_sampled_update_equals_full_step(orc, bc):
     got = orc.sampled_steps(wl, cells, f_at, geoms, 2)
     n = cells[:, 0] + 9 * (cells[:, 1] + 7 * cells[:, 2])
     assert np.allclose(got, run.f[:, n].T, atol=1e-15, rtol=0)
+
+
+# --- static no-slip obstacle (the LBM variant of section V's node benchmark) ---
+def _obstacle_steps(orc, cfg, f, solid, n):
+    for _ in range(n):
+        orc.step_obstacle(cfg, f, solid)
+
+
+@pytest.mark.parametrize("q", [19, 27])
+def test_obstacle_slab_equals_wall_faces(orc, q):
+    """Obstacle rows y = 0 and y = ny-1 of a periodic box give bit for bit the
+    fluid of the box without them whose -y / +y faces are halfway bounce-back
+    walls (the diagonal links cross the periodic x / z wrap as well); obstacle
+    cells keep their values."""
+    nx, ny, nz = 4, 8, 3
+    F = (1e-4, 0.0, 2e-5)
+    cfg_a = _cfg(orc, q, nx=nx, ny=ny, nz=nz, force=F, psm=0)
+    cfg_b = _cfg(orc, q, nx=nx, ny=ny - 2, nz=nz, force=F, psm=0,
+                 bc=("periodic", "periodic", "wall", "wall", "periodic", "periodic"))
+    fa = _random_state(orc, q, nx * ny * nz, 91)
+    solid = np.zeros((nz, ny, nx), np.uint8)
+    solid[:, 0, :] = 1
+    solid[:, ny - 1, :] = 1
+    solid = solid.ravel()
+    fb = fa.reshape(q, nz, ny, nx)[:, :, 1:ny - 1, :].reshape(q, -1).copy()
+    f0 = fa.copy()
+    _obstacle_steps(orc, cfg_a, fa, solid, 7)
+    for _ in range(7):
+        orc.step(cfg_b, fb, None, [])
+    got = fa.reshape(q, nz, ny, nx)[:, :, 1:ny - 1, :].reshape(q, -1)
+    assert np.array_equal(got, fb)
+    assert np.array_equal(fa[:, solid == 1], f0[:, solid == 1])
+
+
+def test_obstacle_poiseuille_exact(orc):
+    """Body-force channel between obstacle rows: the halfway walls sit one cell
+    in, u_x = F/(2 nu) (y - 1)(ny - 1 - y) at the fluid cell centres."""
+    ny, tau, F = 12, 0.8, 1e-5
+    cfg = _cfg(orc, 19, nx=1, ny=ny, nz=1, tau=tau, force=(F, 0, 0), psm=0)
+    c, w, _ = orc.lattice(19)
+    f = np.repeat(w[:, None], ny, axis=1).copy()
+    solid = np.zeros(ny, np.uint8)
+    solid[0] = solid[-1] = 1
+    prev = f.copy()
+    for _ in range(400):
+        _obstacle_steps(orc, cfg, f, solid, 500)
+        if np.abs(f - prev).max() < 1e-14:
+            break
+        prev = f.copy()
+    else:
+        raise AssertionError("no steady state")
+    rho, u = orc.macro(cfg, f)
+    nu = (tau - 0.5) / 3
+    y = np.arange(1, ny - 1) + 0.5
+    ua = F / (2 * nu) * (y - 1) * (ny - 1 - y)
+    assert np.abs(u[1:-1, 0] - ua).max() / ua.max() < 1e-10
+
+
+@pytest.mark.parametrize("q", [19, 27])
+def test_obstacle_conserves_fluid_mass(orc, q):
+    """Random obstacle cells in a periodic box with a body force: every
+    post-collision value of a fluid cell lands in exactly one fluid slot, so
+    the fluid mass is conserved; obstacle cells never change."""
+    nx, ny, nz = 6, 5, 4
+    N = nx * ny * nz
+    cfg = _cfg(orc, q, nx=nx, ny=ny, nz=nz, force=(2e-4, -1e-4, 5e-5), psm=0)
+    f = _random_state(orc, q, N, 93)
+    solid = pi.random_obstacle(7, N, 0.3)
+    assert 0 < solid.sum() < N
+    f0 = f.copy()
+    m0 = f[:, solid == 0].sum()
+    _obstacle_steps(orc, cfg, f, solid, 10)
+    assert abs(f[:, solid == 0].sum() - m0) / m0 < 1e-13
+    assert np.array_equal(f[:, solid == 1], f0[:, solid == 1])
+
+
+def test_obstacle_rest_is_fixed_point(orc):
+    """Rest equilibrium around any obstacle stays at rest (no force)."""
+    nx, ny, nz = 5, 4, 6
+    cfg = _cfg(orc, 19, nx=nx, ny=ny, nz=nz, psm=0, bc=("wall", "wall", "periodic", "periodic", "wall", "wall"))
+    c, w, _ = orc.lattice(19)
+    N = nx * ny * nz
+    f = np.repeat(w[:, None], N, axis=1).copy()
+    solid = pi.random_obstacle(8, N, 0.35)
+    _obstacle_steps(orc, cfg, f, solid, 5)
+    assert np.abs(f - w[:, None]).max() < 1e-15
+
+
+def test_obstacle_empty_mask_is_plain_step(orc):
+    nx, ny, nz = 5, 4, 3
+    cfg = _cfg(orc, 27, nx=nx, ny=ny, nz=nz, psm=0, force=(1e-4, 0, 0),
+               bc=("inlet", "outlet", "wall", "wall", "periodic", "periodic"), u_in=(0.03, 0, 0))
+    f = _random_state(orc, 27, nx * ny * nz, 95)
+    g = f.copy()
+    _obstacle_steps(orc, cfg, f, np.zeros(nx * ny * nz, np.uint8), 4)
+    for _ in range(4):
+        orc.step(cfg, g, None, [])
+    assert np.array_equal(f, g)
