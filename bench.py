@@ -198,32 +198,52 @@ def s_sweep(steps=200):
     return out
 
 
-def rotor_box(steps=200):
-    """Rotor-heavy scenario: one 8-blade rotor of radius 120 filling a 256^3
-    box (s = 2), PSM + mapping every step, and the same lattice as plain LBM."""
+def node_benchmark(steps=200):
+    """The paper's node-level comparison (section V) on one GPU, periodic
+    lattices (inflow / outflow excluded, as there): plain LBM; LBM with the
+    no-slip treatment of the stationary voxelised geometry (lbm_set_obstacle);
+    PSM with the geometry mapped once; PSM with the geometry rotating and
+    mapped every step at s = 0, 1 and the workload's own s.  Scene B: the
+    256^3 channel's ellipsoid (a small body in a large lattice); scene A: the
+    256^3 box filled by an 8-blade rotor of radius 120 (118k triangles)."""
+    import dataclasses
+
     import torch
 
     import psm_inputs as pi
     from paper_2502_20049_amd import sim
 
-    wl = pi.workload_rotor_box(steps=steps)
-    out = {"case": wl.name + f", {sum(len(b.shape.mesh.tris) for b in wl.bodies)} triangles, s=2"}
-    t0 = time.perf_counter()
-    f = sim.Field(wl)
-    out["setup_s"] = round(time.perf_counter() - t0, 2)
-    wall, t = time_field(f, steps, 20)
-    sc, mp = time_kernels(f, 100, t)
-    out["psm_mlups"] = round(wl.n_cells * steps / wall / 1e6, 1)
-    out["collide_ms"] = round(sc, 5)
-    out["map_ms"] = round(mp, 5)
-    out["map_share"] = round(mp * steps / 1e3 / wall, 4)
-    del f
-    torch.cuda.empty_cache()
-    fl = sim.Field(wl, psm=False)
-    wall_l, _ = time_field(fl, steps, 20)
-    out["plain_lbm_mlups"] = round(wl.n_cells * steps / wall_l / 1e6, 1)
-    del fl
-    torch.cuda.empty_cache()
+    def mlups(field, wl):
+        wall, _ = time_field(field, steps, 20)
+        return round(wl.n_cells * steps / wall / 1e6, 1)
+
+    out = {}
+    scenes = {"B_ellipsoid_channel_256": pi.workload_ellipsoid_channel(256, "f32", steps=steps, s=3),
+              "A_rotor_box_256": pi.workload_rotor_box(steps=steps)}
+    for name, wl in scenes.items():
+        wl = dataclasses.replace(wl, bc=("periodic",) * 6, u_in=(0.0, 0.0, 0.0))
+        r = {}
+        f = sim.Field(wl, psm=False)
+        r["lbm"] = mlups(f, wl)
+        solid = sim.voxelize_obstacle(wl, 0)
+        r["obstacle_cells"] = int(solid.sum().item())
+        r["lbm_noslip_near_cells"] = f.set_obstacle(solid)
+        r["lbm_noslip_static"] = mlups(f, wl)
+        del f, solid
+        torch.cuda.empty_cache()
+        fs = sim.Field(wl, remap_every_step=False)
+        r["psm_static"] = mlups(fs, wl)
+        del fs
+        torch.cuda.empty_cache()
+        own = wl.bodies[0].s
+        for sv in sorted({0, 1, own}):
+            w2 = dataclasses.replace(wl, bodies=[dataclasses.replace(b, s=sv) for b in wl.bodies])
+            fr = sim.Field(w2)
+            r[f"psm_rotating_s{sv}"] = mlups(fr, w2)
+            del fr
+            torch.cuda.empty_cache()
+        r["psm_rotating_over_lbm_noslip"] = round(r[f"psm_rotating_s{own}"] / r["lbm_noslip_static"], 4)
+        out[name] = r
     return out
 
 
@@ -284,6 +304,9 @@ def main():
     ap.add_argument("--only-psm", action="store_true", help="time the PSM path only (for profiling)")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="run only the torque-gradient sweep on the 128^3 rotor (for profiling)")
+    ap.add_argument("--node-only", action="store_true",
+                    help="run only the paper's node-level comparison (LBM, LBM + no-slip obstacle, PSM static, "
+                         "PSM rotating)")
     ap.add_argument("--copy-only", action="store_true",
                     help="run only the device copy probe (1 GiB read + 1 GiB written per launch): the "
                          "calibration for rocprofv3 FETCH_SIZE / WRITE_SIZE")
@@ -300,6 +323,9 @@ def main():
     torch.cuda.set_device(0)
     if args.adjoint_only:
         print(json.dumps(adjoint_rate()), flush=True)
+        return
+    if args.node_only:
+        print(json.dumps(node_benchmark()), flush=True)
         return
     if args.copy_only:
         bw = copy_probe(nbytes=1 << 30, reps=5)
@@ -365,7 +391,7 @@ def main():
         extras["psm_frac_of_copy_bw"] = round(achieved / bw, 4)
         extras["accuracy_vs_fp64_oracle"] = accuracy_check()
         extras["supersampling_sweep"] = s_sweep()
-        extras["rotor_box_256"] = rotor_box()
+        extras["node_benchmark"] = node_benchmark()
         extras["adjoint_rotor_128"] = adjoint_rate()
         line["extras"] = extras
     if not args.no_cpu_baseline:

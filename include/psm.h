@@ -54,7 +54,8 @@ extern "C" {
 /* ---- enums --------------------------------------------------------------- */
 enum { PSM_F64 = 0, PSM_F32 = 1, PSM_F16 = 2 };                 /* PDF storage */
 enum { PSM_PERIODIC = 0, PSM_WALL = 1, PSM_INLET = 2, PSM_OUTLET = 3 }; /* faces */
-enum { PSM_BUF_PDF = 0, PSM_BUF_B = 1, PSM_BUF_WORK = 2, PSM_BUF_ADJOINT = 3, PSM_BUF_GRAD_B = 4 };
+enum { PSM_BUF_PDF = 0, PSM_BUF_B = 1, PSM_BUF_WORK = 2, PSM_BUF_ADJOINT = 3, PSM_BUF_GRAD_B = 4,
+       PSM_BUF_OBSTACLE = 5 };
 enum { PSM_SHAPE_ELLIPSOID = 0, PSM_SHAPE_CUBE = 1 };
 #define PSM_MAX_BODIES 8
 
@@ -127,7 +128,10 @@ const char *psm_last_error(void);
  *   ADJOINT  one adjoint PDF buffer of psm_adjoint_step: q*N values in the
  *        adjoint precision (FP64 for PSM_F64 fields, else FP32)
  *   GRAD_B   the dJ/dB accumulator of psm_adjoint_step: N adjoint-precision
- *        values                                                               */
+ *        values
+ *   OBSTACLE  lbm_set_obstacle's buffer (plain-LBM fields; 0 for psm = 1):
+ *        256 B header + N class bytes (padded to 256 B) + 8 B per listed
+ *        cell, sized here for the worst case of N listed cells              */
 int psm_required_bytes(const psm_config *cfg, int which, size_t *out_bytes);
 
 /* This library's lattice: velocities c[q][3], weights w[q], opposite opp[q]
@@ -232,6 +236,27 @@ int psm_step(psm_field *f, const psm_body *map_poses, const psm_body *bodies, co
  * The offset can make B nonzero anywhere, so the field then treats the whole
  * domain as possibly solid (slower; meant for sensitivity runs). */
 int psm_set_fraction_offset(psm_field *f, const float *dB_dev);
+
+/* ---- static no-slip obstacle (plain LBM) ----------------------------------- */
+/* The LBM variant of the paper's node-level benchmark (section V: an LBM
+ * kernel plus the no-slip treatment of a stationary geometry).  For a field
+ * with psm = 0: cells with solid_dev[n] != 0 (device, N bytes, read during
+ * this call only) become obstacle cells, never updated; every link from a
+ * fluid cell whose source x - c_k is an obstacle cell takes halfway
+ * bounce-back, the wall rule (ahead of inlet / outlet faces).  Builds, on
+ * `stream`, the cell classes, the list of fluid cells next to the obstacle
+ * (with their link masks) and the obstacle's bounding box in obst_dev
+ * (caller-owned, 256-byte aligned, kept until the obstacle is replaced;
+ * obst_bytes from psm_required_bytes(PSM_BUF_OBSTACLE) always suffices, a
+ * smaller buffer holds (obst_bytes - 256 - N rounded up to 256) / 8 list
+ * entries), then synchronises `stream` to read the list length back
+ * (*n_near, may be NULL).  Later psm_stream_collide / psm_step calls skip the
+ * obstacle and its neighbours in the bulk kernels and update the neighbours
+ * in a kernel of their own.  solid_dev = NULL removes the obstacle.
+ * psm_field_reset keeps it.  Errors: PSM_EUNSUP on a PSM field, PSM_ESIZE
+ * when the list does not fit (the field is then left without obstacle). */
+int lbm_set_obstacle(psm_field *f, const uint8_t *solid_dev, void *obst_dev, size_t obst_bytes, int64_t *n_near,
+                     void *stream);
 
 /* Reverse-mode (adjoint) of step `step` for the torque objective
  *   J = sum_t wt(t) * axis . T(t)

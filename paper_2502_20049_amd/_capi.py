@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(HERE, "libpsm.so")
 PSM_OK, PSM_EINVAL, PSM_ESIZE, PSM_EUNSUP, PSM_EHIP = 0, -1, -2, -3, -4
 PSM_F64, PSM_F32, PSM_F16 = 0, 1, 2
 PSM_PERIODIC, PSM_WALL, PSM_INLET, PSM_OUTLET = 0, 1, 2, 3
-PSM_BUF_PDF, PSM_BUF_B, PSM_BUF_WORK, PSM_BUF_ADJOINT, PSM_BUF_GRAD_B = 0, 1, 2, 3, 4
+PSM_BUF_PDF, PSM_BUF_B, PSM_BUF_WORK, PSM_BUF_ADJOINT, PSM_BUF_GRAD_B, PSM_BUF_OBSTACLE = 0, 1, 2, 3, 4, 5
 PSM_SHAPE_ELLIPSOID, PSM_SHAPE_CUBE = 0, 1
 PSM_OPT_GENERAL_PATH, PSM_OPT_XCD_REMAP = 1, 2
 PSM_MAX_BODIES = 8
@@ -27,7 +27,7 @@ EXPORTS = [
     "geometry_field_create", "geometry_field_create_analytic", "geometry_field_destroy", "geometry_map_step",
     "psm_stream_collide", "body_force_torque", "psm_mass_fp64", "psm_macroscopic", "psm_error_flags",
     "psm_set_option", "psm_stream_copy", "psm_set_fraction_offset", "psm_adjoint_step", "psm_adjoint_omega",
-    "psm_step",
+    "psm_step", "lbm_set_obstacle",
 ]
 
 
@@ -86,6 +86,7 @@ def _load():
         "psm_set_fraction_offset": (C.c_int, [vp, vp]),
         "psm_adjoint_step": (C.c_int, [vp, vp, i64, vp, vp, vp, C.POINTER(psm_body), dp, C.c_double, vp]),
         "psm_adjoint_omega": (C.c_int, [vp, vp, vp]),
+        "lbm_set_obstacle": (C.c_int, [vp, vp, vp, sz, C.POINTER(i64), vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)

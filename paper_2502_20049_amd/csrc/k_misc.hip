@@ -45,6 +45,8 @@ __device__ double read_f(const SCArgs &a, int parity, int k, int x, int y, int z
   const uint64_t N = a.N;
   const T *A = (const T *)a.pdf;
   if (parity == 0) return (double)A[(uint64_t)k * N + n];
+  // obstacle cells are never updated: their own slots hold their values
+  if (a.ocls && a.ocls[n] == 2) return (double)A[(uint64_t)k * N + n];
   const int ex = cx<Q>(k), ey = cy<Q>(k), ez = cz<Q>(k);
   int sx = x - ex, sy = y - ey, sz = z - ez;
   int kd = K_NONE;
@@ -62,7 +64,8 @@ __device__ double read_f(const SCArgs &a, int parity, int k, int x, int y, int z
   }
   if (kd == K_NONE) {
     const uint64_t src = (uint64_t)sx + (uint64_t)a.nx * ((uint64_t)sy + (uint64_t)a.ny * (uint64_t)sz);
-    return (double)A[(uint64_t)opp<Q>(k) * N + src];
+    if (!(a.ocls && a.ocls[src] == 2)) return (double)A[(uint64_t)opp<Q>(k) * N + src];
+    kd = K_WALL;  // link into an obstacle cell: bounce-back, the wall rule
   }
   double v = (double)A[(uint64_t)k * N + n];
   if (kd == K_INLET) v += 6.0 * wt<Q>(k) * (ex * a.u_in_d[0] + ey * a.u_in_d[1] + ez * a.u_in_d[2]);
@@ -179,6 +182,113 @@ __global__ void k_flags_copy(const int32_t *s, int32_t *d) {
 
 hipError_t launch_flags_copy(const int32_t *src, int32_t *dst, hipStream_t st) {
   hipLaunchKernelGGL(k_flags_copy, dim3(1), dim3(64), 0, st, src, dst);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Static obstacle of a plain-LBM field (set-up, once): per cell the class
+// (0 bulk fluid, 1 fluid with a link into an obstacle cell, 2 obstacle), the
+// list of class-1 cells as (cell, link mask) pairs, and the bounding box of
+// the cells of class 1 and 2.  Bit k of a link mask is set when the source
+// x - c_k of direction k is an obstacle cell (periodic wrap; a source beyond a
+// non-periodic face belongs to the face rules).
+// ---------------------------------------------------------------------------
+__global__ void k_obst_init(ObstHdr *h) {
+  if (threadIdx.x == 0) {
+    h->count = 0;
+    for (int d = 0; d < 3; ++d) {
+      h->lo[d] = 0x7fffffff;
+      h->hi[d] = -1;
+    }
+  }
+}
+
+__device__ __forceinline__ int wave_min_i(int v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ int wave_max_i(int v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+template <int Q>
+__global__ __launch_bounds__(256) void k_obst_build(const SCArgs a, const uint8_t *solid, uint8_t *cls,
+                                                    uint32_t *list, uint32_t cap, ObstHdr *h) {
+  const uint64_t n64 = (uint64_t)blockIdx.x * 256u + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const bool act = n64 < (uint64_t)a.N;
+  const uint32_t n = act ? (uint32_t)n64 : 0u;
+  const uint32_t nx = (uint32_t)a.nx, nxy = nx * (uint32_t)a.ny;
+  const int z = (int)(n / nxy), y = (int)((n - (uint32_t)z * nxy) / nx), x = (int)(n - (uint32_t)z * nxy - (uint32_t)y * nx);
+  uint32_t mask = 0;
+  int c = 0;
+  if (act) {
+    if (solid[n]) {
+      c = 2;
+    } else {
+      sfor<Q>([&](auto K) {
+        constexpr int k = K;
+        if constexpr (k != 0) {
+          int s[3] = {x - cx<Q>(k), y - cy<Q>(k), z - cz<Q>(k)};
+          const int nn[3] = {a.nx, a.ny, a.nz};
+          bool out = false;
+          for (int d = 0; d < 3; ++d) {
+            if (s[d] < 0 || s[d] >= nn[d]) {
+              if (a.periodic[d]) s[d] = s[d] < 0 ? s[d] + nn[d] : s[d] - nn[d];
+              else out = true;
+            }
+          }
+          if (!out) {
+            const uint32_t src = (uint32_t)s[0] + nx * (uint32_t)s[1] + nxy * (uint32_t)s[2];
+            if (solid[src]) mask |= 1u << k;
+          }
+        }
+      });
+      c = mask ? 1 : 0;
+    }
+    cls[n] = (uint8_t)c;
+  }
+  const bool near = act && c == 1;
+  const unsigned long long bm = __ballot(near);
+  if (bm) {
+    const int leader = __ffsll((long long)bm) - 1;
+    uint32_t base = 0;
+    if (lane == leader) base = atomicAdd(&h->count, (uint32_t)__popcll(bm));
+    base = __shfl(base, leader);
+    const uint32_t pos = base + (uint32_t)__popcll(bm & ((1ull << lane) - 1ull));
+    if (near && pos < cap) {
+      list[2 * (size_t)pos] = n;
+      list[2 * (size_t)pos + 1] = mask;
+    }
+  }
+  const bool in = act && c != 0;
+  if (__ballot(in)) {
+    const int lx = wave_min_i(in ? x : 0x7fffffff), ly = wave_min_i(in ? y : 0x7fffffff),
+              lz = wave_min_i(in ? z : 0x7fffffff);
+    const int hx = wave_max_i(in ? x : -1), hy = wave_max_i(in ? y : -1), hz = wave_max_i(in ? z : -1);
+    if (lane == 0) {
+      atomicMin(&h->lo[0], lx);
+      atomicMin(&h->lo[1], ly);
+      atomicMin(&h->lo[2], lz);
+      atomicMax(&h->hi[0], hx);
+      atomicMax(&h->hi[1], hy);
+      atomicMax(&h->hi[2], hz);
+    }
+  }
+}
+
+hipError_t launch_obst_build(const psm_field &f, const uint8_t *solid, uint8_t *cls, uint32_t *list, uint32_t cap,
+                             ObstHdr *h, hipStream_t st) {
+  const SCArgs a = make_sc_args(f);
+  hipLaunchKernelGGL(k_obst_init, dim3(1), dim3(64), 0, st, h);
+  const dim3 g((unsigned)((f.N + 255) / 256));
+  if (f.cfg.q == 19)
+    hipLaunchKernelGGL((k_obst_build<19>), g, dim3(256), 0, st, a, solid, cls, list, cap, h);
+  else
+    hipLaunchKernelGGL((k_obst_build<27>), g, dim3(256), 0, st, a, solid, cls, list, cap, h);
   return hipGetLastError();
 }
 

@@ -535,14 +535,23 @@ __device__ __forceinline__ void fluid_row_cell(const SCArgs &a, int x, int y, in
 }
 
 // A wave's cell: skip lanes past the row end and, with PSM, cells whose B is
-// nonzero (those belong to the solid kernel).
+// nonzero (those belong to the solid kernel); without PSM, with a static
+// obstacle, obstacle cells and the fluid cells next to them (the obstacle
+// kernel takes those).
 template <typename R, bool PSM>
 __device__ __forceinline__ bool fluid_lane(const SCArgs &a, int x, int y, int z, size_t rowbase) {
   if (x >= a.nx) return false;
+  const int x0 = x & ~(a.TX - 1);
   if constexpr (PSM) {
-    const int x0 = x & ~(a.TX - 1);
     if (boxes_touch(a, x0, x0 + a.TX - 1, y, y, z, z) && solid_fraction<R>(a, rowbase + (size_t)x) != R(0))
       return false;
+  } else {
+    if (a.ocls) {
+      const IBox &B = a.obox;
+      if (x0 + a.TX - 1 >= B.lo[0] && x0 <= B.hi[0] && y >= B.lo[1] && y <= B.hi[1] && z >= B.lo[2] &&
+          z <= B.hi[2] && a.ocls[rowbase + (size_t)x] != 0)
+        return false;
+    }
   }
   return true;
 }
@@ -765,20 +774,10 @@ __global__ __launch_bounds__(256) void k_fluid_edge(const SCArgs a) {
 // Fluid cells with the general per-lane face handling, one thread per cell in
 // linear order (the cross-check path of PSM_OPT_GENERAL_PATH).
 // ---------------------------------------------------------------------------
-template <int Q, typename T, int PAR, bool PSM>
-__global__ __launch_bounds__(256) void k_fluid_general(const SCArgs a) {
+template <int Q, typename T, int PAR>
+__device__ __forceinline__ void general_cell(const SCArgs &a, int x, int y, int z, uint64_t n, uint32_t bcm,
+                                             uint32_t outm, uint32_t inm) {
   using R = typename Comp<T>::type;
-  const uint64_t i = (uint64_t)blockIdx.x * 256u + threadIdx.x;
-  if (i >= (uint64_t)a.N) return;
-  const int x = (int)(i % (uint64_t)a.nx);
-  const int y = (int)((i / (uint64_t)a.nx) % (uint64_t)a.ny);
-  const int z = (int)(i / ((uint64_t)a.nx * (uint64_t)a.ny));
-  const uint64_t n = (uint64_t)x + (uint64_t)a.nx * ((uint64_t)y + (uint64_t)a.ny * (uint64_t)z);
-  if constexpr (PSM) {
-    if (boxes_touch(a, x, x, y, y, z, z) && solid_fraction<R>(a, n) != R(0)) return;
-  }
-  uint32_t bcm, outm, inm;
-  classify<Q>(a, x, y, z, bcm, outm, inm);
   R f[Q];
   sfor<Q>([&](auto K) {
     constexpr int k = K;
@@ -798,6 +797,46 @@ __global__ __launch_bounds__(256) void k_fluid_general(const SCArgs a) {
     }
     stv<T, R>(slot_general<Q, T, PAR>(a, a.pdf, k, x, y, z, n, bcm), v);
   });
+}
+
+template <int Q, typename T, int PAR, bool PSM>
+__global__ __launch_bounds__(256) void k_fluid_general(const SCArgs a) {
+  using R = typename Comp<T>::type;
+  const uint64_t i = (uint64_t)blockIdx.x * 256u + threadIdx.x;
+  if (i >= (uint64_t)a.N) return;
+  const int x = (int)(i % (uint64_t)a.nx);
+  const int y = (int)((i / (uint64_t)a.nx) % (uint64_t)a.ny);
+  const int z = (int)(i / ((uint64_t)a.nx * (uint64_t)a.ny));
+  const uint64_t n = (uint64_t)x + (uint64_t)a.nx * ((uint64_t)y + (uint64_t)a.ny * (uint64_t)z);
+  if constexpr (PSM) {
+    if (boxes_touch(a, x, x, y, y, z, z) && solid_fraction<R>(a, n) != R(0)) return;
+  } else {
+    if (a.ocls && a.ocls[n] != 0) return;
+  }
+  uint32_t bcm, outm, inm;
+  classify<Q>(a, x, y, z, bcm, outm, inm);
+  general_cell<Q, T, PAR>(a, x, y, z, n, bcm, outm, inm);
+}
+
+// ---------------------------------------------------------------------------
+// Fluid cells next to a static obstacle (plain-LBM fields), one thread per
+// listed cell: a link into an obstacle cell takes halfway bounce-back, the
+// wall rule, ahead of the face kinds (wall > inlet > outlet).  Obstacle cells
+// are never touched.
+// ---------------------------------------------------------------------------
+template <int Q, typename T, int PAR>
+__global__ __launch_bounds__(256) void k_obstacle(const SCArgs a) {
+  const uint32_t i = blockIdx.x * 256u + threadIdx.x;
+  if (i >= a.ocount) return;
+  const uint32_t n = a.olist[2 * (size_t)i], lm = a.olist[2 * (size_t)i + 1];
+  const uint32_t nx = (uint32_t)a.nx, nxy = nx * (uint32_t)a.ny;
+  const uint32_t z = n / nxy, r = n - z * nxy, y = r / nx, x = r - y * nx;
+  uint32_t bcm, outm, inm;
+  classify<Q>(a, (int)x, (int)y, (int)z, bcm, outm, inm);
+  bcm |= lm;
+  outm &= ~lm;
+  inm &= ~lm;
+  general_cell<Q, T, PAR>(a, (int)x, (int)y, (int)z, (uint64_t)n, bcm, outm, inm);
 }
 
 // ---------------------------------------------------------------------------

@@ -132,6 +132,10 @@ SCArgs make_sc_args(const psm_field &f) {
   a.max_bodies = std::max(1, c.max_bodies);
   a.slots = c.slots;
   a.dB = f.opt_whole_domain ? f.dB : nullptr;
+  a.ocls = f.ocls;
+  a.olist = f.olist;
+  a.ocount = f.ocount;
+  a.obox = f.obox;
   return a;
 }
 
@@ -165,6 +169,9 @@ extern "C" {
 
 const char *psm_last_error(void) { return g_err.c_str(); }
 
+// obstacle buffer: header (256 B), class bytes (N, padded to 256 B), list
+static size_t obst_list_offset(int64_t N) { return 256 + (((size_t)N + 255) & ~(size_t)255); }
+
 int psm_required_bytes(const psm_config *cfg, int which, size_t *out) {
   int r = check_config(cfg);
   if (r) return r;
@@ -185,6 +192,9 @@ int psm_required_bytes(const psm_config *cfg, int which, size_t *out) {
       return PSM_OK;
     case PSM_BUF_GRAD_B:
       *out = (size_t)L.N * (cfg->storage == PSM_F64 ? 8 : 4);
+      return PSM_OK;
+    case PSM_BUF_OBSTACLE:
+      *out = cfg->psm ? 0 : obst_list_offset(L.N) + 8 * (size_t)L.N;
       return PSM_OK;
   }
   return set_error("bad buffer id"), PSM_EINVAL;
@@ -726,6 +736,48 @@ int psm_set_fraction_offset(psm_field *f, const float *dB) {
   if (((uintptr_t)dB) & 3u) return set_error("offset field must be 4-byte aligned"), PSM_EINVAL;
   f->dB = dB;
   f->opt_whole_domain = dB != nullptr;
+  return PSM_OK;
+}
+
+int lbm_set_obstacle(psm_field *f, const uint8_t *solid_dev, void *obst_dev, size_t obst_bytes, int64_t *n_near,
+                     void *stream) {
+  if (!f) return set_error("null handle"), PSM_EINVAL;
+  f->ocls = nullptr;
+  f->olist = nullptr;
+  f->ocount = 0;
+  f->obox = empty_box();
+  if (n_near) *n_near = 0;
+  if (!solid_dev) return PSM_OK;
+  if (f->cfg.psm) return set_error("a static obstacle needs a plain-LBM field (psm = 0)"), PSM_EUNSUP;
+  if (!obst_dev) return set_error("null obstacle buffer"), PSM_EINVAL;
+  if (((uintptr_t)obst_dev) & 255u) return set_error("obstacle buffer must be 256-byte aligned"), PSM_EINVAL;
+  const size_t off = obst_list_offset(f->N);
+  if (obst_bytes < off) return set_error("obstacle buffer smaller than its header and class map"), PSM_ESIZE;
+  const size_t cap64 = (obst_bytes - off) / 8;
+  const uint32_t cap = (uint32_t)std::min<size_t>(cap64, (size_t)f->N);
+  char *base = (char *)obst_dev;
+  ObstHdr *h = (ObstHdr *)base;
+  uint8_t *cls = (uint8_t *)(base + 256);
+  uint32_t *list = (uint32_t *)(base + off);
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = launch_obst_build(*f, solid_dev, cls, list, cap, h, st);
+  if (e != hipSuccess) return hip_fail(e, "lbm_set_obstacle build");
+  ObstHdr hh;
+  e = hipMemcpyAsync(&hh, h, sizeof(hh), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "lbm_set_obstacle read-back");
+  if (n_near) *n_near = hh.count;
+  if (hh.count > cap)
+    return set_error("obstacle list needs " + std::to_string(hh.count) + " entries, the buffer holds " +
+                     std::to_string(cap)),
+           PSM_ESIZE;
+  f->ocls = cls;
+  f->olist = list;
+  f->ocount = hh.count;
+  for (int d = 0; d < 3; ++d) {
+    f->obox.lo[d] = hh.lo[d];
+    f->obox.hi[d] = hh.hi[d];
+  }
   return PSM_OK;
 }
 

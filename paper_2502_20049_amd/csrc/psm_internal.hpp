@@ -119,6 +119,18 @@ struct SCArgs {
   uint32_t cprefix[PSM_MAX_BODIES + 1];  // 256-cell chunk offsets of the boxes
   uint32_t nchunks;
   BodyK body[PSM_MAX_BODIES];
+  // static obstacle of a plain-LBM field (ocls null: none)
+  const uint8_t *ocls;    // per cell: 0 bulk fluid, 1 fluid next to the obstacle, 2 obstacle
+  const uint32_t *olist;  // class-1 cells as (cell, link mask) pairs
+  uint32_t ocount;
+  IBox obox;              // bounding box of the class-1 and class-2 cells
+};
+
+// header of the obstacle buffer (set-up counters)
+struct ObstHdr {
+  uint32_t count;
+  int32_t lo[3];
+  int32_t hi[3];
 };
 
 // arguments of the adjoint step kernel
@@ -205,6 +217,11 @@ struct psm_field {
   int opt_xcd_remap;
   int opt_whole_domain;  // B may be nonzero anywhere (offset field set)
   const float *dB;       // caller-owned offset added to the slot-0 fraction
+  // static obstacle (plain-LBM fields; null: none)
+  uint8_t *ocls;
+  uint32_t *olist;
+  uint32_t ocount;
+  psm::IBox obox;
 };
 
 struct psm_geom {
@@ -236,6 +253,8 @@ hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t st)
 hipError_t launch_flags_copy(const int32_t *src, int32_t *dst, hipStream_t st);
 uint32_t macro_blocks(const psm_field &f);
 hipError_t launch_sum_accumulate(const double *p, uint32_t n, double *out, hipStream_t st);
+hipError_t launch_obst_build(const psm_field &f, const uint8_t *solid, uint8_t *cls, uint32_t *list, uint32_t cap,
+                             ObstHdr *h, hipStream_t st);
 
 // host geometry
 int geom_box(int kind, const double *params, const double *verts, int64_t nv, int s, int32_t mmin[3],

@@ -190,6 +190,22 @@ class Field:
         if ft is not None and self.nb:
             self.force_torque(out=ft)
 
+    def set_obstacle(self, solid):
+        """Static no-slip obstacle of a plain-LBM field: ``solid`` is an (N,)
+        uint8 device tensor (1 = obstacle cell), None removes it.  Returns the
+        number of fluid cells next to the obstacle."""
+        nn = C.c_int64()
+        if solid is None:
+            check(lib.lbm_set_obstacle(self.handle, None, None, 0, C.byref(nn), _stream()), "lbm_set_obstacle")
+            self.obst = None
+            return 0
+        assert solid.dtype == torch.uint8 and solid.numel() == self.N and solid.is_contiguous()
+        ob = required_bytes(self.cfg, capi.PSM_BUF_OBSTACLE)
+        self.obst = torch.empty(ob, dtype=torch.uint8, device=self.pdf.device)
+        check(lib.lbm_set_obstacle(self.handle, C.c_void_p(solid.data_ptr()), C.c_void_p(self.obst.data_ptr()), ob,
+                                   C.byref(nn), _stream()), "lbm_set_obstacle")
+        return nn.value
+
     def force_torque(self, out=None):
         out = self.ft if out is None else out
         check(lib.body_force_torque(self.handle, self.nb, C.c_void_p(out.data_ptr()), _stream()), "body_force_torque")
@@ -217,6 +233,22 @@ class Field:
         if getattr(self, "handle", None) and self.handle.value:
             lib.pdf_field_destroy(self.handle)
             self.handle = C.c_void_p()
+
+
+def voxelize_obstacle(wl, t: int = 0, device="cuda"):
+    """(N,) uint8 obstacle flags of the workload's bodies at step t: a cell is
+    an obstacle cell when its centre lies inside a body (the mapping with one
+    sample per cell, s = 0)."""
+    import dataclasses
+
+    wl0 = dataclasses.replace(wl, bodies=[dataclasses.replace(b, s=0) for b in wl.bodies])
+    f = Field(wl0, storage="f32", psm=True, device=device)
+    f.map(t)
+    B, _ = f.b_view()
+    solid = (B.sum(0) > 0).to(torch.uint8).contiguous()
+    torch.cuda.synchronize()
+    del f
+    return solid
 
 
 def stream_copy(src: torch.Tensor, dst: torch.Tensor):

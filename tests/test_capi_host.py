@@ -58,9 +58,12 @@ def test_required_bytes(capi, sim):
     assert sim.required_bytes(cfg, capi.PSM_BUF_B) == 2 * N * 4 + N
     cfg.q, cfg.storage = 27, capi.PSM_F16
     assert sim.required_bytes(cfg, capi.PSM_BUF_PDF) == 27 * N * 2
+    assert sim.required_bytes(cfg, capi.PSM_BUF_OBSTACLE) == 0
     cfg.psm = 0
     assert sim.required_bytes(cfg, capi.PSM_BUF_B) == 0
     assert sim.required_bytes(cfg, capi.PSM_BUF_WORK) > 256
+    # header + class bytes padded to 256 + one 8-byte list entry per cell
+    assert sim.required_bytes(cfg, capi.PSM_BUF_OBSTACLE) == 256 + ((N + 255) // 256) * 256 + 8 * N
 
 
 @pytest.mark.parametrize("field,value,code", [
