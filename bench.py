@@ -198,7 +198,7 @@ def s_sweep(steps=200):
     return out
 
 
-def node_benchmark(steps=200):
+def node_benchmark(steps=600):
     """The paper's node-level comparison (section V) on one GPU, periodic
     lattices (inflow / outflow excluded, as there): plain LBM; LBM with the
     no-slip treatment of the stationary voxelised geometry (lbm_set_obstacle);

@@ -843,105 +843,147 @@ __global__ __launch_bounds__(256) void k_obstacle(const SCArgs a) {
 // Cells with a nonzero solid fraction (inside the bodies' current boxes):
 // the PSM blend of eq. (4) with SC1/2/3 over up to two body slots, full face
 // handling, and the force / torque of eqs. (10)-(11) on each body.  A fixed
-// grid of workgroups walks the boxes' 256-cell chunks in a fixed order and
-// keeps per-body FP64 sums in LDS (deterministic), written once per
-// workgroup.  A cell inside several boxes is taken by the lowest-index box.
+// grid of workgroups walks groups of a.cpw consecutive 256-cell chunks of the
+// boxes in a fixed order; a workgroup first lists the group's cells with
+// B != 0 in LDS (ascending order), then updates the list 256 cells at a time,
+// so thin or sparse solids still fill whole waves.  Per-body FP64 sums are
+// kept in LDS (deterministic) and written once per workgroup.  A cell inside
+// several boxes is taken by the lowest-index box.
 // ---------------------------------------------------------------------------
 template <int Q, typename T, int PAR, int SC>
 __global__ __launch_bounds__(256) void k_solid(const SCArgs a) {
   using R = typename Comp<T>::type;
   __shared__ double acc[PSM_MAX_BODIES][6];
   __shared__ double wred[4][6];
+  __shared__ uint32_t cells_l[SOLID_MAX_CPW * 256];
+  __shared__ uint32_t wcnt[SOLID_MAX_CPW][4];
   const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
   if (tid < PSM_MAX_BODIES * 6) acc[tid / 6][tid % 6] = 0.0;
   __syncthreads();
-  for (uint32_t ch = blockIdx.x; ch < a.nchunks; ch += gridDim.x) {
-    int rb = 0;
-    while (rb + 1 < a.nbox && ch >= a.cprefix[rb + 1]) ++rb;
-    const IBox &G = a.box[rb];
-    const uint64_t idx = (uint64_t)(ch - a.cprefix[rb]) * 256u + tid;
-    const int ex_ = G.hi[0] - G.lo[0] + 1, ey_ = G.hi[1] - G.lo[1] + 1;
-    const uint64_t cells = (uint64_t)ex_ * (uint64_t)ey_ * (uint64_t)(G.hi[2] - G.lo[2] + 1);
-    const int x = G.lo[0] + (int)(idx % (uint64_t)ex_);
-    const int y = G.lo[1] + (int)((idx / (uint64_t)ex_) % (uint64_t)ey_);
-    const int z = G.lo[2] + (int)(idx / ((uint64_t)ex_ * (uint64_t)ey_));
-    bool act = idx < cells;
-    for (int b = 0; b < rb; ++b)
-      if (box_has(a.box[b], x, y, z)) act = false;
-    const uint64_t n = act ? (uint64_t)x + (uint64_t)a.nx * ((uint64_t)y + (uint64_t)a.ny * (uint64_t)z) : 0;
-    R B0 = 0, B1 = 0;
-    int b0 = 0, b1 = 0;
-    bool two = false;
-    if (act) {
-      B0 = solid_fraction<R>(a, n);
-      act = B0 != R(0);
-    }
-    if (act) {
-      const uint8_t m = a.meta[n];
-      b0 = m & 15;
-      if (b0 >= a.nb) b0 = 0;  // ids come from the mapping; never index past the body table
-      if (a.slots == 2 && (m >> 4)) {
-        b1 = (m >> 4) - 1;
-        if (b1 >= a.nb) b1 = 0;
-        B1 = (R)a.B1[n];
-        two = true;
-      }
-    }
-    R mom0[3] = {0, 0, 0}, mom1[3] = {0, 0, 0};
-    if (__syncthreads_or(act)) {
-      uint32_t bcm = 0, outm = 0, inm = 0;
-      R f[Q];
-      if (act) {
-        classify<Q>(a, x, y, z, bcm, outm, inm);
-        sfor<Q>([&](auto K) {
-          constexpr int k = K;
-          R v = ldv<T, R>(slot_general<Q, T, PAR>(a, a.pdf, k, x, y, z, n, bcm));
-          if constexpr (PAR == 1) {
-            if ((inm >> k) & 1u) v += inlet_term<Q, R>(a, k);
-          }
-          f[k] = v;
-        });
-      } else {
-        sfor<Q>([&](auto K) { f[K] = R(0); });
-      }
-      R us0[3] = {0, 0, 0}, us1[3] = {0, 0, 0};
-      const double xc = x + 0.5, yc = y + 0.5, zc = z + 0.5;
-      for (int b = 0; b < a.nb; ++b) {  // uniform loop: body data stays scalar
-        const BodyK &bd = a.body[b];
-        if (act && (b0 == b || (two && b1 == b))) {
-          const R rx = (R)(xc - bd.X[0]), ry = (R)(yc - bd.X[1]), rz = (R)(zc - bd.X[2]);
-          const R wx = (R)bd.W[0], wy = (R)bd.W[1], wz = (R)bd.W[2];
-          R u0 = (R)bd.V[0] + (wy * rz - wz * ry);
-          R u1 = (R)bd.V[1] + (wz * rx - wx * rz);
-          R u2 = (R)bd.V[2] + (wx * ry - wy * rx);
-          if (b0 == b) {
-            us0[0] = u0;
-            us0[1] = u1;
-            us0[2] = u2;
-          }
-          if (two && b1 == b) {
-            us1[0] = u0;
-            us1[1] = u1;
-            us1[2] = u2;
-          }
+  const uint32_t cpw = (uint32_t)a.cpw;
+  const uint32_t ngroups = (a.nchunks + cpw - 1) / cpw;
+  const uint32_t nx = (uint32_t)a.nx, nxy = nx * (uint32_t)a.ny;
+  for (uint32_t grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {
+    // 1. the group's cells with B != 0, listed in ascending (chunk, thread) order
+    uint32_t mine[SOLID_MAX_CPW];
+    bool hit[SOLID_MAX_CPW];
+#pragma unroll
+    for (int j = 0; j < SOLID_MAX_CPW; ++j) {
+      hit[j] = false;
+      mine[j] = 0;
+      const uint32_t ch = grp * cpw + (uint32_t)j;
+      if ((uint32_t)j < cpw && ch < a.nchunks) {
+        int rb = 0;
+        while (rb + 1 < a.nbox && ch >= a.cprefix[rb + 1]) ++rb;
+        const IBox &G = a.box[rb];
+        const uint64_t idx64 = (uint64_t)(ch - a.cprefix[rb]) * 256u + (uint64_t)tid;
+        const uint32_t ex_ = (uint32_t)(G.hi[0] - G.lo[0] + 1), ey_ = (uint32_t)(G.hi[1] - G.lo[1] + 1);
+        const uint64_t cells = (uint64_t)ex_ * ey_ * (uint64_t)(G.hi[2] - G.lo[2] + 1);
+        if (idx64 < cells) {
+          const uint32_t idx = (uint32_t)idx64;
+          const uint32_t bz = idx / (ex_ * ey_), br = idx - bz * ex_ * ey_, by = br / ex_, bx = br - by * ex_;
+          const int x = G.lo[0] + (int)bx, y = G.lo[1] + (int)by, z = G.lo[2] + (int)bz;
+          bool act = true;
+          for (int b = 0; b < rb; ++b)
+            if (box_has(a.box[b], x, y, z)) act = false;
+          const uint32_t n = (uint32_t)x + nx * (uint32_t)y + nxy * (uint32_t)z;
+          if (act) act = solid_fraction<R>(a, n) != R(0);
+          hit[j] = act;
+          mine[j] = n;
         }
       }
-      if (__any(two)) {
-        collide<Q, SC, 2, R>(f, a, B0, us0, B1, us1, mom0, mom1);
-      } else {
-        collide<Q, SC, 1, R>(f, a, B0, us0, B1, us1, mom0, mom1);
-      }
+      const unsigned long long bm = __ballot(hit[j]);
+      if (lane == 0) wcnt[j][wid] = (uint32_t)__popcll(bm);
+    }
+    __syncthreads();
+    uint32_t total = 0;
+#pragma unroll
+    for (int j = 0; j < SOLID_MAX_CPW; ++j) {
+      const unsigned long long bm = __ballot(hit[j]);
+      uint32_t off = total;
+      for (int w = 0; w < wid; ++w) off += wcnt[j][w];
+      if (hit[j]) cells_l[off + (uint32_t)__popcll(bm & ((1ull << lane) - 1ull))] = mine[j];
+      total += (wcnt[j][0] + wcnt[j][1]) + (wcnt[j][2] + wcnt[j][3]);
+    }
+    __syncthreads();
+    // 2. the listed cells, 256 at a time
+    for (uint32_t base = 0; base < total; base += 256) {
+      const uint32_t li = base + (uint32_t)tid;
+      bool act = li < total;
+      const uint32_t n = act ? cells_l[li] : 0u;
+      const int z = (int)(n / nxy), y = (int)((n - (uint32_t)z * nxy) / nx),
+                x = (int)(n - (uint32_t)z * nxy - (uint32_t)y * nx);
+      R B0 = 0, B1 = 0;
+      int b0 = 0, b1 = 0;
+      bool two = false;
       if (act) {
-        sfor<Q>([&](auto K) {
-          constexpr int k = K;
-          R v = ((outm >> k) & 1u) ? f[k] : f[opp<Q>(k)];
-          if constexpr (PAR == 1) {
-            if ((inm >> k) & 1u) v += inlet_term<Q, R>(a, k);
-          }
-          stv<T, R>(slot_general<Q, T, PAR>(a, a.pdf, k, x, y, z, n, bcm), v);
-        });
+        B0 = solid_fraction<R>(a, n);
+        const uint8_t m = a.meta[n];
+        b0 = m & 15;
+        if (b0 >= a.nb) b0 = 0;  // ids come from the mapping; never index past the body table
+        if (a.slots == 2 && (m >> 4)) {
+          b1 = (m >> 4) - 1;
+          if (b1 >= a.nb) b1 = 0;
+          B1 = (R)a.B1[n];
+          two = true;
+        }
       }
-      // force / torque on each body touched by this chunk
+      R mom0[3] = {0, 0, 0}, mom1[3] = {0, 0, 0};
+      const double xc = x + 0.5, yc = y + 0.5, zc = z + 0.5;
+      if (__any(act)) {  // wave-uniform: waves past the list's end skip the update
+        uint32_t bcm = 0, outm = 0, inm = 0;
+        R f[Q];
+        if (act) {
+          classify<Q>(a, x, y, z, bcm, outm, inm);
+          sfor<Q>([&](auto K) {
+            constexpr int k = K;
+            R v = ldv<T, R>(slot_general<Q, T, PAR>(a, a.pdf, k, x, y, z, n, bcm));
+            if constexpr (PAR == 1) {
+              if ((inm >> k) & 1u) v += inlet_term<Q, R>(a, k);
+            }
+            f[k] = v;
+          });
+        } else {
+          sfor<Q>([&](auto K) { f[K] = R(0); });
+        }
+        R us0[3] = {0, 0, 0}, us1[3] = {0, 0, 0};
+        for (int b = 0; b < a.nb; ++b) {  // uniform loop: body data stays scalar
+          const BodyK &bd = a.body[b];
+          if (act && (b0 == b || (two && b1 == b))) {
+            const R rx = (R)(xc - bd.X[0]), ry = (R)(yc - bd.X[1]), rz = (R)(zc - bd.X[2]);
+            const R wx = (R)bd.W[0], wy = (R)bd.W[1], wz = (R)bd.W[2];
+            R u0 = (R)bd.V[0] + (wy * rz - wz * ry);
+            R u1 = (R)bd.V[1] + (wz * rx - wx * rz);
+            R u2 = (R)bd.V[2] + (wx * ry - wy * rx);
+            if (b0 == b) {
+              us0[0] = u0;
+              us0[1] = u1;
+              us0[2] = u2;
+            }
+            if (two && b1 == b) {
+              us1[0] = u0;
+              us1[1] = u1;
+              us1[2] = u2;
+            }
+          }
+        }
+        if (__any(two)) {
+          collide<Q, SC, 2, R>(f, a, B0, us0, B1, us1, mom0, mom1);
+        } else {
+          collide<Q, SC, 1, R>(f, a, B0, us0, B1, us1, mom0, mom1);
+        }
+        if (act) {
+          sfor<Q>([&](auto K) {
+            constexpr int k = K;
+            R v = ((outm >> k) & 1u) ? f[k] : f[opp<Q>(k)];
+            if constexpr (PAR == 1) {
+              if ((inm >> k) & 1u) v += inlet_term<Q, R>(a, k);
+            }
+            stv<T, R>(slot_general<Q, T, PAR>(a, a.pdf, k, x, y, z, n, bcm), v);
+          });
+        }
+      }
+      // force / torque on each body touched by these cells
       for (int b = 0; b < a.nb; ++b) {
         const bool has = act && (b0 == b || (two && b1 == b));
         if (!__syncthreads_or(has)) continue;
@@ -978,6 +1020,7 @@ __global__ __launch_bounds__(256) void k_solid(const SCArgs a) {
         __syncthreads();
       }
     }
+    __syncthreads();  // the list is rebuilt for the next group
   }
   __syncthreads();
   if (tid < a.nb * 6) a.ftp[((size_t)blockIdx.x * a.max_bodies + tid / 6) * 6 + tid % 6] = acc[tid / 6][tid % 6];

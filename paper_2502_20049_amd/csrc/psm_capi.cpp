@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "psm_internal.hpp"
 
@@ -132,6 +133,7 @@ SCArgs make_sc_args(const psm_field &f) {
   a.max_bodies = std::max(1, c.max_bodies);
   a.slots = c.slots;
   a.dB = f.opt_whole_domain ? f.dB : nullptr;
+  a.cpw = 1;
   a.ocls = f.ocls;
   a.olist = f.olist;
   a.ocount = f.ocount;
@@ -640,6 +642,10 @@ static int sc_plan(psm_field *f, const psm_body *bodies, int nb, int64_t step, c
     for (int b = 1; b <= a.nb; ++b) a.cprefix[b] = whole;
     a.nchunks = whole;
   }
+  // chunks per workgroup group: enough groups for the fixed grid, at most
+  // SOLID_MAX_CPW chunks listed at once
+  a.cpw = (int)std::min<uint32_t>((uint32_t)SOLID_MAX_CPW,
+                                  std::max<uint32_t>(1u, (a.nchunks + SOLID_BLOCKS - 1) / SOLID_BLOCKS));
   a.xcd_remap = f->opt_xcd_remap;
   return PSM_OK;
 }
@@ -771,6 +777,20 @@ int lbm_set_obstacle(psm_field *f, const uint8_t *solid_dev, void *obst_dev, siz
     return set_error("obstacle list needs " + std::to_string(hh.count) + " entries, the buffer holds " +
                      std::to_string(cap)),
            PSM_ESIZE;
+  if (hh.count > 1) {
+    // the kernel appends in arrival order: sort by cell index once, so that
+    // neighbouring lanes of the list kernel update neighbouring cells
+    std::vector<uint64_t> v((size_t)hh.count);
+    e = hipMemcpyAsync(v.data(), list, v.size() * 8, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "lbm_set_obstacle list read-back");
+    for (uint64_t &x : v) x = (x << 32) | (x >> 32);  // (cell, mask) pairs -> key cell
+    std::sort(v.begin(), v.end());
+    for (uint64_t &x : v) x = (x << 32) | (x >> 32);
+    e = hipMemcpyAsync(list, v.data(), v.size() * 8, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "lbm_set_obstacle list upload");
+  }
   f->ocls = cls;
   f->olist = list;
   f->ocount = hh.count;

@@ -87,6 +87,8 @@ struct BodyK {
 // workgroups of the solid-cell kernel (fixed: its per-body partial sums are
 // independent of the grid size)
 constexpr int SOLID_BLOCKS = 2048;
+// at most this many 256-cell chunks per workgroup group of the solid kernel
+constexpr int SOLID_MAX_CPW = 8;
 
 struct SCArgs {
   char *pdf;
@@ -118,6 +120,7 @@ struct SCArgs {
   IBox box[PSM_MAX_BODIES];
   uint32_t cprefix[PSM_MAX_BODIES + 1];  // 256-cell chunk offsets of the boxes
   uint32_t nchunks;
+  int cpw;  // chunks per group of the solid kernel, 1..SOLID_MAX_CPW
   BodyK body[PSM_MAX_BODIES];
   // static obstacle of a plain-LBM field (ocls null: none)
   const uint8_t *ocls;    // per cell: 0 bulk fluid, 1 fluid next to the obstacle, 2 obstacle
