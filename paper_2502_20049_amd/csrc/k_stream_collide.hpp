@@ -856,6 +856,8 @@ __global__ __launch_bounds__(256) void k_solid(const SCArgs a) {
   __shared__ double acc[PSM_MAX_BODIES][6];
   __shared__ double wred[4][6];
   __shared__ uint32_t cells_l[SOLID_MAX_CPW * 256];
+  __shared__ R bfrac_l[SOLID_MAX_CPW * 256];
+  __shared__ uint8_t meta_l[SOLID_MAX_CPW * 256];
   __shared__ uint32_t wcnt[SOLID_MAX_CPW][4];
   const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
   if (tid < PSM_MAX_BODIES * 6) acc[tid / 6][tid % 6] = 0.0;
@@ -864,13 +866,18 @@ __global__ __launch_bounds__(256) void k_solid(const SCArgs a) {
   const uint32_t ngroups = (a.nchunks + cpw - 1) / cpw;
   const uint32_t nx = (uint32_t)a.nx, nxy = nx * (uint32_t)a.ny;
   for (uint32_t grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {
-    // 1. the group's cells with B != 0, listed in ascending (chunk, thread) order
+    // 1. the group's cells with B != 0, listed in ascending (chunk, thread)
+    //    order with their slot-0 fraction and body ids
     uint32_t mine[SOLID_MAX_CPW];
+    R bmine[SOLID_MAX_CPW];
+    uint8_t mmine[SOLID_MAX_CPW];
     bool hit[SOLID_MAX_CPW];
 #pragma unroll
     for (int j = 0; j < SOLID_MAX_CPW; ++j) {
       hit[j] = false;
       mine[j] = 0;
+      bmine[j] = R(0);
+      mmine[j] = 0;
       const uint32_t ch = grp * cpw + (uint32_t)j;
       if ((uint32_t)j < cpw && ch < a.nchunks) {
         int rb = 0;
@@ -887,9 +894,11 @@ __global__ __launch_bounds__(256) void k_solid(const SCArgs a) {
           for (int b = 0; b < rb; ++b)
             if (box_has(a.box[b], x, y, z)) act = false;
           const uint32_t n = (uint32_t)x + nx * (uint32_t)y + nxy * (uint32_t)z;
-          if (act) act = solid_fraction<R>(a, n) != R(0);
-          hit[j] = act;
+          const R b = solid_fraction<R>(a, n);
+          mmine[j] = a.meta[n];
+          hit[j] = act && b != R(0);
           mine[j] = n;
+          bmine[j] = b;
         }
       }
       const unsigned long long bm = __ballot(hit[j]);
@@ -902,7 +911,12 @@ __global__ __launch_bounds__(256) void k_solid(const SCArgs a) {
       const unsigned long long bm = __ballot(hit[j]);
       uint32_t off = total;
       for (int w = 0; w < wid; ++w) off += wcnt[j][w];
-      if (hit[j]) cells_l[off + (uint32_t)__popcll(bm & ((1ull << lane) - 1ull))] = mine[j];
+      if (hit[j]) {
+        const uint32_t e = off + (uint32_t)__popcll(bm & ((1ull << lane) - 1ull));
+        cells_l[e] = mine[j];
+        bfrac_l[e] = bmine[j];
+        meta_l[e] = mmine[j];
+      }
       total += (wcnt[j][0] + wcnt[j][1]) + (wcnt[j][2] + wcnt[j][3]);
     }
     __syncthreads();
@@ -917,8 +931,8 @@ __global__ __launch_bounds__(256) void k_solid(const SCArgs a) {
       int b0 = 0, b1 = 0;
       bool two = false;
       if (act) {
-        B0 = solid_fraction<R>(a, n);
-        const uint8_t m = a.meta[n];
+        B0 = bfrac_l[li];
+        const uint8_t m = meta_l[li];
         b0 = m & 15;
         if (b0 >= a.nb) b0 = 0;  // ids come from the mapping; never index past the body table
         if (a.slots == 2 && (m >> 4)) {
