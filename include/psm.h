@@ -237,6 +237,47 @@ int psm_step(psm_field *f, const psm_body *map_poses, const psm_body *bodies, co
  * domain as possibly solid (slower; meant for sensitivity runs). */
 int psm_set_fraction_offset(psm_field *f, const float *dB_dev);
 
+/* ---- two-way coupling: rigid bodies driven by the hydrodynamic force ------ */
+/* State of a freely moving rigid body (the settling-sphere validation of
+ * section IV: the body moves under gravity, buoyancy and the force / torque of
+ * eqs. (10)-(11)).  Lattice units.
+ *   m      mass
+ *   I      principal moments of inertia (body frame axes, about X)
+ *   F_ext  constant external force on the body (gravity minus buoyancy), lab
+ *   X, V   reference point (body-frame origin) and its velocity, lab
+ *   R      orientation (body -> lab, row-major), W angular velocity, lab */
+typedef struct psm_rigid {
+  double m;
+  double I[3];
+  double F_ext[3];
+  double X[3];
+  double V[3];
+  double R[9];
+  double W[3];
+} psm_rigid;
+
+/* Pose and velocity of a rigid-body state, for the mapping and the solid
+ * collision of the next step. */
+int psm_rigid_body(const psm_rigid *s, psm_body *out);
+
+/* Advance a rigid-body state by dt with the hydrodynamic force / torque
+ * ft = (F, T) of the step just taken (force on the body, torque about X):
+ * semi-implicit Euler,
+ *   V += dt (F + F_ext) / m,  X += dt V,
+ *   W += dt I_lab^-1 (T - W x (I_lab W)),  I_lab = R diag(I) R^T,
+ *   R <- Rot(dt W) R,  Rot by Rodrigues' formula about W / |W| (identity
+ *   when W = 0).  Host arithmetic, FP64.  m and every I must be > 0. */
+int psm_rigid_advance(psm_rigid *s, const double ft[6], double dt);
+
+/* One two-way coupled step of n_bodies free bodies: psm_step with the poses
+ * and velocities of states (map, stream-collide, F/T into ft_dev, device
+ * double[n_bodies][6]), then the F/T are copied to ft_host (host
+ * double[n_bodies][6], may be pinned), `stream` is synchronised, and every
+ * state advances by one step (dt = 1).  The states of step `step` in, those
+ * of step + 1 out. */
+int psm_coupled_step(psm_field *f, psm_rigid *states, const psm_geom *const *geoms, int n_bodies, int64_t step,
+                     double *ft_dev, double *ft_host, void *stream);
+
 /* ---- static no-slip obstacle (plain LBM) ----------------------------------- */
 /* The LBM variant of the paper's node-level benchmark (section V: an LBM
  * kernel plus the no-slip treatment of a stationary geometry).  For a field

@@ -27,8 +27,13 @@ EXPORTS = [
     "geometry_field_create", "geometry_field_create_analytic", "geometry_field_destroy", "geometry_map_step",
     "psm_stream_collide", "body_force_torque", "psm_mass_fp64", "psm_macroscopic", "psm_error_flags",
     "psm_set_option", "psm_stream_copy", "psm_set_fraction_offset", "psm_adjoint_step", "psm_adjoint_omega",
-    "psm_step", "lbm_set_obstacle",
+    "psm_step", "lbm_set_obstacle", "psm_rigid_body", "psm_rigid_advance", "psm_coupled_step",
 ]
+
+
+class psm_rigid(C.Structure):
+    _fields_ = [("m", C.c_double), ("I", C.c_double * 3), ("F_ext", C.c_double * 3), ("X", C.c_double * 3),
+                ("V", C.c_double * 3), ("R", C.c_double * 9), ("W", C.c_double * 3)]
 
 
 class psm_config(C.Structure):
@@ -87,6 +92,9 @@ def _load():
         "psm_adjoint_step": (C.c_int, [vp, vp, i64, vp, vp, vp, C.POINTER(psm_body), dp, C.c_double, vp]),
         "psm_adjoint_omega": (C.c_int, [vp, vp, vp]),
         "lbm_set_obstacle": (C.c_int, [vp, vp, vp, sz, C.POINTER(i64), vp]),
+        "psm_rigid_body": (C.c_int, [C.POINTER(psm_rigid), C.POINTER(psm_body)]),
+        "psm_rigid_advance": (C.c_int, [C.POINTER(psm_rigid), dp, C.c_double]),
+        "psm_coupled_step": (C.c_int, [vp, C.POINTER(psm_rigid), C.POINTER(vp), C.c_int, i64, vp, dp, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)

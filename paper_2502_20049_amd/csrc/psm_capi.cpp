@@ -698,6 +698,73 @@ int psm_step(psm_field *f, const psm_body *map_poses, const psm_body *bodies, co
   return r;
 }
 
+int psm_rigid_body(const psm_rigid *s, psm_body *out) {
+  if (!s || !out) return set_error("psm_rigid_body: null argument"), PSM_EINVAL;
+  for (int i = 0; i < 9; ++i) out->R[i] = s->R[i];
+  for (int d = 0; d < 3; ++d) {
+    out->X[d] = s->X[d];
+    out->V[d] = s->V[d];
+    out->W[d] = s->W[d];
+  }
+  return PSM_OK;
+}
+
+int psm_rigid_advance(psm_rigid *s, const double ft[6], double dt) {
+  if (!s || !ft) return set_error("psm_rigid_advance: null argument"), PSM_EINVAL;
+  if (!(s->m > 0.0) || !(s->I[0] > 0.0) || !(s->I[1] > 0.0) || !(s->I[2] > 0.0) || !isfinite(dt))
+    return set_error("psm_rigid_advance: mass and moments of inertia must be positive, dt finite"), PSM_EINVAL;
+  // translation
+  for (int d = 0; d < 3; ++d) {
+    s->V[d] += dt * ((ft[d] + s->F_ext[d]) / s->m);
+    s->X[d] += dt * s->V[d];
+  }
+  // rotation: body-frame components through R^T, inertia diagonal there
+  const double *R = s->R;
+  double wb[3], lb[3], L[3];
+  for (int i = 0; i < 3; ++i) wb[i] = R[i] * s->W[0] + R[3 + i] * s->W[1] + R[6 + i] * s->W[2];
+  for (int i = 0; i < 3; ++i) lb[i] = s->I[i] * wb[i];
+  for (int i = 0; i < 3; ++i) L[i] = R[3 * i] * lb[0] + R[3 * i + 1] * lb[1] + R[3 * i + 2] * lb[2];
+  const double rhs[3] = {ft[3] - (s->W[1] * L[2] - s->W[2] * L[1]), ft[4] - (s->W[2] * L[0] - s->W[0] * L[2]),
+                         ft[5] - (s->W[0] * L[1] - s->W[1] * L[0])};
+  double ab[3];
+  for (int i = 0; i < 3; ++i) ab[i] = (R[i] * rhs[0] + R[3 + i] * rhs[1] + R[6 + i] * rhs[2]) / s->I[i];
+  for (int i = 0; i < 3; ++i) s->W[i] += dt * (R[3 * i] * ab[0] + R[3 * i + 1] * ab[1] + R[3 * i + 2] * ab[2]);
+  // orientation: rotate by the angle dt |W| about W
+  const double om[3] = {dt * s->W[0], dt * s->W[1], dt * s->W[2]};
+  const double th = sqrt(om[0] * om[0] + om[1] * om[1] + om[2] * om[2]);
+  if (th > 0.0) {
+    const double a[3] = {om[0] / th, om[1] / th, om[2] / th};
+    const double c = cos(th), sn = sin(th), omc = 1.0 - c;
+    const double K[9] = {0.0, -a[2], a[1], a[2], 0.0, -a[0], -a[1], a[0], 0.0};
+    double Q[9], Rn[9];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) Q[3 * i + j] = ((i == j ? c : 0.0) + (omc * a[i]) * a[j]) + sn * K[3 * i + j];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) Rn[3 * i + j] = Q[3 * i] * R[j] + Q[3 * i + 1] * R[3 + j] + Q[3 * i + 2] * R[6 + j];
+    for (int i = 0; i < 9; ++i) s->R[i] = Rn[i];
+  }
+  return PSM_OK;
+}
+
+int psm_coupled_step(psm_field *f, psm_rigid *states, const psm_geom *const *geoms, int nb, int64_t step,
+                     double *ft_dev, double *ft_host, void *stream) {
+  if (!f || !states || !geoms || !ft_dev || !ft_host) return set_error("psm_coupled_step: null argument"), PSM_EINVAL;
+  if (nb < 1 || nb > PSM_MAX_BODIES) return set_error("psm_coupled_step: 1 .. PSM_MAX_BODIES bodies"), PSM_EINVAL;
+  psm_body P[PSM_MAX_BODIES];
+  for (int b = 0; b < nb; ++b) psm_rigid_body(&states[b], &P[b]);
+  int r = psm_step(f, P, P, geoms, nb, step, ft_dev, stream);
+  if (r) return r;
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = hipMemcpyAsync(ft_host, ft_dev, (size_t)nb * 6 * sizeof(double), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "psm_coupled_step force/torque read-back");
+  for (int b = 0; b < nb; ++b) {
+    r = psm_rigid_advance(&states[b], ft_host + 6 * b, 1.0);
+    if (r) return r;
+  }
+  return PSM_OK;
+}
+
 int body_force_torque(psm_field *f, int nb, double *ft, void *stream) {
   if (!f || !ft) return set_error("null argument"), PSM_EINVAL;
   if (!f->cfg.psm) return set_error("body_force_torque on a plain-LBM field"), PSM_EINVAL;

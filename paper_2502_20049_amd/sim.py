@@ -190,6 +190,18 @@ class Field:
         if ft is not None and self.nb:
             self.force_torque(out=ft)
 
+    def coupled_step(self, t: int, states, ft_host=None):
+        """One two-way coupled step (psm_coupled_step): ``states`` is a ctypes
+        array of capi.psm_rigid (one per body), advanced in place; returns the
+        step's F/T as a (n_bodies, 6) numpy array."""
+        import numpy as np
+
+        ft = np.zeros((self.nb, 6)) if ft_host is None else ft_host
+        check(lib.psm_coupled_step(self.handle, states, self._geom_ptrs, self.nb, int(t),
+                                   C.c_void_p(self.ft.data_ptr()), ft.ctypes.data_as(C.POINTER(C.c_double)),
+                                   _stream()), "psm_coupled_step")
+        return ft
+
     def set_obstacle(self, solid):
         """Static no-slip obstacle of a plain-LBM field: ``solid`` is an (N,)
         uint8 device tensor (1 = obstacle cell), None removes it.  Returns the
@@ -233,6 +245,18 @@ class Field:
         if getattr(self, "handle", None) and self.handle.value:
             lib.pdf_field_destroy(self.handle)
             self.handle = C.c_void_p()
+
+
+def rigid_states(rigids):
+    """ctypes array of capi.psm_rigid at rest from dicts (m, I, F_ext, X0)."""
+    arr = (capi.psm_rigid * len(rigids))()
+    for s, r in zip(arr, rigids):
+        s.m = r["m"]
+        s.I = (C.c_double * 3)(*r["I"])
+        s.F_ext = (C.c_double * 3)(*r["F_ext"])
+        s.X = (C.c_double * 3)(*r["X0"])
+        s.R = (C.c_double * 9)(1, 0, 0, 0, 1, 0, 0, 0, 1)
+    return arr
 
 
 def voxelize_obstacle(wl, t: int = 0, device="cuda"):

@@ -379,6 +379,24 @@ def workload_sphere32(storage="f64"):
                     ("periodic",) * 6, (0, 0, 0), 1, 0, 1, 200, [sph])
 
 
+def workload_settling_sphere(nx=135, ny=135, nz=216, r=10.0, storage="f32", steps=4000, tau=0.575,
+                             rho_s=1.16, g=7.4e-4, s=2, z0=None):
+    """A sphere released from rest near the top of a closed box (no-slip walls on
+    every face; the settling-sphere setup of section IV, 135 x 135 x 216 cells),
+    SRT (TRT with Lambda = (tau - 1/2)^2), SC2.  Returns (workload, rigid) with
+    rigid = dict(m, I, F_ext, X0): mass rho_s V, moments 2/5 m r^2, gravity
+    minus buoyancy (rho_s - 1) V g along -z (fluid density 1)."""
+    z0 = nz - 2.0 * r if z0 is None else z0
+    X0 = (nx / 2.0, ny / 2.0, z0)
+    sph = Body(Shape("ellipsoid", (r, r, r)), Motion(x0=X0), s=s)
+    wl = Workload(f"settling_sphere_{nx}x{ny}x{nz}_r{r:g}", nx, ny, nz, 19, storage, tau, (tau - 0.5) ** 2,
+                  (0.0, 0.0, 0.0), ("wall",) * 6, (0.0, 0.0, 0.0), 2, 0, 1, steps, [sph])
+    vol = 4.0 / 3.0 * math.pi * r ** 3
+    m = rho_s * vol
+    rigid = dict(m=m, I=(0.4 * m * r * r,) * 3, F_ext=(0.0, 0.0, -(rho_s - 1.0) * vol * g), X0=X0)
+    return wl, rigid
+
+
 def workload_ellipsoid_channel(n=256, storage="f32", steps=2000, scale=1.0, s=3):
     """n^3 channel (inlet -x u=0.05, outlet +x, walls y,z), rotating ellipsoid about z."""
     a, b, c = 40.0 * scale, 20.0 * scale, 10.0 * scale
