@@ -247,6 +247,37 @@ def node_benchmark(steps=600):
     return out
 
 
+def settling_sphere(steps=2000):
+    """Two-way coupling on the section IV setup: a sphere (d = 20 cells, density
+    ratio 1.16) released from rest near the top of a closed 135 x 135 x 216 box,
+    SRT (tau = 0.575), SC2, s = 2; per step psm_coupled_step (map, stream-collide,
+    F/T read back, host integrator)."""
+    import torch
+
+    import psm_inputs as pi
+    from paper_2502_20049_amd import sim
+
+    wl, rg = pi.workload_settling_sphere(steps=steps)
+    f = sim.Field(wl)
+    states = sim.rigid_states([rg])
+    vz = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for t in range(steps):
+        ft = f.coupled_step(t, states)
+        vz.append(states[0].V[2])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    nu = (wl.tau - 0.5) / 3.0
+    vmax = min(vz)
+    k = vz.index(vmax)
+    return {"case": f"{wl.name}, SRT tau {wl.tau}, SC2, s=2, {steps} coupled steps",
+            "mlups": round(wl.n_cells * steps / wall / 1e6, 1), "ms_per_step": round(wall / steps * 1e3, 4),
+            "max_settling_velocity": round(vmax, 6), "at_step": k, "Re_at_max": round(abs(vmax) * 20.0 / nu, 2),
+            "z_final": round(states[0].X[2], 3),
+            "net_force_over_weight_last_step": round((ft[0, 2] + rg["F_ext"][2]) / abs(rg["F_ext"][2]), 5)}
+
+
 def adjoint_rate(steps=800, window=200):
     """Torque-gradient sweep on the 128^3 4-blade rotor: J = mean axial torque
     over the last 200 of 800 steps; forward (with checkpoints) and backward
@@ -307,6 +338,8 @@ def main():
     ap.add_argument("--node-only", action="store_true",
                     help="run only the paper's node-level comparison (LBM, LBM + no-slip obstacle, PSM static, "
                          "PSM rotating)")
+    ap.add_argument("--settling-only", action="store_true",
+                    help="run only the two-way coupled settling sphere (section IV setup)")
     ap.add_argument("--copy-only", action="store_true",
                     help="run only the device copy probe (1 GiB read + 1 GiB written per launch): the "
                          "calibration for rocprofv3 FETCH_SIZE / WRITE_SIZE")
@@ -326,6 +359,9 @@ def main():
         return
     if args.node_only:
         print(json.dumps(node_benchmark()), flush=True)
+        return
+    if args.settling_only:
+        print(json.dumps(settling_sphere()), flush=True)
         return
     if args.copy_only:
         bw = copy_probe(nbytes=1 << 30, reps=5)
@@ -393,6 +429,7 @@ def main():
         extras["supersampling_sweep"] = s_sweep()
         extras["node_benchmark"] = node_benchmark()
         extras["adjoint_rotor_128"] = adjoint_rate()
+        extras["settling_sphere"] = settling_sphere()
         line["extras"] = extras
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(wl)

@@ -245,7 +245,13 @@ int psm_set_fraction_offset(psm_field *f, const float *dB_dev);
  *   I      principal moments of inertia (body frame axes, about X)
  *   F_ext  constant external force on the body (gravity minus buoyancy), lab
  *   X, V   reference point (body-frame origin) and its velocity, lab
- *   R      orientation (body -> lab, row-major), W angular velocity, lab */
+ *   R      orientation (body -> lab, row-major), W angular velocity, lab
+ *   ft_prev   hydrodynamic F/T of the previous step (zero at rest)
+ *   average   1: advance with the mean of this step's and the previous
+ *             step's hydrodynamic F/T (keeps the explicit coupling of bodies
+ *             not much denser than the fluid stable: the solid collision
+ *             hands the body the change of its inner fluid's momentum one
+ *             step late, up to 1/tau times over with SC2); 0: this step's */
 typedef struct psm_rigid {
   double m;
   double I[3];
@@ -254,6 +260,9 @@ typedef struct psm_rigid {
   double V[3];
   double R[9];
   double W[3];
+  double ft_prev[6];
+  int32_t average;
+  int32_t reserved;
 } psm_rigid;
 
 /* Pose and velocity of a rigid-body state, for the mapping and the solid
@@ -261,7 +270,8 @@ typedef struct psm_rigid {
 int psm_rigid_body(const psm_rigid *s, psm_body *out);
 
 /* Advance a rigid-body state by dt with the hydrodynamic force / torque
- * ft = (F, T) of the step just taken (force on the body, torque about X):
+ * ft = (F, T) of the step just taken (force on the body, torque about X;
+ * with `average`, (ft + ft_prev) / 2 in its place; ft_prev = ft after):
  * semi-implicit Euler,
  *   V += dt (F + F_ext) / m,  X += dt V,
  *   W += dt I_lab^-1 (T - W x (I_lab W)),  I_lab = R diag(I) R^T,

@@ -199,8 +199,12 @@ def rigid_advance(st: dict, ft, dt: float = 1.0) -> None:
     ft = (F, T) of the step (force on the body, torque about X) and the
     constant external force F_ext: semi-implicit Euler, V then X, W then R
     (Newton and Euler's equations written in the lab frame with
-    I_lab = R diag(I) R^T, the orientation rotated by dt|W| about W)."""
-    ft = np.asarray(ft, dtype=np.float64)
+    I_lab = R diag(I) R^T, the orientation rotated by dt|W| about W).  With
+    st["average"], the mean of this step's and the previous step's
+    hydrodynamic F/T drives the step."""
+    ft_step = np.asarray(ft, dtype=np.float64)
+    ft = 0.5 * (ft_step + st["ft_prev"]) if st["average"] else ft_step
+    st["ft_prev"] = ft_step.copy()
     st["V"] = st["V"] + dt * (ft[:3] + np.asarray(st["F_ext"])) / st["m"]
     st["X"] = st["X"] + dt * st["V"]
     R = st["R"]
@@ -221,10 +225,13 @@ def rigid_pose(st: dict) -> Pose:
     return p
 
 
-def rigid_state(rigid: dict) -> dict:
-    """Rest state of a rigid body: dict(m, I, F_ext, X0) -> state dict."""
+def rigid_state(rigid: dict, average: bool = True) -> dict:
+    """Rest state of a rigid body: dict(m, I, F_ext, X0) -> state dict
+    (average: drive each step with the mean hydrodynamic F/T of the last two
+    steps)."""
     return {"m": float(rigid["m"]), "I": tuple(rigid["I"]), "F_ext": tuple(rigid["F_ext"]),
-            "X": np.asarray(rigid["X0"], dtype=np.float64), "V": np.zeros(3), "R": np.eye(3), "W": np.zeros(3)}
+            "X": np.asarray(rigid["X0"], dtype=np.float64), "V": np.zeros(3), "R": np.eye(3), "W": np.zeros(3),
+            "ft_prev": np.zeros(6), "average": bool(average)}
 
 
 def coupled_run(wl, states, steps: int, f0: np.ndarray | None = None):

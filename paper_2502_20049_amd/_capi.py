@@ -33,7 +33,8 @@ EXPORTS = [
 
 class psm_rigid(C.Structure):
     _fields_ = [("m", C.c_double), ("I", C.c_double * 3), ("F_ext", C.c_double * 3), ("X", C.c_double * 3),
-                ("V", C.c_double * 3), ("R", C.c_double * 9), ("W", C.c_double * 3)]
+                ("V", C.c_double * 3), ("R", C.c_double * 9), ("W", C.c_double * 3), ("ft_prev", C.c_double * 6),
+                ("average", C.c_int32), ("reserved", C.c_int32)]
 
 
 class psm_config(C.Structure):

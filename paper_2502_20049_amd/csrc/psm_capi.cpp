@@ -709,10 +709,15 @@ int psm_rigid_body(const psm_rigid *s, psm_body *out) {
   return PSM_OK;
 }
 
-int psm_rigid_advance(psm_rigid *s, const double ft[6], double dt) {
-  if (!s || !ft) return set_error("psm_rigid_advance: null argument"), PSM_EINVAL;
+int psm_rigid_advance(psm_rigid *s, const double ft_step[6], double dt) {
+  if (!s || !ft_step) return set_error("psm_rigid_advance: null argument"), PSM_EINVAL;
   if (!(s->m > 0.0) || !(s->I[0] > 0.0) || !(s->I[1] > 0.0) || !(s->I[2] > 0.0) || !isfinite(dt))
     return set_error("psm_rigid_advance: mass and moments of inertia must be positive, dt finite"), PSM_EINVAL;
+  double ft[6];
+  for (int i = 0; i < 6; ++i) {
+    ft[i] = s->average ? 0.5 * (ft_step[i] + s->ft_prev[i]) : ft_step[i];
+    s->ft_prev[i] = ft_step[i];
+  }
   // translation
   for (int d = 0; d < 3; ++d) {
     s->V[d] += dt * ((ft[d] + s->F_ext[d]) / s->m);

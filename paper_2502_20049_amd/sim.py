@@ -247,10 +247,12 @@ class Field:
             self.handle = C.c_void_p()
 
 
-def rigid_states(rigids):
-    """ctypes array of capi.psm_rigid at rest from dicts (m, I, F_ext, X0)."""
+def rigid_states(rigids, average=True):
+    """ctypes array of capi.psm_rigid at rest from dicts (m, I, F_ext, X0);
+    average: advance with the mean hydrodynamic F/T of the last two steps."""
     arr = (capi.psm_rigid * len(rigids))()
     for s, r in zip(arr, rigids):
+        s.average = 1 if average else 0
         s.m = r["m"]
         s.I = (C.c_double * 3)(*r["I"])
         s.F_ext = (C.c_double * 3)(*r["F_ext"])

@@ -206,8 +206,9 @@ def test_rigid_advance_matches_oracle(capi, orc):
     import psm_inputs as pi
 
     rg = dict(m=7.0, I=(2.0, 3.5, 5.0), F_ext=(0.0, 0.0, -0.3), X0=(4.0, 5.0, 6.0))
-    st = orc.rigid_state(rg)
+    st = orc.rigid_state(rg, average=True)
     s = capi.psm_rigid()
+    s.average = 1
     s.m, s.I, s.F_ext, s.X = rg["m"], (C.c_double * 3)(*rg["I"]), (C.c_double * 3)(*rg["F_ext"]), \
         (C.c_double * 3)(*rg["X0"])
     s.R = (C.c_double * 9)(1, 0, 0, 0, 1, 0, 0, 0, 1)

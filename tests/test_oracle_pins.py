@@ -560,8 +560,36 @@ def test_obstacle_empty_mask_is_plain_step(orc):
 
 
 # --- two-way coupling: rigid-body integrator (section IV's settling sphere) ---
-def _rigid(orc, m=3.0, I=(2.0, 2.0, 2.0), F_ext=(0.0, 0.0, 0.0), X0=(1.0, 2.0, 3.0)):
-    return orc.rigid_state(dict(m=m, I=I, F_ext=F_ext, X0=X0))
+def _rigid(orc, m=3.0, I=(2.0, 2.0, 2.0), F_ext=(0.0, 0.0, 0.0), X0=(1.0, 2.0, 3.0), average=False):
+    return orc.rigid_state(dict(m=m, I=I, F_ext=F_ext, X0=X0), average=average)
+
+
+def test_rigid_force_averaging_closed_form(orc):
+    """With two-step averaging from rest, a constant hydrodynamic force enters
+    the first step at half strength: V(t) = (F_ext t + F_h (t - 1/2)) / m."""
+    F_ext = np.array([0.0, 0.0, -0.2])
+    Fh = np.array([0.05, 0.0, 0.12])
+    st = _rigid(orc, m=2.0, F_ext=tuple(F_ext), average=True)
+    for _ in range(9):
+        orc.rigid_advance(st, np.concatenate([Fh, np.zeros(3)]))
+    assert np.allclose(st["V"], (F_ext * 9 + Fh * 8.5) / 2.0, rtol=0, atol=1e-15)
+
+
+def test_coupled_averaging_keeps_light_sphere_stable(orc):
+    """SC2 at tau = 0.575 hands the body 1/tau times its inner fluid's momentum
+    change one step late: for a density ratio 1.16 the explicit update
+    oscillates with growing amplitude (ratio rho_f V / (m tau) ~ 1.5 > 1);
+    averaging the last two steps' force (roots of z^2 + k/2 z + k/2, |z|^2 =
+    k/2 < 1) keeps it settling smoothly."""
+    wl, rg = pi.workload_settling_sphere(20, 20, 30, r=3.5, storage="f64", tau=0.575, rho_s=1.16, g=7.4e-4)
+    runs = {}
+    for avg in (False, True):
+        st = [orc.rigid_state(rg, average=avg)]
+        _, tr = orc.coupled_run(wl, st, 40)
+        runs[avg] = np.array([r[0]["V"][2] for r in tr])
+    assert np.abs(runs[False]).max() > 1e-2  # the plain explicit update runs away
+    v = runs[True]
+    assert v[-1] < 0 and np.abs(v).max() < 2e-3 and np.all(np.diff(v[5:]) < 2e-5)
 
 
 def test_rigid_constant_force_closed_form(orc):
@@ -622,7 +650,7 @@ def test_coupled_momentum_balance(orc):
     fluid and enters the body)."""
     wl, rg = pi.workload_settling_sphere(16, 16, 20, r=3.0, storage="f64", tau=0.8, rho_s=1.4, g=5e-4, z0=10.0)
     wl.bc = ("periodic",) * 6
-    st = [orc.rigid_state(rg)]
+    st = [orc.rigid_state(rg, average=False)]  # the balance holds step by step without averaging
     st[0]["V"] = np.array([0.002, -0.001, 0.0])
     st[0]["W"] = np.array([0.0, 0.003, 0.001])
     c, w, _ = orc.lattice(19)
