@@ -247,7 +247,7 @@ def node_benchmark(steps=600):
     return out
 
 
-def settling_sphere(steps=2000):
+def settling_sphere(steps=4000):
     """Two-way coupling on the section IV setup: a sphere (d = 20 cells, density
     ratio 1.16) released from rest near the top of a closed 135 x 135 x 216 box,
     SRT (tau = 0.575), SC2, s = 2; per step psm_coupled_step (map, stream-collide,
@@ -268,11 +268,20 @@ def settling_sphere(steps=2000):
         vz.append(states[0].V[2])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    # the same lattice and sphere with prescribed motion (no read-back): the
+    # cost of the per-step host round trip
+    del f
+    torch.cuda.empty_cache()
+    fp = sim.Field(wl)
+    wall_p, _ = time_field(fp, 500, 20)
+    del fp
+    torch.cuda.empty_cache()
     nu = (wl.tau - 0.5) / 3.0
     vmax = min(vz)
     k = vz.index(vmax)
     return {"case": f"{wl.name}, SRT tau {wl.tau}, SC2, s=2, {steps} coupled steps",
             "mlups": round(wl.n_cells * steps / wall / 1e6, 1), "ms_per_step": round(wall / steps * 1e3, 4),
+            "prescribed_motion_ms_per_step": round(wall_p / 500 * 1e3, 4),
             "max_settling_velocity": round(vmax, 6), "at_step": k, "Re_at_max": round(abs(vmax) * 20.0 / nu, 2),
             "z_final": round(states[0].X[2], 3),
             "net_force_over_weight_last_step": round((ft[0, 2] + rg["F_ext"][2]) / abs(rg["F_ext"][2]), 5)}

@@ -194,13 +194,14 @@ class Field:
         """One two-way coupled step (psm_coupled_step): ``states`` is a ctypes
         array of capi.psm_rigid (one per body), advanced in place; returns the
         step's F/T as a (n_bodies, 6) numpy array."""
-        import numpy as np
-
-        ft = np.zeros((self.nb, 6)) if ft_host is None else ft_host
+        if ft_host is None:
+            if getattr(self, "_ft_pinned", None) is None:
+                self._ft_pinned = torch.zeros((max(1, self.nb), 6), dtype=torch.float64, pin_memory=True)
+            ft_host = self._ft_pinned.numpy()
         check(lib.psm_coupled_step(self.handle, states, self._geom_ptrs, self.nb, int(t),
-                                   C.c_void_p(self.ft.data_ptr()), ft.ctypes.data_as(C.POINTER(C.c_double)),
+                                   C.c_void_p(self.ft.data_ptr()), ft_host.ctypes.data_as(C.POINTER(C.c_double)),
                                    _stream()), "psm_coupled_step")
-        return ft
+        return ft_host[: self.nb].copy()
 
     def set_obstacle(self, solid):
         """Static no-slip obstacle of a plain-LBM field: ``solid`` is an (N,)
