@@ -38,7 +38,8 @@ def build(force: bool = True) -> str:
 class Config(C.Structure):
     _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int), ("q", C.c_int),
                 ("tau", C.c_double), ("magic", C.c_double), ("force", C.c_double * 3),
-                ("bc", C.c_int * 6), ("u_in", C.c_double * 3), ("sc", C.c_int), ("psm", C.c_int)]
+                ("bc", C.c_int * 6), ("u_in", C.c_double * 3), ("sc", C.c_int), ("psm", C.c_int),
+                ("collision", C.c_int)]
 
 
 class Pose(C.Structure):
@@ -122,7 +123,7 @@ def make_config(wl=None, **kw) -> Config:
     d = {}
     if wl is not None:
         d = dict(nx=wl.nx, ny=wl.ny, nz=wl.nz, q=wl.q, tau=wl.tau, magic=wl.magic, force=wl.force,
-                 bc=wl.bc, u_in=wl.u_in, sc=wl.sc, psm=1)
+                 bc=wl.bc, u_in=wl.u_in, sc=wl.sc, psm=1, collision=getattr(wl, "collision", "trt"))
     d.update(kw)
     cfg = Config()
     cfg.nx, cfg.ny, cfg.nz, cfg.q = d["nx"], d["ny"], d["nz"], d["q"]
@@ -132,6 +133,8 @@ def make_config(wl=None, **kw) -> Config:
     cfg.u_in = (C.c_double * 3)(*d.get("u_in", (0, 0, 0)))
     cfg.sc = d.get("sc", 1)
     cfg.psm = d.get("psm", 1)
+    coll = d.get("collision", "trt")
+    cfg.collision = {"trt": 0, "cumulant": 1}[coll] if isinstance(coll, str) else int(coll)
     return cfg
 
 

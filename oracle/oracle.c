@@ -116,6 +116,153 @@ void or_pose_at(const double axis[3], double theta0, double omega, const double 
  * with the B_k scaled by 1/sum B when the sum exceeds one.  The force on the
  * body in slot k is dF_k = -B_k sum_i c_i Omega^S_{k,i} (eq. (10), body side).
  * ------------------------------------------------------------------------- */
+/* ---- cumulant fluid collision (section II.B lists it; section V runs with it) ----
+ * D3Q27 without body force.  The shear rate is omega = 1/tau, every other rate
+ * is one (the trace of the second-order cumulants and all cumulants of orders
+ * 3 to 6).  Steps, for one cell:
+ *   1. u = j / rho; central moments M_abc = sum_i (c_ix-u_x)^a (c_iy-u_y)^b
+ *      (c_iz-u_z)^c f_i / rho for a, b, c in {0, 1, 2};
+ *   2. cumulants K_abc of that normalised distribution from the moments: a
+ *      multi-index is a list of n = a+b+c axis labels, and
+ *      K = sum over set partitions P of the list of (-1)^(|P|-1) (|P|-1)!
+ *          times the product over the blocks of the blocks' moments;
+ *   3. relaxation: K_110, K_101, K_011 and the deviators K_200 - K_020,
+ *      K_200 - K_002 are multiplied by (1 - omega), the trace K_200 + K_020 +
+ *      K_002 is set to 3 c_s^2 = 1, every cumulant of order >= 3 to zero;
+ *   4. moments from cumulants: M = sum over set partitions of the product of
+ *      the blocks' cumulants;
+ *   5. the 27 populations solve sum_i (c_i - u)^abc f_i = rho M_abc. */
+static int midx(int a, int b, int c) { return 9 * a + 3 * b + c; }
+
+/* sum over the set partitions of the n labelled positions (n <= 6) of
+ * weight(#blocks) * prod over blocks of T[multi-index of the block] */
+static double partition_sum(int n, const int *lab, const double *T, int signed_weights) {
+  int rgs[6] = {0, 0, 0, 0, 0, 0};
+  double total = 0.0;
+  for (;;) {
+    int nb = 0;
+    for (int i = 0; i < n; ++i)
+      if (rgs[i] + 1 > nb) nb = rgs[i] + 1;
+    double prod = 1.0;
+    for (int b = 0; b < nb; ++b) {
+      int cnt[3] = {0, 0, 0};
+      for (int i = 0; i < n; ++i)
+        if (rgs[i] == b) cnt[lab[i]]++;
+      prod *= T[midx(cnt[0], cnt[1], cnt[2])];
+    }
+    double wgt = 1.0;
+    if (signed_weights) {
+      for (int k = 2; k < nb; ++k) wgt *= k; /* (nb - 1)! */
+      if ((nb - 1) & 1) wgt = -wgt;
+    }
+    total += wgt * prod;
+    /* next restricted growth string: rgs[i] <= 1 + max(rgs[0..i-1]) */
+    int i = n - 1;
+    for (; i > 0; --i) {
+      int mx = 0;
+      for (int k = 0; k < i; ++k)
+        if (rgs[k] > mx) mx = rgs[k];
+      if (rgs[i] <= mx) break;
+    }
+    if (i <= 0) break;
+    rgs[i]++;
+    for (int k = i + 1; k < n; ++k) rgs[k] = 0;
+  }
+  return total;
+}
+
+static int labels_of(int a, int b, int c, int *lab) {
+  int n = 0;
+  for (int k = 0; k < a; ++k) lab[n++] = 0;
+  for (int k = 0; k < b; ++k) lab[n++] = 1;
+  for (int k = 0; k < c; ++k) lab[n++] = 2;
+  return n;
+}
+
+static int solve_dense(int n, double *A, double *x) { /* A[n][n] x = b (x holds b), partial pivoting */
+  for (int k = 0; k < n; ++k) {
+    int p = k;
+    for (int r = k + 1; r < n; ++r)
+      if (fabs(A[r * n + k]) > fabs(A[p * n + k])) p = r;
+    if (A[p * n + k] == 0.0) return -1;
+    if (p != k) {
+      for (int cc = 0; cc < n; ++cc) {
+        double t = A[k * n + cc];
+        A[k * n + cc] = A[p * n + cc];
+        A[p * n + cc] = t;
+      }
+      double t = x[k];
+      x[k] = x[p];
+      x[p] = t;
+    }
+    for (int r = k + 1; r < n; ++r) {
+      double m = A[r * n + k] / A[k * n + k];
+      for (int cc = k; cc < n; ++cc) A[r * n + cc] -= m * A[k * n + cc];
+      x[r] -= m * x[k];
+    }
+  }
+  for (int k = n - 1; k >= 0; --k) {
+    double s = x[k];
+    for (int cc = k + 1; cc < n; ++cc) s -= A[k * n + cc] * x[cc];
+    x[k] = s / A[k * n + k];
+  }
+  return 0;
+}
+
+static void cumulant_collide(const or_config *cfg, const lat_t *L, const double *fin, double *fout) {
+  double rho = 0.0, j[3] = {0.0, 0.0, 0.0};
+  for (int i = 0; i < 27; ++i) {
+    rho += fin[i];
+    for (int a = 0; a < 3; ++a) j[a] += L->c[3 * i + a] * fin[i];
+  }
+  const double u[3] = {j[0] / rho, j[1] / rho, j[2] / rho};
+  double M[27], K[27], Kp[27], Mp[27];
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b)
+      for (int c = 0; c < 3; ++c) {
+        double s = 0.0;
+        for (int i = 0; i < 27; ++i)
+          s += pow(L->c[3 * i] - u[0], a) * pow(L->c[3 * i + 1] - u[1], b) * pow(L->c[3 * i + 2] - u[2], c) * fin[i];
+        M[midx(a, b, c)] = s / rho;
+      }
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b)
+      for (int c = 0; c < 3; ++c) {
+        int lab[6];
+        const int n = labels_of(a, b, c, lab);
+        K[midx(a, b, c)] = n == 0 ? 0.0 : partition_sum(n, lab, M, 1);
+      }
+  const double om = 1.0 / cfg->tau;
+  for (int k = 0; k < 27; ++k) Kp[k] = 0.0;
+  Kp[midx(1, 1, 0)] = (1.0 - om) * K[midx(1, 1, 0)];
+  Kp[midx(1, 0, 1)] = (1.0 - om) * K[midx(1, 0, 1)];
+  Kp[midx(0, 1, 1)] = (1.0 - om) * K[midx(0, 1, 1)];
+  const double dxy = (1.0 - om) * (K[midx(2, 0, 0)] - K[midx(0, 2, 0)]);
+  const double dxz = (1.0 - om) * (K[midx(2, 0, 0)] - K[midx(0, 0, 2)]);
+  const double tr = 1.0; /* 3 c_s^2 */
+  Kp[midx(2, 0, 0)] = (tr + dxy + dxz) / 3.0;
+  Kp[midx(0, 2, 0)] = Kp[midx(2, 0, 0)] - dxy;
+  Kp[midx(0, 0, 2)] = Kp[midx(2, 0, 0)] - dxz;
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b)
+      for (int c = 0; c < 3; ++c) {
+        int lab[6];
+        const int n = labels_of(a, b, c, lab);
+        Mp[midx(a, b, c)] = n == 0 ? 1.0 : partition_sum(n, lab, Kp, 0);
+      }
+  double A[27 * 27], x[27];
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b)
+      for (int c = 0; c < 3; ++c) {
+        const int r = midx(a, b, c);
+        for (int i = 0; i < 27; ++i)
+          A[r * 27 + i] = pow(L->c[3 * i] - u[0], a) * pow(L->c[3 * i + 1] - u[1], b) * pow(L->c[3 * i + 2] - u[2], c);
+        x[r] = rho * Mp[r];
+      }
+  solve_dense(27, A, x);
+  for (int i = 0; i < 27; ++i) fout[i] = x[i];
+}
+
 static void collide_lat(const or_config *cfg, const lat_t *L, const double *fin, int nslot,
                         const double *Bin, const double *us, double *fout, double *dF) {
   const int q = L->q;
@@ -140,12 +287,18 @@ static void collide_lat(const or_config *cfg, const lat_t *L, const double *fin,
   }
   double le = 1.0 / cfg->tau;
   double lo = 1.0 / (0.5 + cfg->magic / (cfg->tau - 0.5));
-  for (int i = 0; i < q; ++i) {
-    int k = L->opp[i];
-    double fp = 0.5 * (fin[i] + fin[k]), fm = 0.5 * (fin[i] - fin[k]);
-    double ep = 0.5 * (feq[i] + feq[k]), em = 0.5 * (feq[i] - feq[k]);
-    double sp = 0.5 * (S[i] + S[k]), sm = 0.5 * (S[i] - S[k]);
-    OmF[i] = -le * (fp - ep) - lo * (fm - em) + (1.0 - 0.5 * le) * sp + (1.0 - 0.5 * lo) * sm;
+  if (cfg->collision == OR_CUMULANT) {
+    double fc[OR_MAXQ];
+    cumulant_collide(cfg, L, fin, fc);
+    for (int i = 0; i < q; ++i) OmF[i] = fc[i] - fin[i];
+  } else {
+    for (int i = 0; i < q; ++i) {
+      int k = L->opp[i];
+      double fp = 0.5 * (fin[i] + fin[k]), fm = 0.5 * (fin[i] - fin[k]);
+      double ep = 0.5 * (feq[i] + feq[k]), em = 0.5 * (feq[i] - feq[k]);
+      double sp = 0.5 * (S[i] + S[k]), sm = 0.5 * (S[i] - S[k]);
+      OmF[i] = -le * (fp - ep) - lo * (fm - em) + (1.0 - 0.5 * le) * sp + (1.0 - 0.5 * lo) * sm;
+    }
   }
   if (!cfg->psm || nslot == 0) {
     for (int i = 0; i < q; ++i) fout[i] = fin[i] + OmF[i];
@@ -182,6 +335,9 @@ int or_collide_cell(const or_config *cfg, const double *fin, int nslot, const do
                     const double *us, double *fout, double *dF) {
   lat_t L;
   if (lat_get(cfg->q, &L) != 0 || nslot < 0 || nslot > 2) return -1;
+  if (cfg->collision == OR_CUMULANT && (cfg->q != 27 || cfg->force[0] != 0.0 || cfg->force[1] != 0.0 ||
+                                        cfg->force[2] != 0.0))
+    return -5;
   collide_lat(cfg, &L, fin, nslot, B, us, fout, dF);
   return 0;
 }
@@ -223,6 +379,9 @@ static int step_impl(const or_config *cfg, double *f, double *fpost, int nb, con
                      const or_pose *poses, double *ft, const unsigned char *solid) {
   lat_t L;
   if (lat_get(cfg->q, &L) != 0) return -1;
+  if (cfg->collision == OR_CUMULANT &&
+      (cfg->q != 27 || cfg->force[0] != 0.0 || cfg->force[1] != 0.0 || cfg->force[2] != 0.0))
+    return -5;
   for (int a = 0; a < 3; ++a)
     if ((cfg->bc[2 * a] == OR_PERIODIC) != (cfg->bc[2 * a + 1] == OR_PERIODIC)) return -2;
   const int q = L.q, nx = cfg->nx, ny = cfg->ny, nz = cfg->nz;

@@ -20,6 +20,9 @@
  *     section III (supersampled body-frame lookup of every sub-sample)
  *   - generalised winding number voxelisation, divergence-theorem volume
  *   - FP64 discrete adjoint of one step (explicit per-cell Jacobian)
+ *   - cumulant fluid collision (D3Q27; shear rate 1/tau, every other rate
+ *     one), through set-partition moment / cumulant relations and a linear
+ *     solve for the populations
  *   - plain LBM with halfway bounce-back on static obstacle cells (the LBM
  *     variant of the node-level benchmark, section V)
  *
@@ -46,7 +49,11 @@ typedef struct {
   double u_in[3]; /* inlet velocity (moving-wall bounce-back) */
   int sc;         /* 1, 2 or 3 */
   int psm;        /* 0: plain LBM (solid fraction ignored), 1: PSM */
+  int collision;  /* OR_TRT or OR_CUMULANT (D3Q27, no body force) */
 } or_config;
+
+/* fluid collision operators */
+enum { OR_TRT = 0, OR_CUMULANT = 1 };
 
 /* Pose of a body at one step: lab = R * body + X; solid velocity
  * u_s(x) = V + W x (x - X). R row-major. */

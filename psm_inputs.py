@@ -362,6 +362,7 @@ class Workload:
     slots: int = 1
     steps: int = 100
     bodies: list = field(default_factory=list)
+    collision: str = "trt"    # "trt" or "cumulant" (D3Q27, no body force)
 
     @property
     def n_cells(self):

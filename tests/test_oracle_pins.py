@@ -662,3 +662,93 @@ def test_coupled_momentum_balance(orc):
         f, _ = orc.coupled_run(wl, st, 1, f0=f)
         dP = P(f) - p0 + rg["m"] * (st[0]["V"] - v0)
         assert np.allclose(dP, Fe, rtol=0, atol=1e-12)
+
+
+# --- cumulant collision (D3Q27; section II.B lists it, section V runs with it) ---
+def _cum_cfg(orc, tau=0.7, **kw):
+    return _cfg(orc, 27, tau=tau, psm=0, collision="cumulant", **kw)
+
+
+def _cum_collide(orc, cfg, f):
+    fo, _ = orc.collide_cell(cfg, f)
+    return fo
+
+
+def test_cumulant_rate_one_gives_product_equilibrium(orc):
+    """With every rate one the post-collision state has all cumulants of
+    order >= 3 zero and the second-order ones at c_s^2 delta: it is the
+    product of the three 1-D distributions on {-1, 0, 1} with mean u_a and
+    variance 1/3, rho prod_a phi(c_a; u_a), phi(+-1) = (1/3 + u^2 +- u)/2,
+    phi(0) = 2/3 - u^2."""
+    cfg = _cum_cfg(orc, tau=1.0)
+    c, w, _ = orc.lattice(27)
+    for seed in range(4):
+        f = _rand_f(27, w, 60 + seed, amp=3.0)
+        rho = f.sum()
+        u = (f @ c) / rho
+        def phi(k, v):
+            return {-1: (1 / 3 + v * v - v) / 2, 0: 2 / 3 - v * v, 1: (1 / 3 + v * v + v) / 2}[k]
+        expect = np.array([rho * phi(cc[0], u[0]) * phi(cc[1], u[1]) * phi(cc[2], u[2]) for cc in c])
+        got = _cum_collide(orc, cfg, f)
+        assert np.abs(got - expect).max() < 1e-15
+
+
+def test_cumulant_conserves_mass_and_momentum(orc):
+    cfg = _cum_cfg(orc, tau=0.63)
+    c, w, _ = orc.lattice(27)
+    for seed in range(4):
+        f = _rand_f(27, w, 70 + seed, amp=3.0)
+        g = _cum_collide(orc, cfg, f)
+        assert abs(g.sum() - f.sum()) < 1e-15
+        assert np.abs(g @ c - f @ c).max() < 1e-15
+        assert np.abs(g - f).max() > 1e-4  # it does relax
+
+
+@pytest.mark.parametrize("perm,sign", [((1, 0, 2), (1, 1, 1)), ((2, 0, 1), (1, 1, 1)), ((0, 1, 2), (-1, 1, 1)),
+                                       ((0, 2, 1), (1, -1, -1))])
+def test_cumulant_commutes_with_lattice_symmetries(orc, perm, sign):
+    """Collision commutes with the cube's symmetries (axis permutations and
+    reflections) of the D3Q27 velocity set."""
+    cfg = _cum_cfg(orc, tau=0.71)
+    c, w, _ = orc.lattice(27)
+    lut = {tuple(v): k for k, v in enumerate(c)}
+    img = np.array([lut[tuple(np.array(sign) * v[list(perm)])] for v in c])  # velocity k -> its image
+    f = _rand_f(27, w, 81, amp=3.0)
+    g = np.empty_like(f)
+    g[img] = f
+    a = _cum_collide(orc, cfg, f)
+    b = _cum_collide(orc, cfg, g)
+    assert np.abs(b[img] - a).max() < 1e-15
+
+
+def test_cumulant_shear_wave_viscosity(orc):
+    """A decaying shear wave u_x(y) = U sin(k y) (periodic, D3Q27): the
+    amplitude decays at the rate nu k^2 with nu = c_s^2 (tau - 1/2) (the shear
+    rate 1/tau sets the viscosity); 1% on the rate at k = 2 pi / 32."""
+    L, tau, U = 32, 0.8, 1e-3
+    cfg = _cum_cfg(orc, tau=tau, nx=1, ny=L, nz=1)
+    c, w, _ = orc.lattice(27)
+    y = np.arange(L) + 0.0
+    ux = U * np.sin(2 * np.pi * y / L)
+    f = np.stack([orc.feq(27, 1.0, (ux[n], 0.0, 0.0)) for n in range(L)], axis=1)
+    amps = {}
+    for t in range(1, 301):
+        orc.step(cfg, f, None, [])
+        if t in (100, 300):
+            _, u = orc.macro(cfg, f)
+            amps[t] = 2 / L * np.sum(u[:, 0] * np.sin(2 * np.pi * y / L))
+    rate = np.log(amps[100] / amps[300]) / 200
+    nu = (tau - 0.5) / 3
+    k = 2 * np.pi / L
+    assert abs(rate / (nu * k * k) - 1) < 0.01
+
+
+def test_cumulant_refuses_force_and_d3q19(orc):
+    cfg = _cfg(orc, 19, psm=0, collision="cumulant")
+    c, w, _ = orc.lattice(19)
+    with pytest.raises(RuntimeError):
+        orc.collide_cell(cfg, w.copy())
+    cfg = _cum_cfg(orc, force=(1e-5, 0, 0))
+    c, w, _ = orc.lattice(27)
+    with pytest.raises(RuntimeError):
+        orc.collide_cell(cfg, w.copy())
