@@ -57,6 +57,7 @@ enum { PSM_PERIODIC = 0, PSM_WALL = 1, PSM_INLET = 2, PSM_OUTLET = 3 }; /* faces
 enum { PSM_BUF_PDF = 0, PSM_BUF_B = 1, PSM_BUF_WORK = 2, PSM_BUF_ADJOINT = 3, PSM_BUF_GRAD_B = 4,
        PSM_BUF_OBSTACLE = 5 };
 enum { PSM_SHAPE_ELLIPSOID = 0, PSM_SHAPE_CUBE = 1 };
+enum { PSM_COLL_TRT = 0, PSM_COLL_CUMULANT = 1 };               /* fluid collision */
 #define PSM_MAX_BODIES 8
 
 /* Simulation configuration (section II.A; readings of unstated details in the
@@ -76,6 +77,11 @@ enum { PSM_SHAPE_ELLIPSOID = 0, PSM_SHAPE_CUBE = 1 };
  *   tau      relaxation time of the even (viscous) moments, > 1/2
  *   magic    TRT parameter Lambda; odd rate 1/(1/2 + Lambda/(tau - 1/2))
  *   force    body-force density (Guo forcing, part of the fluid collision)
+ *   collision  PSM_COLL_TRT (the above) or PSM_COLL_CUMULANT: the cumulant
+ *            operator the paper's performance runs use (section V, listed in
+ *            section II.B), D3Q27 only and without body force: shear rate
+ *            1/tau, every other rate one (second-order trace to 3 c_s^2,
+ *            cumulants of orders 3..6 to zero); magic is unused
  */
 typedef struct psm_config {
   int32_t nx, ny, nz;
@@ -91,6 +97,8 @@ typedef struct psm_config {
   double magic;
   double force[3];
   double u_in[3];
+  int32_t collision;
+  int32_t reserved;
 } psm_config;
 
 /* Pose and velocity of one rigid body at one step: a body-frame point p is at
@@ -314,7 +322,7 @@ int lbm_set_obstacle(psm_field *f, const uint8_t *solid_dev, void *obst_dev, siz
  * of body 0 (eq. (11), force on the body, about X), under the frozen-B
  * convention: the fractions B(t) are inputs (call geometry_map_step for this
  * step first); the rotation rate enters through u_s = V + W x (x - X) only.
- * Needs a PSM field with sc = 1, slots = 1 and one mapped body.
+ * Needs a PSM field with TRT collision, sc = 1, slots = 1 and one mapped body.
  *   fwd_pdf   the forward PDF buffer as it was before step `step` (parity
  *             step&1, the field's storage type and layout)
  *   ahat_in   adjoint of f(step+1): [q][N], standard layout, adjoint precision

@@ -17,6 +17,7 @@ PSM_F64, PSM_F32, PSM_F16 = 0, 1, 2
 PSM_PERIODIC, PSM_WALL, PSM_INLET, PSM_OUTLET = 0, 1, 2, 3
 PSM_BUF_PDF, PSM_BUF_B, PSM_BUF_WORK, PSM_BUF_ADJOINT, PSM_BUF_GRAD_B, PSM_BUF_OBSTACLE = 0, 1, 2, 3, 4, 5
 PSM_SHAPE_ELLIPSOID, PSM_SHAPE_CUBE = 0, 1
+PSM_COLL_TRT, PSM_COLL_CUMULANT = 0, 1
 PSM_OPT_GENERAL_PATH, PSM_OPT_XCD_REMAP = 1, 2
 PSM_MAX_BODIES = 8
 
@@ -42,7 +43,7 @@ class psm_config(C.Structure):
                 ("storage", C.c_int32), ("psm", C.c_int32), ("sc", C.c_int32), ("b_form", C.c_int32),
                 ("slots", C.c_int32), ("max_bodies", C.c_int32), ("bc", C.c_int32 * 6),
                 ("tau", C.c_double), ("magic", C.c_double), ("force", C.c_double * 3),
-                ("u_in", C.c_double * 3)]
+                ("u_in", C.c_double * 3), ("collision", C.c_int32), ("reserved", C.c_int32)]
 
 
 class psm_body(C.Structure):

@@ -81,8 +81,135 @@ __device__ __forceinline__ bool wave_shl1(bool b) {
 }
 
 // Per-cell collision: TRT + Guo fluid collision blended with NS solid slots.
+// Inverse central-moment transform along one axis: the populations at c = -1,
+// 0, +1 of the central moments (m0, m1, m2) about u (linear in the moments).
+template <typename R>
+__device__ __forceinline__ void chim(R m0, R m1, R m2, R u, R (&o)[3]) {
+#pragma clang fp contract(on)
+  o[0] = R(0.5) * ((u * u - u) * m0 + (R(2) * u - R(1)) * m1 + m2);
+  o[1] = (R(1) - u * u) * m0 - R(2) * u * m1 - m2;
+  o[2] = R(0.5) * ((u * u + u) * m0 + (R(2) * u + R(1)) * m1 + m2);
+}
+template <typename R>
+__device__ __forceinline__ void chim02(R m0, R m2, R u, R (&o)[3]) {  // m1 = 0
+#pragma clang fp contract(on)
+  o[0] = R(0.5) * ((u * u - u) * m0 + m2);
+  o[1] = (R(1) - u * u) * m0 - m2;
+  o[2] = R(0.5) * ((u * u + u) * m0 + m2);
+}
+template <typename R>
+__device__ __forceinline__ void chim1(R m1, R u, R (&o)[3]) {  // m0 = m2 = 0
+#pragma clang fp contract(on)
+  o[0] = R(0.5) * (R(2) * u - R(1)) * m1;
+  o[1] = R(-2) * u * m1;
+  o[2] = R(0.5) * (R(2) * u + R(1)) * m1;
+}
+
+// Cumulant fluid collision (D3Q27, no body force), in deviation variables.
+// The shear rate om = 1/tau relaxes the off-diagonal second-order cumulants
+// and the deviators; every other rate is one: the trace goes to 3 c_s^2 and
+// all cumulants of orders 3..6 to zero.  Then the post-collision central
+// moments (about u) are those of a Gaussian with the relaxed covariance S
+// (Isserlis): E[x^2 y^2] = Sxx Syy + 2 Sxy^2, E[x^2 y z] = Sxx Syz + 2 Sxy Sxz,
+// E[x^2 y^2 z^2] = Sxx Syy Szz + 2 (Sxx Syz^2 + Syy Sxz^2 + Szz Sxy^2)
+// + 8 Sxy Sxz Syz, odd orders zero.  Written as deviations from the rest
+// state (S = I/3): the transform of the rest moments is the product of the
+// 1-D weights (1/6, 2/3, 1/6) shifted by u, so
+//   f*_k - w_k = dr w_k + rho (P_k + D_k),
+// P = product-equilibrium minus rest weights, D = transform of the moment
+// deviations (axis by axis: z, then y, then x).  Returns Om = f* - f.
+template <typename R>
+__device__ __forceinline__ void cumulant_fluid(const R (&f)[27], R dr, R rho, R inv, R ux, R uy, R uz, R om,
+                                               R (&Om)[27]) {
+  // contraction only within an expression: the same bits whatever the kernel
+  // around it (the row kernels and the per-cell general path agree exactly)
+#pragma clang fp contract(on)
+  R pxx = 0, pyy = 0, pzz = 0, pxy = 0, pxz = 0, pyz = 0;
+  sfor<27>([&](auto K) {
+    constexpr int k = K;
+    constexpr int ex = cx<27>(k), ey = cy<27>(k), ez = cz<27>(k);
+    if constexpr (ex != 0) pxx += f[k];
+    if constexpr (ey != 0) pyy += f[k];
+    if constexpr (ez != 0) pzz += f[k];
+    if constexpr (ex * ey == 1) pxy += f[k];
+    if constexpr (ex * ey == -1) pxy -= f[k];
+    if constexpr (ex * ez == 1) pxz += f[k];
+    if constexpr (ex * ez == -1) pxz -= f[k];
+    if constexpr (ey * ez == 1) pyz += f[k];
+    if constexpr (ey * ez == -1) pyz -= f[k];
+  });
+  const R third = R(1) / R(3), d3 = dr * third;
+  const R ecx = (pxx - d3) * inv - ux * ux, ecy = (pyy - d3) * inv - uy * uy, ecz = (pzz - d3) * inv - uz * uz;
+  const R w1 = R(1) - om;
+  const R dxy = w1 * (ecx - ecy), dxz = w1 * (ecx - ecz);
+  const R ex_ = (dxy + dxz) * third, ey_ = ex_ - dxy, ez_ = ex_ - dxz;
+  const R sxy = w1 * (pxy * inv - ux * uy), sxz = w1 * (pxz * inv - ux * uz), syz = w1 * (pyz * inv - uy * uz);
+  // post-collision central moments minus their rest values
+  const R M220 = (ex_ + ey_) * third + ex_ * ey_ + R(2) * sxy * sxy;
+  const R M202 = (ex_ + ez_) * third + ex_ * ez_ + R(2) * sxz * sxz;
+  const R M022 = (ey_ + ez_) * third + ey_ * ez_ + R(2) * syz * syz;
+  const R M211 = (third + ex_) * syz + R(2) * sxy * sxz;
+  const R M121 = (third + ey_) * sxz + R(2) * sxy * syz;
+  const R M112 = (third + ez_) * sxy + R(2) * sxz * syz;
+  const R M222 = (ex_ + ey_ + ez_) * (third * third) + (ex_ * ey_ + ex_ * ez_ + ey_ * ez_) * third + ex_ * ey_ * ez_ +
+                 R(2) * ((third + ex_) * syz * syz + (third + ey_) * sxz * sxz + (third + ez_) * sxy * sxy) +
+                 R(8) * sxy * sxz * syz;
+  // z: G[a][b][cz] for the moment pairs (a, b) of x and y
+  R G[3][3][3];
+  G[0][0][0] = R(0.5) * ez_;
+  G[0][0][1] = -ez_;
+  G[0][0][2] = R(0.5) * ez_;
+  chim1(sxz, uz, G[1][0]);
+  chim1(syz, uz, G[0][1]);
+  chim02(sxy, M112, uz, G[1][1]);
+  chim02(ex_, M202, uz, G[2][0]);
+  chim02(ey_, M022, uz, G[0][2]);
+  chim1(M211, uz, G[2][1]);
+  chim1(M121, uz, G[1][2]);
+  chim02(M220, M222, uz, G[2][2]);
+  // y, then x
+  R H[3][3][3];  // H[a][cy][cz]
+#pragma unroll
+  for (int aa = 0; aa < 3; ++aa)
+#pragma unroll
+    for (int cz = 0; cz < 3; ++cz) {
+      R o[3];
+      chim(G[aa][0][cz], G[aa][1][cz], G[aa][2][cz], uy, o);
+      H[aa][0][cz] = o[0];
+      H[aa][1][cz] = o[1];
+      H[aa][2][cz] = o[2];
+    }
+  R D[3][3][3];  // D[cx][cy][cz]
+#pragma unroll
+  for (int cy = 0; cy < 3; ++cy)
+#pragma unroll
+    for (int cz = 0; cz < 3; ++cz) {
+      R o[3];
+      chim(H[0][cy][cz], H[1][cy][cz], H[2][cy][cz], ux, o);
+      D[0][cy][cz] = o[0];
+      D[1][cy][cz] = o[1];
+      D[2][cy][cz] = o[2];
+    }
+  // product equilibrium minus the rest weights, per axis w1d + d
+  const R u2x = ux * ux, u2y = uy * uy, u2z = uz * uz;
+  const R dxv[3] = {R(0.5) * (u2x - ux), -u2x, R(0.5) * (u2x + ux)};
+  const R dyv[3] = {R(0.5) * (u2y - uy), -u2y, R(0.5) * (u2y + uy)};
+  const R dzv[3] = {R(0.5) * (u2z - uz), -u2z, R(0.5) * (u2z + uz)};
+  sfor<27>([&](auto K) {
+    constexpr int k = K;
+    constexpr int ix = cx<27>(k) + 1, iy = cy<27>(k) + 1, iz = cz<27>(k) + 1;
+    constexpr double wx = ix == 1 ? 2.0 / 3.0 : 1.0 / 6.0, wy = iy == 1 ? 2.0 / 3.0 : 1.0 / 6.0,
+                     wz = iz == 1 ? 2.0 / 3.0 : 1.0 / 6.0;
+    const R tz = R(wz) + dzv[iz];
+    const R P = dxv[ix] * ((R(wy) + dyv[iy]) * tz) + R(wx) * (dyv[iy] * tz + R(wy) * dzv[iz]);
+    Om[k] = (dr * R(wt<27>(k)) + rho * (P + D[ix][iy][iz])) - f[k];
+  });
+}
+
 // f holds deviations delta f; on return f holds the post-collision deviations.
-template <int Q, int SC, int NS, typename R>
+// CM = 0: TRT with Guo forcing; CM = 1: the cumulant collision above (D3Q27,
+// no body force) as the fluid part.
+template <int Q, int SC, int NS, typename R, int CM = 0>
 __device__ __forceinline__ void collide(R (&f)[Q], const SCArgs &a, R B0, const R (&us0)[3], R B1,
                                         const R (&us1)[3], R (&mom0)[3], R (&mom1)[3]) {
   constexpr int H = Lat<Q>::H;
@@ -135,13 +262,23 @@ __device__ __forceinline__ void collide(R (&f)[Q], const SCArgs &a, R B0, const 
   R uss0 = 0, uss1 = 0;
   if constexpr (NS >= 1) uss0 = us0[0] * us0[0] + us0[1] * us0[1] + us0[2] * us0[2];
   if constexpr (NS == 2) uss1 = us1[0] * us1[0] + us1[1] * us1[1] + us1[2] * us1[2];
+  R OmC[CM == 1 ? Q : 1];
+  if constexpr (CM == 1) {
+    static_assert(Q == 27, "the cumulant collision is written for D3Q27");
+    cumulant_fluid<R>(f, dr, rho, inv, ux, uy, uz, le, OmC);
+  }
 
   // rest direction
   {
     const R w = (R)wt<Q>(0);
     const R E = w * (dr - R(1.5) * rho * usq);
-    R om = -le * (f[0] - E);
-    if (hf) om += ge * (R(-3) * w * uF);
+    R om;
+    if constexpr (CM == 1) {
+      om = OmC[0];
+    } else {
+      om = -le * (f[0] - E);
+      if (hf) om += ge * (R(-3) * w * uF);
+    }
     R out = f[0] + fl * om;
     if constexpr (NS >= 1) {
       const R Es = w * (dr - R(1.5) * rho * uss0);
@@ -170,12 +307,19 @@ __device__ __forceinline__ void collide(R (&f)[Q], const SCArgs &a, R B0, const 
     const R cu = R(ex) * ux + R(ey) * uy + R(ez) * uz;
     const R E = w * (dr + rho * (R(4.5) * cu * cu - R(1.5) * usq));
     const R O = R(3) * w * rho * cu;
-    const R fp = R(0.5) * (av + bv), fm = R(0.5) * (av - bv);
-    R rp = -le * (fp - E), rm = -lo * (fm - O);
-    if (hf) {
-      const R cF = R(ex) * Fx + R(ey) * Fy + R(ez) * Fz;
-      rp += ge * (w * (R(9) * cu * cF - R(3) * uF));
-      rm += go * (R(3) * w * cF);
+    R rp, rm;
+    if constexpr (CM == 1) {
+      rp = R(0.5) * (OmC[i] + OmC[ib]);
+      rm = R(0.5) * (OmC[i] - OmC[ib]);
+    } else {
+      const R fp = R(0.5) * (av + bv), fm = R(0.5) * (av - bv);
+      rp = -le * (fp - E);
+      rm = -lo * (fm - O);
+      if (hf) {
+        const R cF = R(ex) * Fx + R(ey) * Fy + R(ez) * Fz;
+        rp += ge * (w * (R(9) * cu * cF - R(3) * uF));
+        rm += go * (R(3) * w * cF);
+      }
     }
     R oa = av + fl * (rp + rm);
     R ob = bv + fl * (rp - rm);
@@ -523,14 +667,14 @@ struct RowCell {
   }
 };
 
-template <int Q, typename T, int PAR, bool EDGE>
+template <int Q, typename T, int PAR, bool EDGE, int CM = 0>
 __device__ __forceinline__ void fluid_row_cell(const SCArgs &a, int x, int y, int z, size_t rowbase) {
   using R = typename Comp<T>::type;
   const RowCell<Q, T, PAR, EDGE> c(a, x, y, z, rowbase);
   R f[Q];
   c.load(f);
   R z3[3] = {0, 0, 0}, m0[3] = {0, 0, 0}, m1[3] = {0, 0, 0};
-  collide<Q, 1, 0, R>(f, a, R(0), z3, R(0), z3, m0, m1);
+  collide<Q, 1, 0, R, CM>(f, a, R(0), z3, R(0), z3, m0, m1);
   c.store(f);
 }
 
@@ -573,7 +717,7 @@ __device__ __forceinline__ void edge_row_yz(const SCArgs &a, int r, int &y, int 
 }
 
 // Rows on a y or z face, TY rows (of the list above) of TX cells per block.
-template <int Q, typename T, int PAR, bool PSM>
+template <int Q, typename T, int PAR, bool PSM, int CM = 0>
 __device__ __forceinline__ void edge_block(const SCArgs &a, uint32_t bid) {
   const int tid = threadIdx.x;
   const int txi = (int)(bid % (uint32_t)a.ntx);
@@ -584,7 +728,7 @@ __device__ __forceinline__ void edge_block(const SCArgs &a, uint32_t bid) {
   const int x = txi * a.TX + (tid & (a.TX - 1));
   const size_t rowbase = (size_t)a.nx * (size_t)y + (size_t)a.nx * (size_t)a.ny * (size_t)z;
   if (!fluid_lane<typename Comp<T>::type, PSM>(a, x, y, z, rowbase)) return;
-  fluid_row_cell<Q, T, PAR, true>(a, x, y, z, rowbase);
+  fluid_row_cell<Q, T, PAR, true, CM>(a, x, y, z, rowbase);
 }
 
 // Odd step, 16-bit storage, interior rows: a wave takes 128 consecutive
@@ -596,7 +740,7 @@ __device__ __forceinline__ void edge_block(const SCArgs &a, uint32_t bid) {
 // x0 + 128) are read and written one element each.  Every lane of the wave
 // must be active; only active cells (fluid, in the row) store, and a value is
 // stored only if its own cell is active.
-template <int Q, bool PSM>
+template <int Q, bool PSM, int CM = 0>
 __device__ __forceinline__ void fluid_seg_h2(const SCArgs &a, int x0, int y, int z, size_t rowbase) {
   using T = _Float16;
   using R = float;
@@ -662,7 +806,7 @@ __device__ __forceinline__ void fluid_seg_h2(const SCArgs &a, int x0, int y, int
       }
     });
     ca.load_fix(f);
-    collide<Q, 1, 0, R>(f, a, R(0), z3, R(0), z3, m0, m1);
+    collide<Q, 1, 0, R, CM>(f, a, R(0), z3, R(0), z3, m0, m1);
     sfor<Q>([&](auto K) { o[(int)K].x = (T)f[opp<Q>((int)K)]; });
     if (ca.xface && acta) face_store(ca, f, cha);
   }
@@ -681,7 +825,7 @@ __device__ __forceinline__ void fluid_seg_h2(const SCArgs &a, int x0, int y, int
       }
     });
     cb.load_fix(f);
-    collide<Q, 1, 0, R>(f, a, R(0), z3, R(0), z3, m0, m1);
+    collide<Q, 1, 0, R, CM>(f, a, R(0), z3, R(0), z3, m0, m1);
     sfor<Q>([&](auto K) { o[(int)K].y = (T)f[opp<Q>((int)K)]; });
     if (cb.xface && actb) face_store(cb, f, chb);
   }
@@ -722,7 +866,7 @@ __device__ __forceinline__ void fluid_seg_h2(const SCArgs &a, int x0, int y, int
 // Odd steps with 16-bit storage and rows of a multiple of 128 cells:
 // interior rows in segments of 128 cells, one segment per wave
 // (fluid_seg_h2).  Other row lengths take k_fluid.
-template <int Q, bool PSM>
+template <int Q, bool PSM, int CM = 0>
 __global__ __launch_bounds__(256) void k_fluid_h2odd(const SCArgs a) {
   const int nsx = a.nx / 128;
   const uint32_t seg = blockIdx.x * 4u + (threadIdx.x >> 6);
@@ -733,12 +877,12 @@ __global__ __launch_bounds__(256) void k_fluid_h2odd(const SCArgs a) {
   const int y = 1 + (int)(r % (uint32_t)(a.ny - 2));
   const int z = 1 + (int)(r / (uint32_t)(a.ny - 2));
   const size_t rowbase = (size_t)a.nx * (size_t)y + (size_t)a.nx * (size_t)a.ny * (size_t)z;
-  fluid_seg_h2<Q, PSM>(a, sx * 128, y, z, rowbase);
+  fluid_seg_h2<Q, PSM, CM>(a, sx * 128, y, z, rowbase);
 }
 
 // Interior rows (1 <= y <= ny-2, 1 <= z <= nz-2), TY rows of TX cells per
 // workgroup.
-template <int Q, typename T, int PAR, bool PSM>
+template <int Q, typename T, int PAR, bool PSM, int CM = 0>
 __global__ __launch_bounds__(256) void k_fluid(const SCArgs a) {
   using R = typename Comp<T>::type;
   const int tid = threadIdx.x;
@@ -746,7 +890,7 @@ __global__ __launch_bounds__(256) void k_fluid(const SCArgs a) {
     // even D3Q19 steps: the rows on the y/z faces ride along as extra blocks
     // (there the edge path needs no more registers than the interior one)
     if (blockIdx.x >= a.ntiles_i) {
-      edge_block<Q, T, PAR, PSM>(a, blockIdx.x - a.ntiles_i);
+      edge_block<Q, T, PAR, PSM, CM>(a, blockIdx.x - a.ntiles_i);
       return;
     }
   }
@@ -761,20 +905,20 @@ __global__ __launch_bounds__(256) void k_fluid(const SCArgs a) {
   if (y > a.ny - 2) return;
   const size_t rowbase = (size_t)a.nx * (size_t)y + (size_t)a.nx * (size_t)a.ny * (size_t)z;
   if (!fluid_lane<R, PSM>(a, x, y, z, rowbase)) return;
-  fluid_row_cell<Q, T, PAR, false>(a, x, y, z, rowbase);
+  fluid_row_cell<Q, T, PAR, false, CM>(a, x, y, z, rowbase);
 }
 
 
-template <int Q, typename T, int PAR, bool PSM>
+template <int Q, typename T, int PAR, bool PSM, int CM = 0>
 __global__ __launch_bounds__(256) void k_fluid_edge(const SCArgs a) {
-  edge_block<Q, T, PAR, PSM>(a, blockIdx.x);
+  edge_block<Q, T, PAR, PSM, CM>(a, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
 // Fluid cells with the general per-lane face handling, one thread per cell in
 // linear order (the cross-check path of PSM_OPT_GENERAL_PATH).
 // ---------------------------------------------------------------------------
-template <int Q, typename T, int PAR>
+template <int Q, typename T, int PAR, int CM = 0>
 __device__ __forceinline__ void general_cell(const SCArgs &a, int x, int y, int z, uint64_t n, uint32_t bcm,
                                              uint32_t outm, uint32_t inm) {
   using R = typename Comp<T>::type;
@@ -788,7 +932,7 @@ __device__ __forceinline__ void general_cell(const SCArgs &a, int x, int y, int 
     f[k] = v;
   });
   R z3[3] = {0, 0, 0}, m0[3] = {0, 0, 0}, m1[3] = {0, 0, 0};
-  collide<Q, 1, 0, R>(f, a, R(0), z3, R(0), z3, m0, m1);
+  collide<Q, 1, 0, R, CM>(f, a, R(0), z3, R(0), z3, m0, m1);
   sfor<Q>([&](auto K) {
     constexpr int k = K;
     R v = ((outm >> k) & 1u) ? f[k] : f[opp<Q>(k)];
@@ -799,7 +943,7 @@ __device__ __forceinline__ void general_cell(const SCArgs &a, int x, int y, int 
   });
 }
 
-template <int Q, typename T, int PAR, bool PSM>
+template <int Q, typename T, int PAR, bool PSM, int CM = 0>
 __global__ __launch_bounds__(256) void k_fluid_general(const SCArgs a) {
   using R = typename Comp<T>::type;
   const uint64_t i = (uint64_t)blockIdx.x * 256u + threadIdx.x;
@@ -815,7 +959,7 @@ __global__ __launch_bounds__(256) void k_fluid_general(const SCArgs a) {
   }
   uint32_t bcm, outm, inm;
   classify<Q>(a, x, y, z, bcm, outm, inm);
-  general_cell<Q, T, PAR>(a, x, y, z, n, bcm, outm, inm);
+  general_cell<Q, T, PAR, CM>(a, x, y, z, n, bcm, outm, inm);
 }
 
 // ---------------------------------------------------------------------------
@@ -824,7 +968,7 @@ __global__ __launch_bounds__(256) void k_fluid_general(const SCArgs a) {
 // wall rule, ahead of the face kinds (wall > inlet > outlet).  Obstacle cells
 // are never touched.
 // ---------------------------------------------------------------------------
-template <int Q, typename T, int PAR>
+template <int Q, typename T, int PAR, int CM = 0>
 __global__ __launch_bounds__(256) void k_obstacle(const SCArgs a) {
   const uint32_t i = blockIdx.x * 256u + threadIdx.x;
   if (i >= a.ocount) return;
@@ -836,7 +980,7 @@ __global__ __launch_bounds__(256) void k_obstacle(const SCArgs a) {
   bcm |= lm;
   outm &= ~lm;
   inm &= ~lm;
-  general_cell<Q, T, PAR>(a, (int)x, (int)y, (int)z, (uint64_t)n, bcm, outm, inm);
+  general_cell<Q, T, PAR, CM>(a, (int)x, (int)y, (int)z, (uint64_t)n, bcm, outm, inm);
 }
 
 // ---------------------------------------------------------------------------
@@ -850,7 +994,7 @@ __global__ __launch_bounds__(256) void k_obstacle(const SCArgs a) {
 // kept in LDS (deterministic) and written once per workgroup.  A cell inside
 // several boxes is taken by the lowest-index box.
 // ---------------------------------------------------------------------------
-template <int Q, typename T, int PAR, int SC>
+template <int Q, typename T, int PAR, int SC, int CM = 0>
 __global__ __launch_bounds__(256) void k_solid(const SCArgs a) {
   using R = typename Comp<T>::type;
   __shared__ double acc[PSM_MAX_BODIES][6];
@@ -982,9 +1126,9 @@ __global__ __launch_bounds__(256) void k_solid(const SCArgs a) {
           }
         }
         if (__any(two)) {
-          collide<Q, SC, 2, R>(f, a, B0, us0, B1, us1, mom0, mom1);
+          collide<Q, SC, 2, R, CM>(f, a, B0, us0, B1, us1, mom0, mom1);
         } else {
-          collide<Q, SC, 1, R>(f, a, B0, us0, B1, us1, mom0, mom1);
+          collide<Q, SC, 1, R, CM>(f, a, B0, us0, B1, us1, mom0, mom1);
         }
         if (act) {
           sfor<Q>([&](auto K) {

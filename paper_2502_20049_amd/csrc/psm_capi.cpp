@@ -91,6 +91,11 @@ static int check_config(const psm_config *c) {
   for (int a = 0; a < 3; ++a)
     if ((c->bc[2 * a] == PSM_PERIODIC) != (c->bc[2 * a + 1] == PSM_PERIODIC))
       return set_error("periodic faces must come in pairs"), PSM_EINVAL;
+  if (c->collision != PSM_COLL_TRT && c->collision != PSM_COLL_CUMULANT)
+    return set_error("collision must be PSM_COLL_TRT or PSM_COLL_CUMULANT"), PSM_EINVAL;
+  if (c->collision == PSM_COLL_CUMULANT &&
+      (c->q != 27 || c->force[0] != 0.0 || c->force[1] != 0.0 || c->force[2] != 0.0))
+    return set_error("the cumulant collision is D3Q27 without body force"), PSM_EUNSUP;
   const int64_t NS = N * (int64_t)storage_size(c->storage);
   if (NS > ((int64_t)1 << 32) && c->sc != 1 && c->psm)
     return set_error("direction arrays over 4 GiB support sc=1 only"), PSM_EUNSUP;
@@ -877,8 +882,8 @@ int psm_adjoint_step(psm_field *f, const void *fwd, int64_t step, const void *ai
                      const psm_body *body, const double axis[3], double wt, void *stream) {
   if (!f || !fwd || !ain || !aout || !dJdB || !body || !axis) return set_error("null argument"), PSM_EINVAL;
   if (step < 0) return set_error("negative step"), PSM_EINVAL;
-  if (!f->cfg.psm || f->cfg.sc != 1 || f->cfg.slots != 1)
-    return set_error("psm_adjoint_step supports PSM fields with SC1 and one body slot"), PSM_EUNSUP;
+  if (!f->cfg.psm || f->cfg.sc != 1 || f->cfg.slots != 1 || f->cfg.collision != PSM_COLL_TRT)
+    return set_error("psm_adjoint_step supports PSM fields with TRT, SC1 and one body slot"), PSM_EUNSUP;
   if (f->nb_mapped != 1) return set_error("psm_adjoint_step needs the single body mapped for this step"), PSM_EINVAL;
   if (ain == aout) return set_error("adjoint input and output must differ"), PSM_EINVAL;
   const double an = axis[0] * axis[0] + axis[1] * axis[1] + axis[2] * axis[2];

@@ -78,6 +78,23 @@ def test_config_validation(capi, sim, field, value, code):
     assert capi.last_error()
 
 
+def test_cumulant_config_validation(capi, sim):
+    """The cumulant collision is D3Q27 without body force; other values of
+    `collision` are invalid."""
+    n = C.c_size_t()
+    cfg = _cfg(sim)
+    cfg.q, cfg.collision = 27, capi.PSM_COLL_CUMULANT
+    assert capi.lib.psm_required_bytes(C.byref(cfg), 0, C.byref(n)) == capi.PSM_OK
+    cfg.q = 19
+    assert capi.lib.psm_required_bytes(C.byref(cfg), 0, C.byref(n)) == capi.PSM_EUNSUP
+    cfg.q = 27
+    cfg.force[0] = 1e-5
+    assert capi.lib.psm_required_bytes(C.byref(cfg), 0, C.byref(n)) == capi.PSM_EUNSUP
+    cfg.force[0] = 0.0
+    cfg.collision = 2
+    assert capi.lib.psm_required_bytes(C.byref(cfg), 0, C.byref(n)) == capi.PSM_EINVAL
+
+
 def test_unpaired_periodic_face_rejected(capi, sim):
     cfg = _cfg(sim)
     cfg.bc[0] = capi.PSM_PERIODIC

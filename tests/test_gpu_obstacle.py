@@ -240,3 +240,17 @@ def test_obstacle_macroscopic_odd_parity(orc, sim, gc, q):
     eu = np.abs(u.cpu().numpy() - uo).max()
     _say(f"[obstacle macro] q={q} rho {er:.1e} u {eu:.1e}")
     assert er < 1e-12 and eu < 1e-12
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_obstacle_cumulant_matches_oracle(orc, sim, gc, storage):
+    """The no-slip obstacle with the cumulant collision (D3Q27, no force)."""
+    wl = _wl(27, storage, "channel", force=(0.0, 0.0, 0.0))
+    wl.collision = "cumulant"
+    _say(f"[obstacle cumulant] {storage}")
+    solid = pi.random_obstacle(61, wl.n_cells, 0.15)
+    f, fo, _ = _run_pair(orc, sim, gc, wl, solid, 4)
+    got = gc.gpu_state_oracle_order(f, orc, sim)
+    err = np.abs(got - fo).max()
+    _say(f"  max |f - f_oracle| = {err:.2e}")
+    assert err < 2 * TOL[storage]
