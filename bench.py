@@ -247,6 +247,33 @@ def node_benchmark(steps=600):
     return out
 
 
+def cumulant_cror(steps=200):
+    """The counter-rotating rotor pair (768 x 384 x 384 D3Q27, FP16 storage, s = 2)
+    with the TRT fluid collision and with the cumulant one (the paper's
+    performance operator): whole-step MLUPS and the stream-collide launch."""
+    import dataclasses
+
+    import torch
+
+    import psm_inputs as pi
+    from paper_2502_20049_amd import sim
+
+    out = {}
+    base = pi.workload_cror(storage="f16")
+    for coll in ("trt", "cumulant"):
+        wl = dataclasses.replace(base, collision=coll)
+        f = sim.Field(wl)
+        wall, t = time_field(f, steps, 10)
+        sc, mp = time_kernels(f, 50, t)
+        out[coll] = {"mlups": round(wl.n_cells * steps / wall / 1e6, 1), "collide_ms": round(sc, 4),
+                     "collide_gbs": round(bytes_per_cell(wl.q, wl.storage) * wl.n_cells / sc / 1e6, 1),
+                     "map_ms": round(mp, 4)}
+        del f
+        torch.cuda.empty_cache()
+    out["case"] = base.name + ", FP16 storage, two counter-rotating 8-blade rotors, s=2"
+    return out
+
+
 def settling_sphere(steps=4000):
     """Two-way coupling on the section IV setup: a sphere (d = 20 cells, density
     ratio 1.16) released from rest near the top of a closed 135 x 135 x 216 box,
@@ -349,6 +376,8 @@ def main():
                          "PSM rotating)")
     ap.add_argument("--settling-only", action="store_true",
                     help="run only the two-way coupled settling sphere (section IV setup)")
+    ap.add_argument("--cumulant-only", action="store_true",
+                    help="run only the TRT / cumulant comparison on the counter-rotating rotor pair")
     ap.add_argument("--copy-only", action="store_true",
                     help="run only the device copy probe (1 GiB read + 1 GiB written per launch): the "
                          "calibration for rocprofv3 FETCH_SIZE / WRITE_SIZE")
@@ -371,6 +400,9 @@ def main():
         return
     if args.settling_only:
         print(json.dumps(settling_sphere()), flush=True)
+        return
+    if args.cumulant_only:
+        print(json.dumps(cumulant_cror()), flush=True)
         return
     if args.copy_only:
         bw = copy_probe(nbytes=1 << 30, reps=5)
@@ -439,6 +471,7 @@ def main():
         extras["node_benchmark"] = node_benchmark()
         extras["adjoint_rotor_128"] = adjoint_rate()
         extras["settling_sphere"] = settling_sphere()
+        extras["cumulant_vs_trt_cror"] = cumulant_cror()
         line["extras"] = extras
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(wl)
