@@ -164,3 +164,62 @@ def test_capacity_1024_full_size(orc, sim):
     _map_samples(orc, f, wl, geoms, bcells, 1)
     mass = f.mass(2).item()
     assert np.isfinite(mass)
+
+
+def test_cror_768_cumulant_full_size(orc, sim):
+    """The rotor pair with the cumulant collision (FP16 storage, the odd steps
+    on the one-cell-per-lane kernel): sampled cells against the oracle's
+    one-cell updates."""
+    _say("[full-size] 768x384x384 D3Q27 rotor pair, cumulant, FP16 storage")
+    wl = pi.workload_cror(storage="f16")
+    wl.collision = "cumulant"
+    rng = np.random.default_rng(6)
+    cells = _far_from_bodies(wl, _edge_cells(wl, rng), 4.0)
+    _run(orc, sim, wl, 7, cells, lambda d: np.full_like(d, 4 * 2.0 ** -11 * np.abs(d).max() + 2e-6), lazy=True)
+
+
+def test_rotor_box_256_obstacle_full_size(sim):
+    """LBM with the voxelised 8-blade rotor (r = 120) as a static no-slip
+    obstacle on the 256^3 periodic box, two steps from a seeded state:
+    obstacle cells keep their values bit for bit; cells whose two-step
+    dependence cone holds no obstacle cell or neighbour match plain LBM bit for
+    bit (same kernel path); FP64 mass of all slots conserved up to the FP32
+    rounding of the stored deviations."""
+    import dataclasses
+
+    import torch
+    import torch.nn.functional as F
+
+    _say("[full-size] 256^3 rotor box, LBM + no-slip obstacle, FP32")
+    wl = dataclasses.replace(pi.workload_rotor_box(steps=2), bc=("periodic",) * 6, u_in=(0.0, 0.0, 0.0))
+    solid = sim.voxelize_obstacle(wl, 0)
+    c, _, _ = sim.lattice(19)
+    runs = []
+    for with_obst in (True, False):
+        f = sim.Field(wl, psm=False)
+        for k in range(19):
+            f.pdf_view()[k].copy_(pi.random_state_torch(8, c[k:k + 1], wl.n_cells, f.pdf.device, f.dtype)[0])
+        if with_obst:
+            n_near = f.set_obstacle(solid)
+            f0 = f.pdf_view()[:, solid.bool()].clone()
+            m0 = float(f.mass(0).item())
+        f.step(0)
+        f.step(1)
+        torch.cuda.synchronize()
+        if with_obst:
+            assert torch.equal(f.pdf_view()[:, solid.bool()], f0)
+            m1 = float(f.mass(2).item())
+            assert abs(m1 - m0) / abs(m0) < 1e-7  # FP32 rounding of ~3e8 stored deviations
+        runs.append(f.pdf_view().clone())
+        del f
+        torch.cuda.empty_cache()
+    # cells at distance > 3 from every obstacle cell (periodic): a 7^3 max filter of the mask
+    s3 = solid.view(1, 1, wl.nz, wl.ny, wl.nx).float()
+    s3 = torch.cat([s3[..., -3:, :, :], s3, s3[..., :3, :, :]], dim=2)
+    s3 = torch.cat([s3[..., :, -3:, :], s3, s3[..., :, :3, :]], dim=3)
+    s3 = torch.cat([s3[..., :, :, -3:], s3, s3[..., :, :, :3]], dim=4)
+    near = F.max_pool3d(s3, 7, stride=1).view(-1) > 0
+    far = ~near
+    _say(f"  near cells {n_near}, far cells {int(far.sum())}")
+    assert int(far.sum()) > wl.n_cells // 2
+    assert torch.equal(runs[0][:, far], runs[1][:, far])
