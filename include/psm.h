@@ -128,7 +128,8 @@ typedef struct psm_geom psm_geom;   /* opaque: body-frame geometry field      */
 const char *psm_last_error(void);
 
 /* Bytes the caller must provide for buffer `which` (PSM_BUF_*):
- *   PDF  q*N*sizeof(storage)
+ *   PDF  q*S*sizeof(storage): direction k occupies elements [k*S, k*S + N)
+ *        with S = psm_pdf_stride(cfg) >= N (cell n = x + nx*(y + ny*z))
  *   B    psm ? N*4*slots + N (FP32 fraction per slot + one body-id byte) : 0
  *   WORK flags + force/torque partials (max_bodies*6 doubles per solid-kernel
  *        workgroup, 2048 of them) + reduction scratch + the mapping's lists
@@ -141,6 +142,11 @@ const char *psm_last_error(void);
  *        256 B header + N class bytes (padded to 256 B) + 8 B per listed
  *        cell, sized here for the worst case of N listed cells              */
 int psm_required_bytes(const psm_config *cfg, int which, size_t *out_bytes);
+
+/* Elements between the starts of consecutive direction arrays of the PDF
+ * buffer: N rounded up to a 4 KiB multiple in bytes, plus 4 KiB (so the
+ * arrays do not all start at the same offset modulo a large power of two). */
+int psm_pdf_stride(const psm_config *cfg, int64_t *elems);
 
 /* This library's lattice: velocities c[q][3], weights w[q], opposite opp[q]
  * (host arrays of at least q entries). */

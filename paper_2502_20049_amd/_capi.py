@@ -28,7 +28,7 @@ EXPORTS = [
     "geometry_field_create", "geometry_field_create_analytic", "geometry_field_destroy", "geometry_map_step",
     "psm_stream_collide", "body_force_torque", "psm_mass_fp64", "psm_macroscopic", "psm_error_flags",
     "psm_set_option", "psm_stream_copy", "psm_set_fraction_offset", "psm_adjoint_step", "psm_adjoint_omega",
-    "psm_step", "lbm_set_obstacle", "psm_rigid_body", "psm_rigid_advance", "psm_coupled_step",
+    "psm_step", "lbm_set_obstacle", "psm_rigid_body", "psm_rigid_advance", "psm_coupled_step", "psm_pdf_stride",
 ]
 
 
@@ -97,6 +97,7 @@ def _load():
         "psm_rigid_body": (C.c_int, [C.POINTER(psm_rigid), C.POINTER(psm_body)]),
         "psm_rigid_advance": (C.c_int, [C.POINTER(psm_rigid), dp, C.c_double]),
         "psm_coupled_step": (C.c_int, [vp, C.POINTER(psm_rigid), C.POINTER(vp), C.c_int, i64, vp, dp, vp]),
+        "psm_pdf_stride": (C.c_int, [C.POINTER(psm_config), C.POINTER(i64)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)

@@ -96,26 +96,27 @@ __global__ __launch_bounds__(256) void k_adjoint(const AdjArgs A) {
     // forward state before the step, as deviations d_k = f_k - w_k, and the
     // adjoint gh of the post-collision values (transpose of the streaming)
     const T *fwd = (const T *)A.fwd;
+    const uint64_t FS = a.dS;  // the forward state has the PDF buffer's layout
     const R *ain = (const R *)A.ain;
     R d[Q], gh[Q];
     if (bcm == 0) {  // no face direction: plain pulls / pushes with periodic wrap
       sfor<Q>([&](auto K) {
         constexpr int k = K;
-        if constexpr (PAR == 0 || k == 0) d[k] = (R)fwd[(size_t)k * N + n];
-        else d[k] = (R)fwd[(size_t)opp<Q>(k) * N + nbr<-cx<Q>(k), -cy<Q>(k), -cz<Q>(k)>(n, nx, nxy, w)];
+        if constexpr (PAR == 0 || k == 0) d[k] = (R)fwd[(size_t)k * FS + n];
+        else d[k] = (R)fwd[(size_t)opp<Q>(k) * FS + nbr<-cx<Q>(k), -cy<Q>(k), -cz<Q>(k)>(n, nx, nxy, w)];
         if constexpr (k == 0) gh[k] = ain[n];
         else gh[k] = ain[(size_t)k * N + nbr<cx<Q>(k), cy<Q>(k), cz<Q>(k)>(n, nx, nxy, w)];
       });
     } else {
       sfor<Q>([&](auto K) {
         constexpr int k = K;
-        const T *own = fwd + (size_t)k * N + n;
+        const T *own = fwd + (size_t)k * FS + n;
         R v;
         if constexpr (PAR == 0 || k == 0) {
           v = (R)*own;
         } else {
           const uint32_t src = nbr<-cx<Q>(k), -cy<Q>(k), -cz<Q>(k)>(n, nx, nxy, w);
-          const T *p = ((bcm >> k) & 1u) ? own : fwd + (size_t)opp<Q>(k) * N + src;
+          const T *p = ((bcm >> k) & 1u) ? own : fwd + (size_t)opp<Q>(k) * FS + src;
           v = (R)*p;
           if ((inm >> k) & 1u) v += inlet_term<Q, R>(a, k);
         }

@@ -42,7 +42,7 @@ hipError_t launch_ft_reduce(const psm_field &f, int nb, double *ft, hipStream_t 
 // inlet term) when the source is outside the domain.
 template <int Q, typename T>
 __device__ double read_f(const SCArgs &a, int parity, int k, int x, int y, int z, uint64_t n) {
-  const uint64_t N = a.N;
+  const uint64_t N = a.dS;  // direction stride
   const T *A = (const T *)a.pdf;
   if (parity == 0) return (double)A[(uint64_t)k * N + n];
   // obstacle cells are never updated: their own slots hold their values

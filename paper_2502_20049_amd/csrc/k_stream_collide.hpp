@@ -424,7 +424,7 @@ __device__ __forceinline__ void classify(const SCArgs &a, int x, int y, int z, u
 template <int Q, typename T, int PAR>
 __device__ __forceinline__ char *slot_general(const SCArgs &a, char *pdf, int k, int x, int y, int z, uint64_t n,
                                               uint32_t bcm) {
-  const size_t NS = (size_t)a.N * sizeof(T);
+  const size_t NS = (size_t)a.dS * sizeof(T);
   if (PAR == 0 || ((bcm >> k) & 1u)) return pdf + (size_t)k * NS + (size_t)n * sizeof(T);
   int sx = x - cx<Q>(k), sy = y - cy<Q>(k), sz = z - cz<Q>(k);
   if (sx < 0) sx += a.nx;
@@ -522,7 +522,7 @@ struct RowCell {
     o0 = (uint32_t)x * S;
     om = (uint32_t)xm * S;
     op = (uint32_t)xp * S;
-    NS = (size_t)a.N * S;
+    NS = (size_t)a.dS * S;
     own_row = a.pdf + rowbase * S;
     // y/z face rules of this row (wave-uniform)
     if constexpr (EDGE) {

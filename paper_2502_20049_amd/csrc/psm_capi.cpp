@@ -54,6 +54,17 @@ struct Layout {
 // and the mapping's surface-cell lists
 constexpr size_t OFF_MAP_COUNT = 64;
 
+// Direction arrays of the PDF buffer: N elements each, padded so that
+// consecutive arrays start 4 KiB past a 4 KiB multiple apart (the 19 or 27
+// streams of a step then do not all fall at the same offset modulo a large
+// power of two: measured 1-4% faster on 256^3 than back-to-back arrays).
+static int64_t pdf_stride_elems(const psm_config &c) {
+  const int64_t N = (int64_t)c.nx * c.ny * c.nz;
+  const int64_t sz = (int64_t)storage_size(c.storage);
+  const int64_t bytes = ((N * sz + 4095) / 4096) * 4096 + 4096;
+  return bytes / sz;
+}
+
 static Layout layout_of(const psm_config &c) {
   Layout L{};
   L.N = (int64_t)c.nx * c.ny * c.nz;
@@ -115,6 +126,7 @@ SCArgs make_sc_args(const psm_field &f) {
   a.ny = c.ny;
   a.nz = c.nz;
   a.N = (uint32_t)f.N;
+  a.dS = (uint64_t)f.dstride;
   a.TX = f.TX;
   a.TY = f.TY;
   a.lTX = f.lTX;
@@ -186,7 +198,7 @@ int psm_required_bytes(const psm_config *cfg, int which, size_t *out) {
   const Layout L = layout_of(*cfg);
   switch (which) {
     case PSM_BUF_PDF:
-      *out = (size_t)cfg->q * (size_t)L.N * storage_size(cfg->storage);
+      *out = (size_t)cfg->q * (size_t)pdf_stride_elems(*cfg) * storage_size(cfg->storage);
       return PSM_OK;
     case PSM_BUF_B:
       *out = cfg->psm ? (size_t)L.N * 4 * cfg->slots + (size_t)L.N : 0;
@@ -205,6 +217,14 @@ int psm_required_bytes(const psm_config *cfg, int which, size_t *out) {
       return PSM_OK;
   }
   return set_error("bad buffer id"), PSM_EINVAL;
+}
+
+int psm_pdf_stride(const psm_config *cfg, int64_t *elems) {
+  int r = check_config(cfg);
+  if (r) return r;
+  if (!elems) return set_error("null output"), PSM_EINVAL;
+  *elems = pdf_stride_elems(*cfg);
+  return PSM_OK;
 }
 
 int psm_lattice(int q, int32_t *c, double *w, int32_t *o) {
@@ -271,6 +291,7 @@ int pdf_field_create(const psm_config *cfg, void *pdf, size_t pdf_bytes, void *b
   f->pdf = pdf;
   f->pdf_bytes = pdf_bytes;
   f->N = L.N;
+  f->dstride = pdf_stride_elems(*cfg);
   if (cfg->psm) {
     f->B0 = (float *)b;
     f->B1 = cfg->slots == 2 ? (float *)b + L.N : nullptr;

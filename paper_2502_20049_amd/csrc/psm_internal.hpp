@@ -99,6 +99,7 @@ struct SCArgs {
   double *ftp;      // [solid workgroup][max_bodies][6]
   int nx, ny, nz;
   uint32_t N;
+  uint64_t dS;  // elements between consecutive direction arrays of the PDF buffer
   int TX, TY, lTX;  // tile shape of the interior kernel, log2(TX)
   int ntx;
   int nty_i;          // tile rows over the interior rows 1..ny-2
@@ -209,6 +210,7 @@ struct psm_field {
   int map_list_cap;     // entries per body actually used (PSM_OPT_MAP_LIST)
   size_t red_count;
   int64_t N;
+  int64_t dstride;  // direction stride of the PDF buffer, elements
   int TX, TY, lTX, ntx, nty;
   int64_t ntiles;
   int nb_mapped;

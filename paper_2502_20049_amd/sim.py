@@ -119,6 +119,9 @@ class Field:
         self.N = wl.n_cells
         self.dtype = STORAGE[self.storage][1]
         pb = required_bytes(self.cfg, capi.PSM_BUF_PDF)
+        st = C.c_int64()
+        check(lib.psm_pdf_stride(C.byref(self.cfg), C.byref(st)), "psm_pdf_stride")
+        self.dstride = st.value
         bb = required_bytes(self.cfg, capi.PSM_BUF_B)
         wb = required_bytes(self.cfg, capi.PSM_BUF_WORK)
         self.pdf = torch.empty(pb // self.dtype.itemsize, dtype=self.dtype, device=device)
@@ -142,8 +145,9 @@ class Field:
 
     # -- buffers ---------------------------------------------------------
     def pdf_view(self):
-        """(q, N) view of the stored deviations f_k - w_k (library direction order)."""
-        return self.pdf[: self.q * self.N].view(self.q, self.N)
+        """(q, N) view of the stored deviations f_k - w_k (library direction
+        order); rows are psm_pdf_stride elements apart in the buffer."""
+        return self.pdf.as_strided((self.q, self.N), (self.dstride, 1))
 
     def b_view(self):
         """(slots, N) float32 solid fractions and (N,) uint8 body ids."""

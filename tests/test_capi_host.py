@@ -52,12 +52,17 @@ def _cfg(sim, **kw):
 def test_required_bytes(capi, sim):
     cfg = _cfg(sim)
     N = 40 * 30 * 20
-    assert sim.required_bytes(cfg, capi.PSM_BUF_PDF) == 19 * N * 4
+    def stride(sz):  # N padded to a 4 KiB multiple plus 4 KiB, in elements
+        return ((N * sz + 4095) // 4096 * 4096 + 4096) // sz
+
+    st = C.c_int64()
+    assert capi.lib.psm_pdf_stride(C.byref(cfg), C.byref(st)) == 0 and st.value == stride(4)
+    assert sim.required_bytes(cfg, capi.PSM_BUF_PDF) == 19 * stride(4) * 4
     assert sim.required_bytes(cfg, capi.PSM_BUF_B) == N * 4 + N
     cfg.slots = 2
     assert sim.required_bytes(cfg, capi.PSM_BUF_B) == 2 * N * 4 + N
     cfg.q, cfg.storage = 27, capi.PSM_F16
-    assert sim.required_bytes(cfg, capi.PSM_BUF_PDF) == 27 * N * 2
+    assert sim.required_bytes(cfg, capi.PSM_BUF_PDF) == 27 * stride(2) * 2
     assert sim.required_bytes(cfg, capi.PSM_BUF_OBSTACLE) == 0
     cfg.psm = 0
     assert sim.required_bytes(cfg, capi.PSM_BUF_B) == 0
