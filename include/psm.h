@@ -9,7 +9,7 @@
  * One time step of the hot path is, on the caller's HIP stream:
  *   geometry_map_step   solid fractions B(x,t) from body-frame geometry fields
  *                       under each body's current rotation/translation (sec. III)
- *   psm_stream_collide  fused in-place (AA pattern) stream + TRT collision
+ *   psm_stream_collide  fused in-place (AA pattern) stream + TRT (or cumulant) collision
  *                       blended with the solid collision, eq. (4), summed over
  *                       up to two overlapping bodies per cell; writes per-tile
  *                       force/torque partials (eqs. (10)-(11))
@@ -26,8 +26,9 @@
  *     failures are reported as PSM_EHIP.  No C++ exception crosses the ABI.
  *   - Lattice units: dx = dt = 1, rest density 1, cell (i,j,k) has its centre
  *     at (i+1/2, j+1/2, k+1/2).  Linear cell index n = x + nx*(y + ny*z).
- *   - PDF layout: structure of arrays, slot (k, n) at element k*N + n (N =
- *     nx*ny*nz cells, x fastest).  Stored values are deviations
+ *   - PDF layout: structure of arrays, slot (k, n) at element k*S + n (N =
+ *     nx*ny*nz cells, x fastest; S = psm_pdf_stride() >= N, the direction
+ *     arrays padded apart).  Stored values are deviations
  *     delta f_k = f_k - w_k from the lattice weights, in the storage type.
  *     Direction order is this library's own (psm_lattice()).  The in-place
  *     AA pattern leaves the buffer in the standard layout (slot (k,n) holds
@@ -331,7 +332,8 @@ int lbm_set_obstacle(psm_field *f, const uint8_t *solid_dev, void *obst_dev, siz
  * Needs a PSM field with TRT collision, sc = 1, slots = 1 and one mapped body.
  *   fwd_pdf   the forward PDF buffer as it was before step `step` (parity
  *             step&1, the field's storage type and layout)
- *   ahat_in   adjoint of f(step+1): [q][N], standard layout, adjoint precision
+ *   ahat_in   adjoint of f(step+1): [q][N] (element k*N + n, unpadded),
+ *             standard layout, adjoint precision
  *   ahat_out  adjoint of f(step) (written; must not alias ahat_in)
  *   dJdB      accumulated: dJdB[n] += dJ/dB(n, step)
  *   body      the pose/velocity of body 0 used by the forward step (W may
