@@ -236,7 +236,25 @@ void coarse_map(int s, const int32_t mmin[3], const int32_t dims[3], const uint3
       out[(r)*cdims[0] + (bx - cmin[0])] = (uint8_t)st;
     }
   });
-  (void)nblk;
+  // bit 2: the block and its 26 neighbours (outside the box: all out) share
+  // one uniform state, so a cell whose centre lies in the block is decided by
+  // that block alone (its sub-samples stay within one block of the centre)
+  std::vector<uint8_t> st(out, out + nblk);
+  auto at = [&](int64_t x, int64_t y, int64_t z) -> int {
+    if (x < 0 || y < 0 || z < 0 || x >= cdims[0] || y >= cdims[1] || z >= cdims[2]) return 0;
+    return st[(z * cdims[1] + y) * cdims[0] + x];
+  };
+  parallel_rows((int64_t)cdims[1] * cdims[2], [&](int64_t r) {
+    const int64_t y = r % cdims[1], z = r / cdims[1];
+    for (int64_t x = 0; x < cdims[0]; ++x) {
+      const int v = at(x, y, z);
+      bool uni = v != 2;
+      for (int dz = -1; dz <= 1 && uni; ++dz)
+        for (int dy = -1; dy <= 1 && uni; ++dy)
+          for (int dx = -1; dx <= 1 && uni; ++dx) uni = at(x + dx, y + dy, z + dz) == v;
+      if (uni) out[r * cdims[0] + x] = (uint8_t)(v | 4);
+    }
+  });
 }
 
 }  // namespace psm

@@ -48,7 +48,20 @@ __device__ __forceinline__ int coarse_state(const MapBodyK &g, long long bx, lon
   if ((unsigned long long)jx >= (unsigned long long)g.cdims[0] || (unsigned long long)jy >= (unsigned long long)g.cdims[1] ||
       (unsigned long long)jz >= (unsigned long long)g.cdims[2])
     return 0;
-  return g.coarse[((size_t)jz * g.cdims[1] + (size_t)jy) * g.cdims[0] + (size_t)jx];
+  return g.coarse[((size_t)jz * g.cdims[1] + (size_t)jy) * g.cdims[0] + (size_t)jx] & 3;
+}
+
+// The cell decided from the block of its centre alone: every sub-sample lies
+// within one block of the centre, so a centre two or more blocks outside the
+// box is all out, and a block marked uniform with its 26 neighbours (bit 2)
+// gives its state.  -1: undecided (look at every block the sub-samples span).
+__device__ __forceinline__ int coarse_centre(const MapBodyK &g, const long long P[3]) {
+  const long long jx = (P[0] >> (32 + g.s)) - g.cmin[0], jy = (P[1] >> (32 + g.s)) - g.cmin[1],
+                  jz = (P[2] >> (32 + g.s)) - g.cmin[2];
+  if (jx < -1 || jy < -1 || jz < -1 || jx > g.cdims[0] || jy > g.cdims[1] || jz > g.cdims[2]) return 0;
+  if (jx < 0 || jy < 0 || jz < 0 || jx >= g.cdims[0] || jy >= g.cdims[1] || jz >= g.cdims[2]) return -1;
+  const int v = g.coarse[((size_t)jz * g.cdims[1] + (size_t)jy) * g.cdims[0] + (size_t)jx];
+  return (v & 4) ? (v & 3) : -1;
 }
 
 // Wave-cooperative sampling of the surface cells of a wave (s >= 2): the
@@ -202,7 +215,7 @@ __global__ __launch_bounds__(256) void k_map(const MapArgs a) {
       body_point(g, x, y, z, P);
       if (s == 0) {
         state = 2;
-      } else {
+      } else if ((state = coarse_centre(g, P)) < 0) {
         long long lo[3], hi[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
