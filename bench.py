@@ -344,14 +344,22 @@ def adjoint_rate(steps=800, window=200):
             "backward_mcell_steps_per_s": round(N * steps / (t2 - t1) / 1e6, 1)}
 
 
-def cpu_baseline(wl, nsteps=2):
+def cpu_baseline(wl, min_seconds=12.0):
+    """The FP64 oracle on the host cores, full-size steps of the same workload
+    (map + collide/stream + F/T), two at a time until about min_seconds have
+    passed."""
     import oracle
 
     oracle.build(force=False)
     run = oracle.Run(wl)
     t0 = time.perf_counter()
-    run.advance(nsteps)
-    dt = time.perf_counter() - t0
+    nsteps = 0
+    while True:
+        run.advance(2)
+        nsteps += 2
+        dt = time.perf_counter() - t0
+        if dt >= min_seconds:
+            break
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": round(wl.n_cells * nsteps / dt / 1e6, 3), "unit": "MLUPS", "cores": threads,
             "kind": "oracle",
