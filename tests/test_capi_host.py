@@ -248,3 +248,17 @@ def test_rigid_advance_matches_oracle(capi, orc):
     assert np.array_equal(np.array(body.X), np.array(s.X)) and np.array_equal(np.array(body.W), np.array(s.W))
     bad = capi.psm_rigid()
     assert capi.lib.psm_rigid_advance(C.byref(bad), ft.ctypes.data_as(C.POINTER(C.c_double)), 1.0) == capi.PSM_EINVAL
+
+
+def test_new_entry_points_reject_null_arguments(capi, sim):
+    """Host-side argument checks of the obstacle, coupling and layout calls
+    (no device access)."""
+    cfg = _cfg(sim)
+    st = C.c_int64()
+    assert capi.lib.psm_pdf_stride(None, C.byref(st)) == capi.PSM_EINVAL
+    assert capi.lib.psm_pdf_stride(C.byref(cfg), None) == capi.PSM_EINVAL
+    assert capi.lib.lbm_set_obstacle(None, None, None, 0, None, None) == capi.PSM_EINVAL
+    assert capi.lib.psm_coupled_step(None, None, None, 1, 0, None, None, None) == capi.PSM_EINVAL
+    assert capi.lib.psm_rigid_body(None, None) == capi.PSM_EINVAL
+    s = capi.psm_rigid()
+    assert capi.lib.psm_rigid_advance(C.byref(s), None, 1.0) == capi.PSM_EINVAL
