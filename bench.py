@@ -147,37 +147,6 @@ def traffic_record(kname, wname):
     return rec.get("bytes_per_launch")
 
 
-def accuracy_check(steps=100):
-    """FP32 / FP16 storage vs the FP64 oracle on a reduced copy of the channel."""
-    import numpy as np
-    import torch
-
-    import oracle
-    import psm_inputs as pi
-    from paper_2502_20049_amd import sim
-
-    out = {}
-    wl = pi.workload_ellipsoid_channel(n=48, steps=steps, scale=0.25, s=3)
-    wl.bodies[0].motion.omega = 4e-3
-    run = oracle.Run(wl).advance(steps)
-    _, uo = run.macro()
-    Tz_o = np.array(run.ft)[:, 0, 5]
-    for st in ("f32", "f16"):
-        f = sim.Field(wl, storage=st)
-        ft = []
-        for t in range(steps):
-            f.step(t)
-            ft.append(f.force_torque()[0, 5].item())
-        _, ug = f.macroscopic(steps)
-        ug = ug.cpu().numpy()
-        out[st] = {"u_rel_l2": float(np.linalg.norm(ug - uo) / np.linalg.norm(uo)),
-                   "torque_rel_max": float(np.abs(np.array(ft) - Tz_o).max() / np.abs(Tz_o).max())}
-        del f
-        torch.cuda.empty_cache()
-    out["case"] = f"48^3 channel, ellipsoid (10,5,2) s=3, {steps} steps, vs FP64 oracle"
-    return out
-
-
 def s_sweep(steps=200):
     """The channel workload at supersampling s = 0..3 (PSM + mapping every step)."""
     import torch
@@ -375,7 +344,7 @@ def main():
     ap.add_argument("--storage", choices=["f64", "f32", "f16"], default=None,
                     help="PDF storage type (default: the workload's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extras", action="store_true", help="skip variants, copy probe and accuracy")
+    ap.add_argument("--no-extras", action="store_true", help="skip the variants, the copy probe and the other workloads")
     ap.add_argument("--only-psm", action="store_true", help="time the PSM path only (for profiling)")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="run only the torque-gradient sweep on the 128^3 rotor (for profiling)")
@@ -474,7 +443,6 @@ def main():
         bw = copy_probe()
         extras["copy_probe_gbs"] = round(bw, 1)
         extras["psm_frac_of_copy_bw"] = round(achieved / bw, 4)
-        extras["accuracy_vs_fp64_oracle"] = accuracy_check()
         extras["supersampling_sweep"] = s_sweep()
         extras["node_benchmark"] = node_benchmark()
         extras["adjoint_rotor_128"] = adjoint_rate()

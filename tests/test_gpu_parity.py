@@ -421,3 +421,33 @@ def test_ellipsoid_channel_fp32_trajectory(orc, sim, gc):
     _say(f"  u rel L2 {relu:.2e}; torque series rel {relT:.2e}; window mean rel {relJ:.2e}")
     assert relu < 1e-5
     assert relT < 1e-4 and relJ < 1e-4
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_channel_accuracy_vs_fp64_oracle(orc, sim, storage):
+    """Reduced rotating-ellipsoid channel (48^3, s = 3, 100 steps): FP32 and
+    FP16 deviation storage against the FP64 oracle, velocity rel. L2 and the
+    torque series (targets: FP32 1e-5 / 1e-4; FP16 storage rounds each stored
+    deviation to 11 bits: 5e-4 / 1e-4)."""
+    import torch
+
+    wl = pi.workload_ellipsoid_channel(n=48, storage=storage, steps=100, scale=0.25, s=3)
+    wl.bodies[0].motion.omega = 4e-3
+    run = orc.Run(wl).advance(wl.steps)
+    _, uo = run.macro()
+    Tz_o = np.array(run.ft)[:, 0, 5]
+    f = sim.Field(wl)
+    tz = []
+    for t in range(wl.steps):
+        f.step(t)
+        tz.append(f.force_torque()[0, 5].item())
+    _, ug = f.macroscopic(wl.steps)
+    torch.cuda.synchronize()
+    ug = ug.cpu().numpy()
+    relu = float(np.linalg.norm(ug - uo) / np.linalg.norm(uo))
+    relT = float(np.abs(np.array(tz) - Tz_o).max() / np.abs(Tz_o).max())
+    _say(f"[accuracy] {storage}: u rel L2 {relu:.2e}, torque rel max {relT:.2e}")
+    if storage == "f32":
+        assert relu < 1e-5 and relT < 1e-4
+    else:
+        assert relu < 5e-4 and relT < 1e-4
