@@ -997,14 +997,13 @@ __global__ __launch_bounds__(256) void k_obstacle(const SCArgs a) {
 template <int Q, typename T, int PAR, int SC, int CM = 0>
 __global__ __launch_bounds__(256) void k_solid(const SCArgs a) {
   using R = typename Comp<T>::type;
-  __shared__ double acc[PSM_MAX_BODIES][6];
-  __shared__ double wred[4][6];
+  __shared__ double wacc[4][PSM_MAX_BODIES][6];  // per-wave F/T sums (each wave writes only its own)
   __shared__ uint32_t cells_l[SOLID_MAX_CPW * 256];
   __shared__ R bfrac_l[SOLID_MAX_CPW * 256];
   __shared__ uint8_t meta_l[SOLID_MAX_CPW * 256];
   __shared__ uint32_t wcnt[SOLID_MAX_CPW][4];
   const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
-  if (tid < PSM_MAX_BODIES * 6) acc[tid / 6][tid % 6] = 0.0;
+  if (tid < 4 * PSM_MAX_BODIES * 6) (&wacc[0][0][0])[tid] = 0.0;
   __syncthreads();
   const uint32_t cpw = (uint32_t)a.cpw;
   const uint32_t ngroups = (a.nchunks + cpw - 1) / cpw;
@@ -1141,10 +1140,11 @@ __global__ __launch_bounds__(256) void k_solid(const SCArgs a) {
           });
         }
       }
-      // force / torque on each body touched by these cells
+      // force / torque on each body touched by these cells, summed per wave
+      // (fixed lane tree, rounds in order) into the wave's own slots
       for (int b = 0; b < a.nb; ++b) {
         const bool has = act && (b0 == b || (two && b1 == b));
-        if (!__syncthreads_or(has)) continue;
+        if (!__any(has)) continue;  // wave-uniform
         const BodyK &bd = a.body[b];
         double v0 = 0, v1 = 0, v2 = 0;
         if (act && b0 == b) {
@@ -1166,22 +1166,22 @@ __global__ __launch_bounds__(256) void k_solid(const SCArgs a) {
         v4 = wave_sum(v4);
         v5 = wave_sum(v5);
         if (lane == 0) {
-          wred[wid][0] = v0;
-          wred[wid][1] = v1;
-          wred[wid][2] = v2;
-          wred[wid][3] = v3;
-          wred[wid][4] = v4;
-          wred[wid][5] = v5;
+          wacc[wid][b][0] += v0;
+          wacc[wid][b][1] += v1;
+          wacc[wid][b][2] += v2;
+          wacc[wid][b][3] += v3;
+          wacc[wid][b][4] += v4;
+          wacc[wid][b][5] += v5;
         }
-        __syncthreads();
-        if (tid < 6) acc[b][tid] += ((wred[0][tid] + wred[1][tid]) + wred[2][tid]) + wred[3][tid];
-        __syncthreads();
       }
     }
     __syncthreads();  // the list is rebuilt for the next group
   }
   __syncthreads();
-  if (tid < a.nb * 6) a.ftp[((size_t)blockIdx.x * a.max_bodies + tid / 6) * 6 + tid % 6] = acc[tid / 6][tid % 6];
+  if (tid < a.nb * 6) {
+    const int b = tid / 6, c = tid % 6;
+    a.ftp[((size_t)blockIdx.x * a.max_bodies + b) * 6 + c] = ((wacc[0][b][c] + wacc[1][b][c]) + wacc[2][b][c]) + wacc[3][b][c];
+  }
 }
 
 }  // namespace psm
