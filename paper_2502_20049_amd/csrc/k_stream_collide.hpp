@@ -991,8 +991,9 @@ __global__ __launch_bounds__(256) void k_obstacle(const SCArgs a) {
 // boxes in a fixed order; a workgroup first lists the group's cells with
 // B != 0 in LDS (ascending order), then updates the list 256 cells at a time,
 // so thin or sparse solids still fill whole waves.  Per-body FP64 sums are
-// kept in LDS (deterministic) and written once per workgroup.  A cell inside
-// several boxes is taken by the lowest-index box.
+// kept per wave in LDS, added across the waves once and written once per
+// workgroup (fixed order: deterministic).  A cell inside several boxes is
+// taken by the lowest-index box.
 // ---------------------------------------------------------------------------
 template <int Q, typename T, int PAR, int SC, int CM = 0>
 __global__ __launch_bounds__(256) void k_solid(const SCArgs a) {
