@@ -180,11 +180,12 @@ def test_cumulant_fast_path_bitwise_equals_general_path(sim, gc, storage):
     assert torch.equal(res[0], res[1])
 
 
-@pytest.mark.parametrize("case", ["two_bodies_mixed", "channel_96", "plain_static"])
+@pytest.mark.parametrize("case", ["two_bodies_mixed", "channel_96", "channel_192", "plain_static"])
 def test_psm_step_equals_separate_calls(sim, gc, case):
     """psm_step against geometry_map_step + psm_stream_collide +
     body_force_torque called one by one: bit-identical PDFs, fractions and
-    F/T."""
+    F/T (channel_192: more solid workgroups than the 256 threads of the F/T
+    sum)."""
     import torch
 
     _say(f"[psm_step] {case}")
@@ -193,6 +194,8 @@ def test_psm_step_equals_separate_calls(sim, gc, case):
     elif case == "channel_96":
         wl, steps = pi.workload_ellipsoid_channel(n=96, storage="f32", steps=8, scale=0.4, s=2), 8
         wl.bodies[0].motion.omega = 0.02
+    elif case == "channel_192":
+        wl, steps = pi.workload_ellipsoid_channel(n=192, storage="f32", steps=4, s=3), 4
     else:
         wl, steps = pi.workload_sphere32(storage="f32"), 4
     res = []
