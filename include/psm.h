@@ -364,8 +364,13 @@ int psm_error_flags(psm_field *f, int32_t *out_dev, void *stream);
  *                             (s = 3 bodies) that geometry_map_step samples in
  *                             a second kernel (one wave per cell); cells beyond it,
  *                             and every cell with 0, are sampled in the
- *                             classification kernel.  Results are identical. */
-enum { PSM_OPT_GENERAL_PATH = 1, PSM_OPT_XCD_REMAP = 2, PSM_OPT_MAP_LIST = 4 };
+ *                             classification kernel.  Results are identical.
+ *   PSM_OPT_SOLID_GRID [2048] most workgroups of the solid-cell kernel (1 ..
+ *                             2048, 0 = default); fewer make each workgroup walk
+ *                             more groups of chunks.  PDFs are identical; the
+ *                             F/T partials are grouped differently (FP64
+ *                             rounding only).  Meant for tests. */
+enum { PSM_OPT_GENERAL_PATH = 1, PSM_OPT_XCD_REMAP = 2, PSM_OPT_MAP_LIST = 4, PSM_OPT_SOLID_GRID = 8 };
 int psm_set_option(psm_field *f, int option, int value);
 /* Device-to-device copy kernel (measured-bandwidth probe); 16-byte aligned
  * src and dst. */

@@ -18,7 +18,7 @@ PSM_PERIODIC, PSM_WALL, PSM_INLET, PSM_OUTLET = 0, 1, 2, 3
 PSM_BUF_PDF, PSM_BUF_B, PSM_BUF_WORK, PSM_BUF_ADJOINT, PSM_BUF_GRAD_B, PSM_BUF_OBSTACLE = 0, 1, 2, 3, 4, 5
 PSM_SHAPE_ELLIPSOID, PSM_SHAPE_CUBE = 0, 1
 PSM_COLL_TRT, PSM_COLL_CUMULANT = 0, 1
-PSM_OPT_GENERAL_PATH, PSM_OPT_XCD_REMAP = 1, 2
+PSM_OPT_GENERAL_PATH, PSM_OPT_XCD_REMAP, PSM_OPT_MAP_LIST, PSM_OPT_SOLID_GRID = 1, 2, 4, 8
 PSM_MAX_BODIES = 8
 
 # every symbol include/psm.h declares

@@ -989,19 +989,24 @@ __global__ __launch_bounds__(256) void k_obstacle(const SCArgs a) {
 // handling, and the force / torque of eqs. (10)-(11) on each body.  A fixed
 // grid of workgroups walks groups of a.cpw consecutive 256-cell chunks of the
 // boxes in a fixed order; a workgroup first lists the group's cells with
-// B != 0 in LDS (ascending order), then updates the list 256 cells at a time,
-// so thin or sparse solids still fill whole waves.  Per-body FP64 sums are
+// B != 0 in LDS (ascending order), then updates the list in whole rounds of
+// 256 cells (a short remainder waits for the workgroup's next group), so thin
+// or sparse solids still fill whole waves.  NS: fraction slots of the field
+// (the two-body blend exists only in the NS = 2 instantiation: one slot needs
+// fewer registers, 3 waves per SIMD instead of 2 for D3Q19 FP32).  Per-body FP64 sums are
 // kept per wave in LDS, added across the waves once and written once per
 // workgroup (fixed order: deterministic).  A cell inside several boxes is
 // taken by the lowest-index box.
 // ---------------------------------------------------------------------------
-template <int Q, typename T, int PAR, int SC, int CM = 0>
+template <int Q, typename T, int PAR, int SC, int CM, int NS>
 __global__ __launch_bounds__(256) void k_solid(const SCArgs a) {
   using R = typename Comp<T>::type;
   __shared__ double wacc[4][PSM_MAX_BODIES][6];  // per-wave F/T sums (each wave writes only its own)
-  __shared__ uint32_t cells_l[SOLID_MAX_CPW * 256];
-  __shared__ R bfrac_l[SOLID_MAX_CPW * 256];
-  __shared__ uint8_t meta_l[SOLID_MAX_CPW * 256];
+  // listed cells: fewer than 256 left over from earlier groups, then this group's
+  constexpr int LCAP = SOLID_MAX_CPW * 256 + 256;
+  __shared__ uint32_t cells_l[LCAP];
+  __shared__ R bfrac_l[LCAP];
+  __shared__ uint8_t meta_l[LCAP];
   __shared__ uint32_t wcnt[SOLID_MAX_CPW][4];
   const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
   if (tid < 4 * PSM_MAX_BODIES * 6) (&wacc[0][0][0])[tid] = 0.0;
@@ -1009,9 +1014,10 @@ __global__ __launch_bounds__(256) void k_solid(const SCArgs a) {
   const uint32_t cpw = (uint32_t)a.cpw;
   const uint32_t ngroups = (a.nchunks + cpw - 1) / cpw;
   const uint32_t nx = (uint32_t)a.nx, nxy = nx * (uint32_t)a.ny;
+  uint32_t pending = 0;  // listed cells not yet updated (wave-uniform)
   for (uint32_t grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {
-    // 1. the group's cells with B != 0, listed in ascending (chunk, thread)
-    //    order with their slot-0 fraction and body ids
+    // 1. the group's cells with B != 0, appended to the list in ascending
+    //    (chunk, thread) order with their slot-0 fraction and body ids
     uint32_t mine[SOLID_MAX_CPW];
     R bmine[SOLID_MAX_CPW];
     uint8_t mmine[SOLID_MAX_CPW];
@@ -1049,7 +1055,7 @@ __global__ __launch_bounds__(256) void k_solid(const SCArgs a) {
       if (lane == 0) wcnt[j][wid] = (uint32_t)__popcll(bm);
     }
     __syncthreads();
-    uint32_t total = 0;
+    uint32_t total = pending;
 #pragma unroll
     for (int j = 0; j < SOLID_MAX_CPW; ++j) {
       const unsigned long long bm = __ballot(hit[j]);
@@ -1064,10 +1070,14 @@ __global__ __launch_bounds__(256) void k_solid(const SCArgs a) {
       total += (wcnt[j][0] + wcnt[j][1]) + (wcnt[j][2] + wcnt[j][3]);
     }
     __syncthreads();
-    // 2. the listed cells, 256 at a time
-    for (uint32_t base = 0; base < total; base += 256) {
+    // 2. the listed cells in whole rounds of 256 (the workgroup's last group:
+    //    all of them); a short remainder waits for the next group, so that
+    //    sparse boxes still fill the waves
+    const bool last_grp = grp + gridDim.x >= ngroups;
+    const uint32_t nproc = last_grp ? total : (total & ~255u);
+    for (uint32_t base = 0; base < nproc; base += 256) {
       const uint32_t li = base + (uint32_t)tid;
-      bool act = li < total;
+      bool act = li < nproc;
       const uint32_t n = act ? cells_l[li] : 0u;
       const int z = (int)(n / nxy), y = (int)((n - (uint32_t)z * nxy) / nx),
                 x = (int)(n - (uint32_t)z * nxy - (uint32_t)y * nx);
@@ -1079,7 +1089,7 @@ __global__ __launch_bounds__(256) void k_solid(const SCArgs a) {
         const uint8_t m = meta_l[li];
         b0 = m & 15;
         if (b0 >= a.nb) b0 = 0;  // ids come from the mapping; never index past the body table
-        if (a.slots == 2 && (m >> 4)) {
+        if (NS == 2 && (m >> 4)) {
           b1 = (m >> 4) - 1;
           if (b1 >= a.nb) b1 = 0;
           B1 = (R)a.B1[n];
@@ -1125,7 +1135,7 @@ __global__ __launch_bounds__(256) void k_solid(const SCArgs a) {
             }
           }
         }
-        if (__any(two)) {
+        if (NS == 2 && __any(two)) {
           collide<Q, SC, 2, R, CM>(f, a, B0, us0, B1, us1, mom0, mom1);
         } else {
           collide<Q, SC, 1, R, CM>(f, a, B0, us0, B1, us1, mom0, mom1);
@@ -1176,7 +1186,27 @@ __global__ __launch_bounds__(256) void k_solid(const SCArgs a) {
         }
       }
     }
-    __syncthreads();  // the list is rebuilt for the next group
+    // the remainder (fewer than 256, none after the last group) moves to the
+    // front; the next group appends after it
+    pending = total - nproc;
+    __syncthreads();
+    if (pending && nproc) {
+      uint32_t c = 0;
+      R bv = R(0);
+      uint8_t mv = 0;
+      if ((uint32_t)tid < pending) {
+        c = cells_l[nproc + tid];
+        bv = bfrac_l[nproc + tid];
+        mv = meta_l[nproc + tid];
+      }
+      __syncthreads();
+      if ((uint32_t)tid < pending) {
+        cells_l[tid] = c;
+        bfrac_l[tid] = bv;
+        meta_l[tid] = mv;
+      }
+      __syncthreads();
+    }
   }
   __syncthreads();
   if (tid < a.nb * 6) {

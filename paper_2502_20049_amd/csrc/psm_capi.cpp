@@ -151,6 +151,7 @@ SCArgs make_sc_args(const psm_field &f) {
   a.slots = c.slots;
   a.dB = f.opt_whole_domain ? f.dB : nullptr;
   a.cpw = 1;
+  a.solid_grid = f.opt_solid_grid;
   a.ocls = f.ocls;
   a.olist = f.olist;
   a.ocount = f.ocount;
@@ -316,6 +317,7 @@ int pdf_field_create(const psm_config *cfg, void *pdf, size_t pdf_bytes, void *b
   f->ntiles = L.ntiles;
   for (int i = 0; i < PSM_MAX_BODIES; ++i) f->active[i] = empty_box();
   f->opt_xcd_remap = 0;
+  f->opt_solid_grid = SOLID_BLOCKS;
   f->map_list_cap = cfg->psm ? (int)MAP_LIST_CAP : 0;
   if (hipGetDevice(&f->device) != hipSuccess) f->device = -1;
   {
@@ -670,8 +672,8 @@ static int sc_plan(psm_field *f, const psm_body *bodies, int nb, int64_t step, c
   }
   // chunks per workgroup group: enough groups for the fixed grid, at most
   // SOLID_MAX_CPW chunks listed at once
-  a.cpw = (int)std::min<uint32_t>((uint32_t)SOLID_MAX_CPW,
-                                  std::max<uint32_t>(1u, (a.nchunks + SOLID_BLOCKS - 1) / SOLID_BLOCKS));
+  const uint32_t grid = (uint32_t)a.solid_grid;
+  a.cpw = (int)std::min<uint32_t>((uint32_t)SOLID_MAX_CPW, std::max<uint32_t>(1u, (a.nchunks + grid - 1) / grid));
   a.xcd_remap = f->opt_xcd_remap;
   return PSM_OK;
 }
@@ -825,6 +827,10 @@ int psm_set_option(psm_field *f, int option, int value) {
   switch (option) {
     case PSM_OPT_GENERAL_PATH: f->opt_general_path = value ? 1 : 0; return PSM_OK;
     case PSM_OPT_XCD_REMAP: f->opt_xcd_remap = value ? 1 : 0; return PSM_OK;
+    case PSM_OPT_SOLID_GRID:
+      if (value < 0 || value > SOLID_BLOCKS) return set_error("PSM_OPT_SOLID_GRID takes 0 .. 2048"), PSM_EINVAL;
+      f->opt_solid_grid = value ? value : SOLID_BLOCKS;
+      return PSM_OK;
     case PSM_OPT_MAP_LIST:
       if (value < 0 || (uint32_t)value > MAP_LIST_CAP)
         return set_error("PSM_OPT_MAP_LIST takes 0 .. the list capacity"), PSM_EINVAL;

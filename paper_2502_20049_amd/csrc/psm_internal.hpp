@@ -117,6 +117,7 @@ struct SCArgs {
   int max_bodies;
   int slots;
   int xcd_remap;  // PSM_OPT_XCD_REMAP: contiguous tile ranges per XCD
+  int solid_grid;  // most workgroups of the solid kernel (PSM_OPT_SOLID_GRID), 1..SOLID_BLOCKS
   int nbox;       // boxes outside which every B is zero (one per body)
   IBox box[PSM_MAX_BODIES];
   uint32_t cprefix[PSM_MAX_BODIES + 1];  // 256-cell chunk offsets of the boxes
@@ -220,6 +221,7 @@ struct psm_field {
   int device;
   int opt_general_path;
   int opt_xcd_remap;
+  int opt_solid_grid;
   int opt_whole_domain;  // B may be nonzero anywhere (offset field set)
   const float *dB;       // caller-owned offset added to the slot-0 fraction
   // static obstacle (plain-LBM fields; null: none)

@@ -63,13 +63,15 @@ def _workload(q, storage, bc, sc=1, two=False, s=2, force=(0, 0, 0), nx=70, ny=2
                        (0.04, 0.01, -0.02), sc, b_form, 2 if two else 1, 2, bodies)
 
 
-def _two_step_compare(orc, sim, gc, wl, seed=5, general=False):
+def _two_step_compare(orc, sim, gc, wl, seed=5, general=False, solid_grid=0):
     import torch
 
     torch.manual_seed(0)
     f = sim.Field(wl)
     if general:
         f.set_option(1, 1)
+    if solid_grid:
+        f.set_option(8, solid_grid)  # PSM_OPT_SOLID_GRID
     gc.load_random_state(f, seed)
     run = orc.Run(wl, f0=gc.oracle_state(orc, wl, seed))
     out = {}
@@ -110,6 +112,50 @@ def test_two_steps_parity(orc, sim, gc, q, storage, bc):
     _say(f"[two_steps] q={q} storage={storage} bc={bc}")
     wl = _workload(q, storage, bc)
     _two_step_compare(orc, sim, gc, wl)
+
+
+@pytest.mark.parametrize("grid", [1, 2])
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("q", [19, 27])
+def test_solid_kernel_few_workgroups(orc, sim, gc, q, storage, grid):
+    """The solid kernel capped at 1 or 2 workgroups (PSM_OPT_SOLID_GRID), two
+    overlapping bodies: each workgroup walks several groups of chunks and
+    carries the cells short of a whole round of 256 over to the next group.
+    PDFs, B and F/T against the oracle."""
+    _say(f"[solid_grid] q={q} {storage} grid={grid}")
+    wl = _workload(q, storage, "mixed", two=True, force=(1e-5, 0.0, 0.0))
+    _two_step_compare(orc, sim, gc, wl, solid_grid=grid)
+
+
+def test_solid_grid_option_pdfs_bitwise(sim, gc):
+    """The 192^3 channel (a few hundred chunks of 256 cells): the solid kernel
+    capped at 3 workgroups gives the same PDF bits as the default grid, and
+    F/T equal to FP64 rounding of the other grouping; out-of-range values are
+    refused."""
+    import ctypes as C
+
+    import torch
+    from paper_2502_20049_amd import _capi as capi
+
+    wl = pi.workload_ellipsoid_channel(n=192, storage="f32", steps=4, s=3)
+    res = []
+    for grid in (0, 3):
+        f = sim.Field(wl)
+        f.set_option(8, grid)
+        gc.load_random_state(f, 2)
+        fts = []
+        for t in range(4):
+            ft = torch.zeros((1, 6), dtype=torch.float64, device="cuda")
+            f.step(t, ft=ft)
+            fts.append(ft)
+        torch.cuda.synchronize()
+        res.append((f.pdf_view().clone(), torch.stack(fts)))
+    assert torch.equal(res[0][0], res[1][0])
+    d = (res[0][1] - res[1][1]).abs().max().item() / res[0][1].abs().max().item()
+    _say(f"[solid_grid 192] F/T rel diff {d:.1e}")
+    assert d < 1e-12
+    for bad in (-1, 2049):
+        assert capi.lib.psm_set_option(f.handle, 8, bad) == capi.PSM_EINVAL
 
 
 @pytest.mark.parametrize("sc", [1, 2, 3])
