@@ -101,9 +101,10 @@ class Geometry:
         self.dims = tuple(dims)
         self.s = s
 
-    def __del__(self):
+    def __del__(self, _lib=lib):
+        # _lib bound at definition: module globals may already be gone at exit
         if getattr(self, "handle", None) and self.handle.value:
-            lib.geometry_field_destroy(self.handle)
+            _lib.geometry_field_destroy(self.handle)
             self.handle = C.c_void_p()
 
 
@@ -247,9 +248,9 @@ class Field:
         check(lib.psm_error_flags(self.handle, C.c_void_p(out.data_ptr()), _stream()), "psm_error_flags")
         return out
 
-    def __del__(self):
+    def __del__(self, _lib=lib):
         if getattr(self, "handle", None) and self.handle.value:
-            lib.pdf_field_destroy(self.handle)
+            _lib.pdf_field_destroy(self.handle)
             self.handle = C.c_void_p()
 
 
