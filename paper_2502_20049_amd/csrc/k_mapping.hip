@@ -203,10 +203,13 @@ __global__ __launch_bounds__(256) void k_map(const MapArgs a) {
   int id[2] = {0, 0};
   int used = 0;
   bool overflow = false;
+  __shared__ uint32_t lcnt[4], lbase;  // list appends: per-wave counts, the workgroup's base
+  const int wid = threadIdx.x >> 6;
   for (int bb = 0; bb < a.nb; ++bb) {
     const MapBodyK &g = a.body[bb];
     const bool inb = active && in_box(g.active, x, y, z);
-    if (!__any(inb)) continue;
+    const bool listing = a.list && g.s == 3;  // workgroup-uniform: every wave reaches its barriers
+    if (!__any(inb) && !listing) continue;
     const int s = g.s;
     const int ns = 1 << (3 * s);
     long long P[3] = {0, 0, 0};
@@ -261,20 +264,25 @@ __global__ __launch_bounds__(256) void k_map(const MapArgs a) {
       // list's capacity, are sampled here.  At s = 2 (64 sub-samples, one
       // per lane) sampling here, several cells per round, is faster.
       bool listed = false;
-      if (a.list && s == 3) {
+      if (listing) {
+        // one counter atomic per workgroup (the counter is shared by every
+        // workgroup of the launch): wave counts, then the workgroup's base
         const bool cand = inb && state == 2 && nin == 1;
         const unsigned long long cm = __ballot(cand);
-        if (cm) {
-          const int leader = __ffsll((long long)cm) - 1;
-          uint32_t base = 0;
-          if (lane == leader) base = atomicAdd(&a.count[bb], (uint32_t)__popcll(cm));
-          base = __shfl(base, leader);
-          const uint32_t pos = base + (uint32_t)__popcll(cm & ((1ull << lane) - 1ull));
-          if (cand && pos < a.cap) {
-            a.list[(size_t)bb * a.cap + pos] = (uint32_t)n;
-            listed = true;
-          }
+        if (lane == 0) lcnt[wid] = (uint32_t)__popcll(cm);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+          const uint32_t t = (lcnt[0] + lcnt[1]) + (lcnt[2] + lcnt[3]);
+          lbase = t ? atomicAdd(&a.count[bb], t) : 0u;
         }
+        __syncthreads();
+        uint32_t pos = lbase + (uint32_t)__popcll(cm & ((1ull << lane) - 1ull));
+        for (int w = 0; w < wid; ++w) pos += lcnt[w];
+        if (cand && pos < a.cap) {
+          a.list[(size_t)bb * a.cap + pos] = (uint32_t)n;
+          listed = true;
+        }
+        __syncthreads();  // lcnt and lbase are reused for the next body
       }
       const unsigned long long sm = __ballot(state == 2 && !listed);
       if (s == 2)

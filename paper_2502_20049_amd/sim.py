@@ -101,11 +101,11 @@ class Geometry:
         self.dims = tuple(dims)
         self.s = s
 
-    def __del__(self, _lib=lib):
-        # _lib bound at definition: module globals may already be gone at exit
+    def __del__(self, _lib=lib, _vp=C.c_void_p):
+        # bound at definition: module globals may already be gone at exit
         if getattr(self, "handle", None) and self.handle.value:
             _lib.geometry_field_destroy(self.handle)
-            self.handle = C.c_void_p()
+            self.handle = _vp()
 
 
 class Field:
@@ -248,10 +248,10 @@ class Field:
         check(lib.psm_error_flags(self.handle, C.c_void_p(out.data_ptr()), _stream()), "psm_error_flags")
         return out
 
-    def __del__(self, _lib=lib):
+    def __del__(self, _lib=lib, _vp=C.c_void_p):
         if getattr(self, "handle", None) and self.handle.value:
             _lib.pdf_field_destroy(self.handle)
-            self.handle = C.c_void_p()
+            self.handle = _vp()
 
 
 def rigid_states(rigids, average=True):
