@@ -313,7 +313,8 @@ __global__ __launch_bounds__(256) void k_map(const MapArgs a) {
   }
 }
 
-// Listed surface cells (s = 3): one wave per cell, 8 sub-samples per lane, B
+// Listed surface cells (s = 3): a wave samples three cells per round, 8
+// sub-samples of each per lane (all gathers issued before the ballots), B
 // and the body id written for cells with a nonzero count (the classification
 // kernel already wrote zeros).  Also clears the counters the
 // next mapping call appends to.
@@ -323,20 +324,28 @@ __global__ __launch_bounds__(256) void k_map_sample(const MapArgs a) {
   if (blockIdx.x == 0 && threadIdx.x == 0) a.count_next[bb] = 0u;
   if (G.s != 3) return;
   const uint32_t total = min(a.count[bb], a.cap);
-  if (blockIdx.x * 4u >= total) return;  // whole workgroup idle
+  constexpr int NCS = 3;  // cells per wave and round: their gathers are in flight together
+  if (blockIdx.x * 4u * NCS >= total) return;  // whole workgroup idle
   __shared__ long long tab[3][512];
   fill_table(G, tab);
   const int lane = threadIdx.x & 63;
   const int ns = 1 << (3 * G.s);
-  for (uint32_t e = blockIdx.x * 4u + (threadIdx.x >> 6); e < total; e += gridDim.x * 4u) {
-    const uint32_t n = a.list[(size_t)bb * a.cap + e];
-    const int x = (int)(n % (uint32_t)a.nx);
-    const int y = (int)((n / (uint32_t)a.nx) % (uint32_t)a.ny);
-    const int z = (int)(n / ((uint32_t)a.nx * (uint32_t)a.ny));
-    long long P[3];
-    body_point(G, x, y, z, P);
-    const int c = sample_cells<8, 1>(G, true, tab, 1ull, P, lane, 0);
-    if (lane == 0 && c > 0) {
+  const uint32_t stride = gridDim.x * 4u * NCS;
+  for (uint32_t e0 = (blockIdx.x * 4u + (threadIdx.x >> 6)) * NCS; e0 < total; e0 += stride) {
+    // lanes 0 .. NCS-1 hold the entries e0 .. e0+NCS-1
+    const uint32_t e = e0 + (uint32_t)lane;
+    const bool mine = lane < NCS && e < total;
+    uint32_t n = 0;
+    long long P[3] = {0, 0, 0};
+    if (mine) {
+      n = a.list[(size_t)bb * a.cap + e];
+      const int x = (int)(n % (uint32_t)a.nx);
+      const int y = (int)((n / (uint32_t)a.nx) % (uint32_t)a.ny);
+      const int z = (int)(n / ((uint32_t)a.nx * (uint32_t)a.ny));
+      body_point(G, x, y, z, P);
+    }
+    const int c = sample_cells<8, NCS>(G, true, tab, __ballot(mine), P, lane, 0);
+    if (mine && c > 0) {
       a.B0[n] = fraction_of(a, c, ns);
       a.meta[n] = (uint8_t)(bb & 15);
     }
