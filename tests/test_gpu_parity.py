@@ -338,6 +338,28 @@ def test_bodies_outside_or_across_the_domain(orc, sim, gc):
     _two_step_compare(orc, sim, gc, wl)
 
 
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_eight_bodies(orc, sim, gc, storage):
+    """The most bodies a field takes (8): spheres, ellipsoids and cubes,
+    moving and spinning, two pairs overlapping (two slots), one body partly
+    outside the lattice, SC2 with a body force; B per body bit for bit, F/T of
+    every body and the PDFs against the oracle over two steps."""
+    _say(f"[eight bodies] {storage}")
+    shapes = [pi.Shape("ellipsoid", (4.0, 3.0, 2.5)), pi.Shape("ellipsoid", (2.5, 2.5, 2.5)),
+              pi.Shape("cube", (2.6,)), pi.Shape("ellipsoid", (3.5, 2.0, 2.0))]
+    centres = [(8.0, 8.0, 7.0), (12.5, 9.0, 8.0), (24.0, 10.0, 9.0), (36.0, 14.0, 12.0),
+               (47.0, 10.0, 8.5), (49.5, 12.0, 10.0), (60.0, 9.0, 11.0), (70.5, 20.0, 9.0)]
+    bodies = []
+    for i, x0 in enumerate(centres):
+        axis = ((0.0, 0.0, 1.0), (0.6, 0.8, 0.0), (0.0, 1.0, 0.0), (0.48, 0.6, 0.64))[i % 4]
+        bodies.append(pi.Body(shapes[i % 4], pi.Motion(axis=axis, theta0=0.1 * i, omega=0.05 * (i - 3.5),
+                                                         x0=x0, v=(0.02 * (i % 3), -0.01 * (i % 2), 0.0)),
+                              s=1 + (i % 3)))
+    wl = pi.Workload(f"eight_{storage}", 72, 22, 19, 19, storage, 0.8, 3 / 16, (2e-5, 0.0, -1e-5), BCS["mixed"],
+                     (0.04, 0.0, 0.0), 2, 0, 2, 2, bodies)
+    _two_step_compare(orc, sim, gc, wl)
+
+
 def test_xcd_remap_bitwise_identical(sim, gc):
     import torch
 
