@@ -362,7 +362,7 @@ int psm_error_flags(psm_field *f, int32_t *out_dev, void *stream);
  *                             XCDs walks a contiguous range of tiles
  *   PSM_OPT_MAP_LIST  [2^21]  entries per body of the list of surface cells
  *                             (s = 3 bodies) that geometry_map_step samples in
- *                             a second kernel (one wave per cell); cells beyond it,
+ *                             a second kernel (three cells per wave); cells beyond it,
  *                             and every cell with 0, are sampled in the
  *                             classification kernel.  Results are identical.
  *   PSM_OPT_SOLID_GRID [2048] most workgroups of the solid-cell kernel (1 ..

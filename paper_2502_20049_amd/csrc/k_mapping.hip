@@ -260,7 +260,7 @@ __global__ __launch_bounds__(256) void k_map(const MapArgs a) {
       }
     } else {
       // at s = 3 (512 sub-samples) surface cells of a single body go to the
-      // sampling list (one wave per cell there); the rest, and any beyond the
+      // sampling list (three cells per wave and round there); the rest, and any beyond the
       // list's capacity, are sampled here.  At s = 2 (64 sub-samples, one
       // per lane) sampling here, several cells per round, is faster.
       bool listed = false;
