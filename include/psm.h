@@ -241,7 +241,10 @@ int body_force_torque(psm_field *f, int n_bodies, double *ft_dev, void *stream);
  * that order on `stream`.  map_poses may be NULL (= bodies); it differs from
  * bodies only when the velocity used by the solid collision differs from the
  * motion that places the geometry (sensitivity runs).  A plain-LBM field (or
- * n_bodies = 0) takes one psm_stream_collide. */
+ * n_bodies = 0) takes one psm_stream_collide.  With ft_dev the per-body sum is
+ * taken by one extra workgroup of the interior fluid launch (one launch fewer;
+ * same order as body_force_torque, so the same bits); the partials stay
+ * readable by a later body_force_torque. */
 int psm_step(psm_field *f, const psm_body *map_poses, const psm_body *bodies, const psm_geom *const *geoms,
              int n_bodies, int64_t step, double *ft_dev, void *stream);
 

@@ -4,30 +4,11 @@
 
 namespace psm {
 
-__device__ __forceinline__ double block_sum256(double v, double *sh) {
-  v = wave_sum(v);
-  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  __syncthreads();
-  if (lane == 0) sh[wid] = v;
-  __syncthreads();
-  return ((sh[0] + sh[1]) + sh[2]) + sh[3];
-}
-
-// One workgroup per body: the solid-kernel partials of the last step in
-// increasing workgroup order (thread t takes every 256th), then a fixed tree.
+// One workgroup per body (the same sum also runs as an extra workgroup of the
+// interior fluid launch when a whole step is one call).
 __global__ __launch_bounds__(256) void k_ft_reduce(const double *ftp, int max_bodies, int nblocks, double *ft) {
-  const int b = blockIdx.x;
-  double acc[6] = {0, 0, 0, 0, 0, 0};
-  for (int i = threadIdx.x; i < nblocks; i += 256) {
-    const double *p = ftp + ((size_t)i * max_bodies + b) * 6;
-#pragma unroll
-    for (int c = 0; c < 6; ++c) acc[c] += p[c];
-  }
   __shared__ double sh[4];
-  for (int c = 0; c < 6; ++c) {
-    const double s = block_sum256(acc[c], sh);
-    if (threadIdx.x == 0) ft[b * 6 + c] = s;
-  }
+  ft_body_sum(ftp, max_bodies, nblocks, (int)blockIdx.x, ft, sh);
 }
 
 hipError_t launch_ft_reduce(const psm_field &f, int nb, double *ft, hipStream_t st) {

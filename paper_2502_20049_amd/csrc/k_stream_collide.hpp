@@ -368,6 +368,43 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// Sum over a 256-thread workgroup: fixed lane tree per wave, then the four
+// waves in order (every thread gets the result).
+__device__ __forceinline__ double block_sum256(double v, double *sh) {
+  v = wave_sum(v);
+  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __syncthreads();
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  return ((sh[0] + sh[1]) + sh[2]) + sh[3];
+}
+
+// Force/torque of body b from the solid kernel's per-workgroup partials, by
+// one 256-thread workgroup: partials in increasing workgroup order (thread t
+// takes every 256th), then the fixed tree above (deterministic).
+__device__ __forceinline__ void ft_body_sum(const double *ftp, int max_bodies, int nblocks, int b, double *ft,
+                                            double *sh) {
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  for (int i = threadIdx.x; i < nblocks; i += 256) {
+    const double *p = ftp + ((size_t)i * max_bodies + b) * 6;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) acc[c] += p[c];
+  }
+  for (int c = 0; c < 6; ++c) {
+    const double s = block_sum256(acc[c], sh);
+    if (threadIdx.x == 0) ft[b * 6 + c] = s;
+  }
+}
+
+// The extra last workgroup of an interior launch that also sums the F/T (the
+// solid kernel, an earlier launch, has finished writing the partials).
+__device__ __forceinline__ bool ft_extra_block(const SCArgs &a) {
+  if (a.ft_out == nullptr || blockIdx.x != a.ft_block) return false;
+  __shared__ double sh[4];
+  for (int b = 0; b < a.ft_nb; ++b) ft_body_sum(a.ftp, a.max_bodies, a.ft_nblocks, b, a.ft_out, sh);
+  return true;
+}
+
 // Inlet term 6 w_k (c_k . u_in) of the velocity-inlet rule.  Not contracted
 // into the add that applies it, so every kernel (whatever its code shape)
 // rounds the face rule the same way.
@@ -868,6 +905,7 @@ __device__ __forceinline__ void fluid_seg_h2(const SCArgs &a, int x0, int y, int
 // (fluid_seg_h2).  Other row lengths take k_fluid.
 template <int Q, bool PSM, int CM = 0>
 __global__ __launch_bounds__(256) void k_fluid_h2odd(const SCArgs a) {
+  if (ft_extra_block(a)) return;
   const int nsx = a.nx / 128;
   const uint32_t seg = blockIdx.x * 4u + (threadIdx.x >> 6);
   const uint32_t nseg = (uint32_t)nsx * (uint32_t)(a.ny - 2) * (uint32_t)(a.nz - 2);
@@ -885,6 +923,7 @@ __global__ __launch_bounds__(256) void k_fluid_h2odd(const SCArgs a) {
 template <int Q, typename T, int PAR, bool PSM, int CM = 0>
 __global__ __launch_bounds__(256) void k_fluid(const SCArgs a) {
   using R = typename Comp<T>::type;
+  if (ft_extra_block(a)) return;
   const int tid = threadIdx.x;
   if constexpr (PAR == 0 && Q == 19) {
     // even D3Q19 steps: the rows on the y/z faces ride along as extra blocks

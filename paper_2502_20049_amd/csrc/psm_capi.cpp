@@ -22,9 +22,9 @@ int hip_fail(hipError_t e, const char *what) {
 }
 
 hipError_t launch_adjoint(const psm_field &f, const AdjArgs &A, hipStream_t st);
-hipError_t launch_sc_f64(const psm_config &, const SCArgs &, int, hipStream_t, int *);
-hipError_t launch_sc_f32(const psm_config &, const SCArgs &, int, hipStream_t, int *);
-hipError_t launch_sc_f16(const psm_config &, const SCArgs &, int, hipStream_t, int *);
+hipError_t launch_sc_f64(const psm_config &, const SCArgs &, int, hipStream_t, int *, int *);
+hipError_t launch_sc_f32(const psm_config &, const SCArgs &, int, hipStream_t, int *, int *);
+hipError_t launch_sc_f16(const psm_config &, const SCArgs &, int, hipStream_t, int *, int *);
 
 static size_t storage_size(int st) { return st == PSM_F64 ? 8 : (st == PSM_F32 ? 4 : 2); }
 
@@ -152,6 +152,10 @@ SCArgs make_sc_args(const psm_field &f) {
   a.dB = f.opt_whole_domain ? f.dB : nullptr;
   a.cpw = 1;
   a.solid_grid = f.opt_solid_grid;
+  a.ft_out = nullptr;
+  a.ft_nb = 0;
+  a.ft_nblocks = 0;
+  a.ft_block = 0;
   a.ocls = f.ocls;
   a.olist = f.olist;
   a.ocount = f.ocount;
@@ -678,17 +682,20 @@ static int sc_plan(psm_field *f, const psm_body *bodies, int nb, int64_t step, c
   return PSM_OK;
 }
 
-static int sc_launch(psm_field *f, const SCArgs &a, int64_t step, hipStream_t st) {
+// ft_done (may be null): set when the step's launches also summed the F/T
+// into a.ft_out
+static int sc_launch(psm_field *f, const SCArgs &a, int64_t step, hipStream_t st, int *ft_done = nullptr) {
   const int parity = (int)(step & 1);
   hipError_t e;
-  int sb = 0;
+  int sb = 0, fd = 0;
   switch (f->cfg.storage) {
-    case PSM_F64: e = launch_sc_f64(f->cfg, a, parity, st, &sb); break;
-    case PSM_F32: e = launch_sc_f32(f->cfg, a, parity, st, &sb); break;
-    default: e = launch_sc_f16(f->cfg, a, parity, st, &sb); break;
+    case PSM_F64: e = launch_sc_f64(f->cfg, a, parity, st, &sb, &fd); break;
+    case PSM_F32: e = launch_sc_f32(f->cfg, a, parity, st, &sb, &fd); break;
+    default: e = launch_sc_f16(f->cfg, a, parity, st, &sb, &fd); break;
   }
   if (e != hipSuccess) return hip_fail(e, "psm_stream_collide launch");
   f->solid_blocks = sb;
+  if (ft_done) *ft_done = fd;
   return PSM_OK;
 }
 
@@ -702,14 +709,25 @@ int geometry_map_step(psm_field *f, const psm_body *bodies, const psm_geom *cons
   return PSM_OK;
 }
 
-int psm_stream_collide(psm_field *f, const psm_body *bodies, int nb, int64_t step, void *stream) {
+// ft_dev (may be null): the F/T of the step too, summed by an extra workgroup
+// of the interior launch, else by the separate reduction kernel
+static int stream_collide(psm_field *f, const psm_body *bodies, int nb, int64_t step, void *stream,
+                          double *ft_dev) {
   if (!f) return set_error("null handle"), PSM_EINVAL;
   if (f->cfg.psm && nb > 0 && nb != f->nb_mapped)
     return set_error("psm_stream_collide: bodies do not match the mapped field"), PSM_EINVAL;
   SCArgs a;
   int r = sc_plan(f, bodies, nb, step, f->active, a);
   if (r) return r;
-  return sc_launch(f, a, step, (hipStream_t)stream);
+  a.ft_out = (ft_dev && a.nb > 0) ? ft_dev : nullptr;
+  int done = 0;
+  r = sc_launch(f, a, step, (hipStream_t)stream, &done);
+  if (!r && ft_dev && !done) r = body_force_torque(f, nb, ft_dev, stream);
+  return r;
+}
+
+int psm_stream_collide(psm_field *f, const psm_body *bodies, int nb, int64_t step, void *stream) {
+  return stream_collide(f, bodies, nb, step, stream, nullptr);
 }
 
 int psm_step(psm_field *f, const psm_body *map_poses, const psm_body *bodies, const psm_geom *const *geoms, int nb,
@@ -721,8 +739,7 @@ int psm_step(psm_field *f, const psm_body *map_poses, const psm_body *bodies, co
   }
   if (!map_poses) map_poses = bodies;
   int r = geometry_map_step(f, map_poses, geoms, nb, stream);
-  if (!r) r = psm_stream_collide(f, bodies, nb, step, stream);
-  if (!r && ft_dev) r = body_force_torque(f, nb, ft_dev, stream);
+  if (!r) r = stream_collide(f, bodies, nb, step, stream, ft_dev);
   return r;
 }
 

@@ -123,6 +123,11 @@ struct SCArgs {
   uint32_t cprefix[PSM_MAX_BODIES + 1];  // 256-cell chunk offsets of the boxes
   uint32_t nchunks;
   int cpw;  // chunks per group of the solid kernel, 1..SOLID_MAX_CPW
+  // non-null: the interior launch has one extra workgroup (index ft_block)
+  // that sums the F/T of ft_nb bodies from ft_nblocks solid partials into it
+  double *ft_out;
+  int ft_nb, ft_nblocks;
+  uint32_t ft_block;
   BodyK body[PSM_MAX_BODIES];
   // static obstacle of a plain-LBM field (ocls null: none)
   const uint8_t *ocls;    // per cell: 0 bulk fluid, 1 fluid next to the obstacle, 2 obstacle
