@@ -242,7 +242,7 @@ int body_force_torque(psm_field *f, int n_bodies, double *ft_dev, void *stream);
  * bodies only when the velocity used by the solid collision differs from the
  * motion that places the geometry (sensitivity runs).  A plain-LBM field (or
  * n_bodies = 0) takes one psm_stream_collide.  With ft_dev the per-body sum is
- * taken by one extra workgroup of the interior fluid launch (one launch fewer;
+ * taken by one extra workgroup of the step's last fluid launch (one launch fewer;
  * same order as body_force_torque, so the same bits); the partials stay
  * readable by a later body_force_torque. */
 int psm_step(psm_field *f, const psm_body *map_poses, const psm_body *bodies, const psm_geom *const *geoms,

@@ -396,8 +396,11 @@ __device__ __forceinline__ void ft_body_sum(const double *ftp, int max_bodies, i
   }
 }
 
-// The extra last workgroup of an interior launch that also sums the F/T (the
-// solid kernel, an earlier launch, has finished writing the partials).
+// The extra last workgroup of the step's last fluid launch (the face rows, or
+// the interior rows with the face rows as extra blocks on even D3Q19 steps)
+// that also sums the F/T; the solid kernel, an earlier launch, has finished
+// writing the partials.  Those launches need more registers than this, or
+// stay within their occupancy step.
 __device__ __forceinline__ bool ft_extra_block(const SCArgs &a) {
   if (a.ft_out == nullptr || blockIdx.x != a.ft_block) return false;
   __shared__ double sh[4];
@@ -905,7 +908,6 @@ __device__ __forceinline__ void fluid_seg_h2(const SCArgs &a, int x0, int y, int
 // (fluid_seg_h2).  Other row lengths take k_fluid.
 template <int Q, bool PSM, int CM = 0>
 __global__ __launch_bounds__(256) void k_fluid_h2odd(const SCArgs a) {
-  if (ft_extra_block(a)) return;
   const int nsx = a.nx / 128;
   const uint32_t seg = blockIdx.x * 4u + (threadIdx.x >> 6);
   const uint32_t nseg = (uint32_t)nsx * (uint32_t)(a.ny - 2) * (uint32_t)(a.nz - 2);
@@ -923,7 +925,9 @@ __global__ __launch_bounds__(256) void k_fluid_h2odd(const SCArgs a) {
 template <int Q, typename T, int PAR, bool PSM, int CM = 0>
 __global__ __launch_bounds__(256) void k_fluid(const SCArgs a) {
   using R = typename Comp<T>::type;
-  if (ft_extra_block(a)) return;
+  if constexpr (PAR == 0 && Q == 19) {
+    if (ft_extra_block(a)) return;  // the step's last launch here (face rows ride along)
+  }
   const int tid = threadIdx.x;
   if constexpr (PAR == 0 && Q == 19) {
     // even D3Q19 steps: the rows on the y/z faces ride along as extra blocks
@@ -950,6 +954,7 @@ __global__ __launch_bounds__(256) void k_fluid(const SCArgs a) {
 
 template <int Q, typename T, int PAR, bool PSM, int CM = 0>
 __global__ __launch_bounds__(256) void k_fluid_edge(const SCArgs a) {
+  if (ft_extra_block(a)) return;
   edge_block<Q, T, PAR, PSM, CM>(a, blockIdx.x);
 }
 
