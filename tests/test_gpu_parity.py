@@ -226,7 +226,8 @@ def test_cumulant_fast_path_bitwise_equals_general_path(sim, gc, storage):
     assert torch.equal(res[0], res[1])
 
 
-@pytest.mark.parametrize("case", ["two_bodies_mixed", "channel_96", "channel_192", "plain_static"])
+@pytest.mark.parametrize("case", ["two_bodies_mixed", "channel_96", "channel_192", "plain_static", "q27_channel",
+                                  "f16_rows_128", "general_path"])
 def test_psm_step_equals_separate_calls(sim, gc, case):
     """psm_step against geometry_map_step + psm_stream_collide +
     body_force_torque called one by one: bit-identical PDFs, fractions and
@@ -242,11 +243,19 @@ def test_psm_step_equals_separate_calls(sim, gc, case):
         wl.bodies[0].motion.omega = 0.02
     elif case == "channel_192":
         wl, steps = pi.workload_ellipsoid_channel(n=192, storage="f32", steps=4, s=3), 4
+    elif case == "q27_channel":  # face-row launch on both parities
+        wl, steps = _workload(27, "f32", "channel", two=True), 4
+    elif case == "f16_rows_128":  # paired odd-step kernel, then the face rows
+        wl, steps = _workload(19, "f16", "channel", two=True, nx=128, ny=24, nz=20), 4
+    elif case == "general_path":  # no row kernels: the separate reduction
+        wl, steps = _workload(19, "f32", "mixed", two=True), 4
     else:
         wl, steps = pi.workload_sphere32(storage="f32"), 4
     res = []
     for fused in (False, True):
         f = sim.Field(wl, fused=fused, remap_every_step=case != "plain_static")
+        if case == "general_path":
+            f.set_option(1, 1)  # PSM_OPT_GENERAL_PATH
         gc.load_random_state(f, 11)
         fts = []
         for t in range(steps):
