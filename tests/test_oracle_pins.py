@@ -208,6 +208,69 @@ def test_periodic_mass_and_momentum_balance(orc, q, sc):
     assert abs(orc.mass(cfg, f) - m0) / m0 < 1e-13
 
 
+def _angular_momentum(c, f, dims, O):
+    """L = sum_x sum_i (x_c - O) x c_i f_i(x) about the point O (cell centres at
+    index + 1/2, cell n = x + nx (y + ny z))."""
+    nx, ny, nz = dims
+    zz, yy, xx = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    r = np.stack([xx.ravel() + 0.5, yy.ravel() + 0.5, zz.ravel() + 0.5], axis=1) - np.asarray(O)
+    j = f.T @ c  # momentum per cell (N, 3)
+    return np.cross(r, j).sum(axis=0)
+
+
+@pytest.mark.parametrize("q", [19, 27])
+@pytest.mark.parametrize("sc", [1, 2, 3])
+def test_periodic_angular_momentum_balance_pins_torque(orc, q, sc):
+    """Eq. (11): in a periodic box without body force, where the bodies and all
+    non-equilibrium cells stay two cells away from the faces and rest
+    equilibrium fills the rest, one step changes the fluid's angular momentum
+    about any point O by exactly -sum_k (T_k + (X_k - O) x F_k).  Collision
+    hands each body the momentum -dF at x_c; streaming keeps (x - O) x c f
+    (c x c = 0), and the uniform rest populations crossing the periodic wrap
+    are only permuted.  Two bodies with different centres pin the lever arm
+    x_c - X_k and the sign of the cross product."""
+    nx, ny, nz = 12, 11, 10
+    N = nx * ny * nz
+    cfg = _cfg(orc, q, nx=nx, ny=ny, nz=nz, sc=sc)
+    c, w, _ = orc.lattice(q)
+    zz, yy, xx = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    inner = ((xx >= 2) & (xx < nx - 2) & (yy >= 2) & (yy < ny - 2) & (zz >= 2) & (zz < nz - 2)).ravel()
+    core = ((xx >= 3) & (xx < nx - 3) & (yy >= 3) & (yy < ny - 3) & (zz >= 3) & (zz < nz - 3)).ravel()
+    f = np.repeat(w[:, None], N, axis=1)
+    f[:, inner] = _random_state(orc, q, N, 90 + sc)[:, inner]
+    B = np.stack([pi.random_fractions(11 + sc, N) * 0.5, pi.random_fractions(21 + sc, N, stream=5) * 0.5])
+    B[:, ~core] = 0.0
+    poses = [_pose_fixed(orc, np.eye(3), (5.3, 4.6, 5.2), V=(0.01, -0.004, 0.002), W=(0.003, -0.002, 0.005)),
+             _pose_fixed(orc, np.eye(3), (6.9, 5.8, 3.7), V=(-0.006, 0.0, 0.008), W=(-0.004, 0.006, 0.001))]
+    for O in [(0.0, 0.0, 0.0), (4.25, 7.5, 3.0)]:
+        g = f.copy()
+        L0 = _angular_momentum(c, g, (nx, ny, nz), O)
+        ft = orc.step(cfg, g, B, poses)
+        L1 = _angular_momentum(c, g, (nx, ny, nz), O)
+        expect = -sum(ft[k, 3:] + np.cross(np.array(poses[k].X[:]) - O, ft[k, :3]) for k in range(2))
+        assert np.abs(ft[:, 3:]).max() > 1e-3  # the torques are not trivially small
+        assert np.allclose(L1 - L0, expect, rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("q", [19, 27])
+@pytest.mark.parametrize("u_in", [(0.05, 0.0, 0.0), (0.04, 0.012, -0.007)])
+def test_uniform_inflow_is_fixed_point_pins_outlet(orc, q, u_in):
+    """Uniform flow at the inlet velocity (rho = 1) through an inlet (-x) /
+    outlet (+x) channel, periodic in y and z, is an exact fixed point: the
+    inlet's moving-wall rule returns f^eq_k = f^eq_kbar + 2 w_k c_k.u/c_s^2 (the
+    odd part of eq. 3), and the zero-gradient outlet returns the cell's own
+    post-collision f_k.  Bounce-back at the outlet (f*_kbar) would break it."""
+    nx, ny, nz = 7, 4, 3
+    N = nx * ny * nz
+    cfg = _cfg(orc, q, nx=nx, ny=ny, nz=nz, u_in=u_in,
+               bc=("inlet", "outlet", "periodic", "periodic", "periodic", "periodic"))
+    feq = orc.feq(q, 1.0, np.array(u_in))
+    f = np.repeat(feq[:, None], N, axis=1).copy()
+    for _ in range(5):
+        orc.step(cfg, f, None, [])
+    assert np.abs(f - feq[:, None]).max() < 1e-14
+
+
 def test_closed_box_walls_conserve_mass(orc):
     nx, ny, nz = 5, 6, 7
     cfg = _cfg(orc, 19, nx=nx, ny=ny, nz=nz, bc=("wall",) * 6)
@@ -326,34 +389,41 @@ def test_mapping_quarter_turn_is_permutation(orc):
     assert np.array_equal(B1, np.rot90(B0, k=1, axes=(2, 1)))
 
 
-def test_mapping_fixed_point_matches_exact_arithmetic(orc):
+@pytest.mark.parametrize("s_depth,trials,cells", [(1, 6, 5), (2, 4, 4), (3, 2, 2)])
+def test_mapping_fixed_point_matches_exact_arithmetic(orc, s_depth, trials, cells):
     """Fixed-point lookup equals exact rational arithmetic on the same FP64
-    rotation, except for samples within 2^-28 of a lattice plane."""
+    rotation, except for samples within 2^-28 sub-cells of a lattice plane;
+    s = 1, 2 and 3 (the depths the mapping runs at)."""
     from fractions import Fraction as Fr
 
-    g = orc.OracleGeometry(pi.Shape("ellipsoid", (3.0, 2.0, 1.5)), 1)
-    rng = np.random.default_rng(5)
-    mism = 0
-    for trial in range(6):
+    n = 2 ** s_depth
+    g = orc.OracleGeometry(pi.Shape("ellipsoid", (3.0, 2.0, 1.5)), s_depth)
+    rng = np.random.default_rng(5 + s_depth)
+    all_cells = [(5, 5, 5), (6, 4, 5), (3, 5, 6), (7, 6, 4), (4, 4, 4)]
+    mism = checked = 0
+    for trial in range(trials):
         ax = rng.normal(size=3)
         ax /= np.linalg.norm(ax)
         m = pi.Motion(axis=tuple(ax), omega=float(rng.uniform(0, 6)), x0=(5.0, 5.0, 5.0))
         pose = orc.pose_at(m, 1)
         R = np.array(pose.R[:]).reshape(3, 3)
         Rf = [[Fr(float(R[i, j])) for j in range(3)] for i in range(3)]
-        for (x, y, z) in [(5, 5, 5), (6, 4, 5), (3, 5, 6), (7, 6, 4), (4, 4, 4)]:
-            cnt, near = 0, False
-            for kx, ky, kz in itertools.product(range(2), repeat=3):
-                q = [Fr(x) + Fr(2 * kx + 1, 4) - 5, Fr(y) + Fr(2 * ky + 1, 4) - 5, Fr(z) + Fr(2 * kz + 1, 4) - 5]
-                p = [sum(Rf[j][a] * q[j] for j in range(3)) * 2 for a in range(3)]  # sub-cell units
-                mi = [math.floor(v) for v in p]
+        for (x, y, z) in all_cells[:cells]:
+            pts, near = [], False
+            for kx, ky, kz in itertools.product(range(n), repeat=3):
+                q = [Fr(x) + Fr(2 * kx + 1, 2 * n) - 5, Fr(y) + Fr(2 * ky + 1, 2 * n) - 5,
+                     Fr(z) + Fr(2 * kz + 1, 2 * n) - 5]
+                p = [sum(Rf[j][a] * q[j] for j in range(3)) * n for a in range(3)]  # sub-cell units
+                pts.append([math.floor(v) for v in p])
                 if any(abs(v - round(v)) < Fr(1, 2 ** 28) for v in p):
                     near = True
-                cnt += bool(g.inside([mi])[0])
-            if cnt / 8 != orc.map_cell(g, pose, x, y, z):
+            cnt = int(g.inside(pts).sum())
+            checked += 0 < cnt < n ** 3
+            if Fr(cnt, n ** 3) != Fr(orc.map_cell(g, pose, x, y, z)):
                 assert near
                 mism += 1
     assert mism == 0
+    assert checked >= 1  # at least one cell cuts the surface
 
 
 def test_b_tau_weighted_form(orc):
@@ -741,6 +811,70 @@ def test_cumulant_shear_wave_viscosity(orc):
     nu = (tau - 0.5) / 3
     k = 2 * np.pi / L
     assert abs(rate / (nu * k * k) - 1) < 0.01
+
+
+def test_cumulant_post_collision_central_moments(orc):
+    """Second- and third-order central moments of the collision's output, from
+    their definition C_abc = sum_i f_i (c_x - u_x)^a (c_y - u_y)^b (c_z - u_z)^c
+    (u conserved): the trace relaxes to rho (3 c_s^2 rho, bulk rate one), the
+    deviators C_xx - C_yy, C_xx - C_zz and the off-diagonal C_xy, C_xz, C_yz keep
+    (1 - 1/tau) of their value, and the third-order ones with exponents <= 2 per
+    axis (third-order cumulants, rate one) vanish.  At tau != 1, so a wrong
+    deviator or bulk rate shows."""
+    tau = 0.66
+    om = 1 / tau
+    cfg = _cum_cfg(orc, tau=tau)
+    c, w, _ = orc.lattice(27)
+
+    def central(f, u, e):
+        d = c - u
+        return float(np.sum(f * d[:, 0] ** e[0] * d[:, 1] ** e[1] * d[:, 2] ** e[2]))
+
+    for seed in range(5):
+        f = _rand_f(27, w, 120 + seed, amp=3.0)
+        g = _cum_collide(orc, cfg, f)
+        rho = f.sum()
+        u = (f @ c) / rho
+        assert np.abs((g @ c) / g.sum() - u).max() < 1e-15
+        Cf = {e: central(f, u, e) for e in itertools.product(range(3), repeat=3) if sum(e) == 2}
+        Cg = {e: central(g, u, e) for e in Cf}
+        xx, yy, zz = (2, 0, 0), (0, 2, 0), (0, 0, 2)
+        assert abs(Cg[xx] + Cg[yy] + Cg[zz] - rho) < 1e-14
+        assert abs(Cf[xx] + Cf[yy] + Cf[zz] - rho) > 1e-3  # the input is off the trace equilibrium
+        for a, b in [(xx, yy), (xx, zz)]:
+            assert abs((Cg[a] - Cg[b]) - (1 - om) * (Cf[a] - Cf[b])) < 1e-14
+            assert abs(Cf[a] - Cf[b]) > 1e-3
+        for e in [(1, 1, 0), (1, 0, 1), (0, 1, 1)]:
+            assert abs(Cg[e] - (1 - om) * Cf[e]) < 1e-14
+            assert abs(Cf[e]) > 1e-4
+        for e in itertools.product(range(3), repeat=3):
+            if sum(e) == 3:
+                assert abs(central(g, u, e)) < 1e-14
+                assert abs(central(f, u, e)) > 1e-6 or e == (1, 1, 1)
+
+
+def test_cumulant_diagonal_shear_wave_viscosity(orc):
+    """A shear wave along the face diagonal, u = U sin(k.x) (1, -1, 0)/sqrt 2
+    with k = 2 pi (1, 1, 0)/L (periodic, D3Q27): its strain is purely diagonal
+    in the lattice frame (S_xx = -S_yy, S_xy = 0), so the decay rate nu |k|^2,
+    nu = c_s^2 (tau - 1/2), is set by the deviator rate, which the axis-aligned
+    wave never sees; 1% on the rate."""
+    L, tau, U = 24, 0.8, 1e-3
+    cfg = _cum_cfg(orc, tau=tau, nx=L, ny=L, nz=1)
+    yy, xx = np.meshgrid(np.arange(L), np.arange(L), indexing="ij")
+    ph = 2 * np.pi * (xx + yy).ravel() / L
+    amp = U * np.sin(ph) / np.sqrt(2)
+    f = np.stack([orc.feq(27, 1.0, (a, -a, 0.0)) for a in amp], axis=1)
+    amps = {}
+    for t in range(1, 121):
+        orc.step(cfg, f, None, [])
+        if t in (40, 120):
+            _, u = orc.macro(cfg, f)
+            amps[t] = 2 / (L * L) * np.sum((u[:, 0] - u[:, 1]) / np.sqrt(2) * np.sin(ph))
+    rate = np.log(amps[40] / amps[120]) / 80
+    nu = (tau - 0.5) / 3
+    k2 = 2 * (2 * np.pi / L) ** 2
+    assert abs(rate / (nu * k2) - 1) < 0.01
 
 
 def test_cumulant_refuses_force_and_d3q19(orc):
