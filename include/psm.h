@@ -170,6 +170,32 @@ int pdf_field_create(const psm_config *cfg, void *pdf_dev, size_t pdf_bytes, voi
                      psm_field **out);
 int pdf_field_destroy(psm_field *f);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * pdf_field_create without the work buffer.  The field's work area (error
+ * flags, mapping counters, force/torque partials, reduction scratch and the
+ * mapping's surface-cell lists) is instead a static device array of the
+ * library, PSM_STATIC_WORK_BYTES (16 MiB), of which each GPU the library runs
+ * on holds one copy until the process ends.  The caller still passes the PDF
+ * and B buffers (sizes and alignment as for pdf_field_create).  This call and
+ * every later call on the field allocate nothing (no hipMalloc / hipFree).
+ * Results are bitwise those of a field made by pdf_field_create: the
+ * surface-cell lists are cut to what fits (PSM_OPT_MAP_LIST's upper limit
+ * shrinks accordingly), and cells beyond a list are sampled by the
+ * classification kernel, which gives the same fractions.
+ * Sharing: all such fields on one GPU share its array.  Creating one (or
+ * psm_field_reset of one) claims the array and clears its flags and counters
+ * on `stream`; calls on an earlier such field of that GPU then fail with
+ * PSM_EINVAL until it is reset.  Calls on the owning field that overlap in
+ * time (several host threads, or several streams) race on the array.
+ * Errors: as pdf_field_create; PSM_ESIZE when the lattice and max_bodies need
+ * more than PSM_STATIC_WORK_BYTES before any list entry (the reduction scratch
+ * takes N/32 bytes: about 5e8 cells at most); PSM_EHIP when the array's
+ * device address cannot be looked up. */
+#define PSM_STATIC_WORK_BYTES (16u << 20)
+int pdf_field_create_noalloc(const psm_config *cfg, void *pdf_dev, size_t pdf_bytes, void *b_dev, size_t b_bytes,
+                             void *stream, psm_field **out);
+
 /* Rest equilibrium (delta f = 0, rho = 1, u = 0), B = 0, body ids 0, flags 0. */
 int psm_field_reset(psm_field *f, void *stream);
 

@@ -20,6 +20,7 @@ PSM_SHAPE_ELLIPSOID, PSM_SHAPE_CUBE = 0, 1
 PSM_COLL_TRT, PSM_COLL_CUMULANT = 0, 1
 PSM_OPT_GENERAL_PATH, PSM_OPT_XCD_REMAP, PSM_OPT_MAP_LIST, PSM_OPT_SOLID_GRID = 1, 2, 4, 8
 PSM_MAX_BODIES = 8
+PSM_STATIC_WORK_BYTES = 16 << 20
 
 # every symbol include/psm.h declares
 EXPORTS = [
@@ -29,6 +30,7 @@ EXPORTS = [
     "psm_stream_collide", "body_force_torque", "psm_mass_fp64", "psm_macroscopic", "psm_error_flags",
     "psm_set_option", "psm_stream_copy", "psm_set_fraction_offset", "psm_adjoint_step", "psm_adjoint_omega",
     "psm_step", "lbm_set_obstacle", "psm_rigid_body", "psm_rigid_advance", "psm_coupled_step", "psm_pdf_stride",
+    "pdf_field_create_noalloc",
 ]
 
 
@@ -73,6 +75,7 @@ def _load():
         "psm_lattice": (C.c_int, [C.c_int, i32p, dp, i32p]),
         "psm_body_pose": (C.c_int, [C.POINTER(psm_motion), i64, C.POINTER(psm_body)]),
         "pdf_field_create": (C.c_int, [C.POINTER(psm_config), vp, sz, vp, sz, vp, sz, vp, C.POINTER(vp)]),
+        "pdf_field_create_noalloc": (C.c_int, [C.POINTER(psm_config), vp, sz, vp, sz, vp, C.POINTER(vp)]),
         "pdf_field_destroy": (C.c_int, [vp]),
         "psm_field_reset": (C.c_int, [vp, vp]),
         "psm_geometry_box": (C.c_int, [C.c_int, dp, dp, i64, C.c_int, i32p, i32p, C.POINTER(C.c_size_t)]),

@@ -4,6 +4,8 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -185,6 +187,45 @@ static IBox box_union(const IBox &a, const IBox &b) {
   return r;
 }
 
+// ---- library-owned work area of pdf_field_create_noalloc ---------------------
+// A file-scope device array: every GPU the library runs on holds its own copy
+// until the process ends.  On the host the name is only a stand-in symbol, so
+// host code never passes it to a kernel or copy: each device's address is
+// looked up once (hipGetSymbolAddress, with that device current) and kept.
+static __device__ __align__(256) unsigned char scratch[PSM_STATIC_WORK_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[MAX_DEVICES];
+// the field created (or reset) last on each device with the static work area;
+// only that field may use it
+static std::atomic<const psm_field *> g_scratch_owner[MAX_DEVICES];
+
+static int scratch_address(int dev, void **out) {
+  if (dev < 0 || dev >= MAX_DEVICES) return set_error("device ordinal out of range for the static work area"), PSM_EUNSUP;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "static work area: hipGetSymbolAddress");
+    if (!p) return set_error("static work area: null symbol address"), PSM_EHIP;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return PSM_OK;
+}
+
+// Entry points that touch the work area call this: a field on the static work
+// area must be the one that last claimed it on its device.
+static int work_usable(const psm_field *f) {
+  if (!f->static_work) return PSM_OK;
+  if (f->device < 0 || f->device >= MAX_DEVICES || g_scratch_owner[f->device].load() != f)
+    return set_error("another field has claimed the library's static work area on this device since this field "
+                     "was created or reset (psm_field_reset claims it back)"),
+           PSM_EINVAL;
+  return PSM_OK;
+}
+
 }  // namespace psm
 
 using namespace psm;
@@ -272,19 +313,18 @@ int psm_body_pose(const psm_motion *m, int64_t step, psm_body *out) {
   return PSM_OK;
 }
 
-int pdf_field_create(const psm_config *cfg, void *pdf, size_t pdf_bytes, void *b, size_t b_bytes, void *work,
-                     size_t work_bytes, void *stream, psm_field **out) {
-  int r = check_config(cfg);
-  if (r) return r;
-  if (!out) return set_error("null output handle"), PSM_EINVAL;
-  size_t need_pdf, need_b, need_w;
+// Shared by pdf_field_create and pdf_field_create_noalloc: `work` is the
+// caller's buffer, or the device's static work area with the surface-cell
+// lists cut to `list_cap` entries per body.
+static int field_create(const psm_config *cfg, void *pdf, size_t pdf_bytes, void *b, size_t b_bytes, void *work,
+                        size_t work_bytes, uint32_t list_cap, bool static_work, int device, void *stream,
+                        psm_field **out) {
+  size_t need_pdf, need_b;
   psm_required_bytes(cfg, PSM_BUF_PDF, &need_pdf);
   psm_required_bytes(cfg, PSM_BUF_B, &need_b);
-  psm_required_bytes(cfg, PSM_BUF_WORK, &need_w);
   if (!pdf || !work || (cfg->psm && !b)) return set_error("null device buffer"), PSM_EINVAL;
   if (pdf_bytes < need_pdf) return set_error("pdf buffer too small"), PSM_ESIZE;
   if (b_bytes < need_b) return set_error("B buffer too small"), PSM_ESIZE;
-  if (work_bytes < need_w) return set_error("work buffer too small"), PSM_ESIZE;
   if (((uintptr_t)pdf | (uintptr_t)work | (uintptr_t)b) & 15u)
     return set_error("device buffers must be 16-byte aligned"), PSM_EINVAL;
   psm_field *f = new (std::nothrow) psm_field;
@@ -305,6 +345,7 @@ int pdf_field_create(const psm_config *cfg, void *pdf, size_t pdf_bytes, void *b
   }
   f->work = (char *)work;
   f->work_bytes = work_bytes;
+  f->static_work = static_work;
   f->err = (int32_t *)work;
   f->ftp = (double *)((char *)work + L.off_ftp);
   f->red = (double *)((char *)work + L.off_red);
@@ -322,8 +363,9 @@ int pdf_field_create(const psm_config *cfg, void *pdf, size_t pdf_bytes, void *b
   for (int i = 0; i < PSM_MAX_BODIES; ++i) f->active[i] = empty_box();
   f->opt_xcd_remap = 0;
   f->opt_solid_grid = SOLID_BLOCKS;
-  f->map_list_cap = cfg->psm ? (int)MAP_LIST_CAP : 0;
-  if (hipGetDevice(&f->device) != hipSuccess) f->device = -1;
+  f->map_list_max = cfg->psm ? (int)list_cap : 0;
+  f->map_list_cap = f->map_list_max;
+  f->device = device;
   {
     // error flags and mapping counters start at zero
     hipError_t e = launch_fill_zero(work, 256, (hipStream_t)stream);
@@ -332,12 +374,52 @@ int pdf_field_create(const psm_config *cfg, void *pdf, size_t pdf_bytes, void *b
       return hip_fail(e, "pdf_field_create: clear");
     }
   }
+  if (static_work) g_scratch_owner[device].store(f);
   *out = f;
   return PSM_OK;
 }
 
+int pdf_field_create(const psm_config *cfg, void *pdf, size_t pdf_bytes, void *b, size_t b_bytes, void *work,
+                     size_t work_bytes, void *stream, psm_field **out) {
+  int r = check_config(cfg);
+  if (r) return r;
+  if (!out) return set_error("null output handle"), PSM_EINVAL;
+  size_t need_w;
+  psm_required_bytes(cfg, PSM_BUF_WORK, &need_w);
+  if (work && work_bytes < need_w) return set_error("work buffer too small"), PSM_ESIZE;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) dev = -1;
+  return field_create(cfg, pdf, pdf_bytes, b, b_bytes, work, work_bytes, MAP_LIST_CAP, false, dev, stream, out);
+}
+
+int pdf_field_create_noalloc(const psm_config *cfg, void *pdf, size_t pdf_bytes, void *b, size_t b_bytes,
+                             void *stream, psm_field **out) {
+  int r = check_config(cfg);
+  if (r) return r;
+  if (!out) return set_error("null output handle"), PSM_EINVAL;
+  const Layout L = layout_of(*cfg);
+  if (L.off_list > (size_t)PSM_STATIC_WORK_BYTES)
+    return set_error("pdf_field_create_noalloc: this lattice and body count need " + std::to_string(L.off_list) +
+                     " bytes of work area, more than the static " + std::to_string((size_t)PSM_STATIC_WORK_BYTES)),
+           PSM_ESIZE;
+  const int mb = cfg->psm ? std::max(1, cfg->max_bodies) : 1;
+  const size_t fit = ((size_t)PSM_STATIC_WORK_BYTES - L.off_list) / ((size_t)mb * sizeof(uint32_t));
+  const uint32_t cap = (uint32_t)std::min<size_t>(fit, MAP_LIST_CAP);
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "pdf_field_create_noalloc: hipGetDevice");
+  void *work = nullptr;
+  r = scratch_address(dev, &work);
+  if (r) return r;
+  return field_create(cfg, pdf, pdf_bytes, b, b_bytes, work, PSM_STATIC_WORK_BYTES, cap, true, dev, stream, out);
+}
+
 int pdf_field_destroy(psm_field *f) {
   if (!f) return set_error("null handle"), PSM_EINVAL;
+  if (f->static_work && f->device >= 0 && f->device < MAX_DEVICES) {
+    const psm_field *mine = f;
+    g_scratch_owner[f->device].compare_exchange_strong(mine, nullptr);
+  }
   delete f;
   return PSM_OK;
 }
@@ -354,6 +436,7 @@ int psm_field_reset(psm_field *f, void *stream) {
   }
   if (e == hipSuccess) e = launch_fill_zero(f->work, 256, st);
   if (e != hipSuccess) return hip_fail(e, "psm_field_reset");
+  if (f->static_work) g_scratch_owner[f->device].store(f);
   f->nb_mapped = 0;
   f->map_parity = 0;
   for (int i = 0; i < PSM_MAX_BODIES; ++i) {
@@ -506,6 +589,7 @@ int geometry_field_destroy(psm_geom *g) {
 // ---- per-step path -----------------------------------------------------------
 static int check_bodies(const psm_field *f, const psm_body *bodies, int nb) {
   if (!f) return set_error("null handle"), PSM_EINVAL;
+  if (int r = work_usable(f)) return r;
   if (nb < 0 || nb > f->cfg.max_bodies) return set_error("n_bodies exceeds max_bodies"), PSM_EINVAL;
   if (nb > 0 && !bodies) return set_error("null bodies"), PSM_EINVAL;
   for (int b = 0; b < nb; ++b)
@@ -818,6 +902,7 @@ int psm_coupled_step(psm_field *f, psm_rigid *states, const psm_geom *const *geo
 int body_force_torque(psm_field *f, int nb, double *ft, void *stream) {
   if (!f || !ft) return set_error("null argument"), PSM_EINVAL;
   if (!f->cfg.psm) return set_error("body_force_torque on a plain-LBM field"), PSM_EINVAL;
+  if (int r = work_usable(f)) return r;
   if (nb < 1 || nb > f->nb_mapped) return set_error("n_bodies does not match the mapped bodies"), PSM_EINVAL;
   hipError_t e = launch_ft_reduce(*f, nb, ft, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "body_force_torque launch");
@@ -826,6 +911,7 @@ int body_force_torque(psm_field *f, int nb, double *ft, void *stream) {
 
 int psm_mass_fp64(psm_field *f, int64_t step, double *out, void *stream) {
   if (!f || !out) return set_error("null argument"), PSM_EINVAL;
+  if (int r = work_usable(f)) return r;
   hipError_t e = launch_macro(*f, (int)(step & 1), nullptr, nullptr, f->red, 0, (hipStream_t)stream);
   if (e == hipSuccess) e = launch_mass_final(f->red, f->red_count, out, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "psm_mass_fp64 launch");
@@ -834,6 +920,7 @@ int psm_mass_fp64(psm_field *f, int64_t step, double *out, void *stream) {
 
 int psm_macroscopic(psm_field *f, int64_t step, double *rho, double *u, void *stream) {
   if (!f || !rho || !u) return set_error("null argument"), PSM_EINVAL;
+  if (int r = work_usable(f)) return r;
   hipError_t e = launch_macro(*f, (int)(step & 1), rho, u, f->red, 1, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "psm_macroscopic launch");
   return PSM_OK;
@@ -849,7 +936,7 @@ int psm_set_option(psm_field *f, int option, int value) {
       f->opt_solid_grid = value ? value : SOLID_BLOCKS;
       return PSM_OK;
     case PSM_OPT_MAP_LIST:
-      if (value < 0 || (uint32_t)value > MAP_LIST_CAP)
+      if (value < 0 || value > f->map_list_max)
         return set_error("PSM_OPT_MAP_LIST takes 0 .. the list capacity"), PSM_EINVAL;
       f->map_list_cap = value;
       return PSM_OK;
@@ -925,6 +1012,7 @@ int lbm_set_obstacle(psm_field *f, const uint8_t *solid_dev, void *obst_dev, siz
 int psm_adjoint_step(psm_field *f, const void *fwd, int64_t step, const void *ain, void *aout, void *dJdB,
                      const psm_body *body, const double axis[3], double wt, void *stream) {
   if (!f || !fwd || !ain || !aout || !dJdB || !body || !axis) return set_error("null argument"), PSM_EINVAL;
+  if (int r = work_usable(f)) return r;
   if (step < 0) return set_error("negative step"), PSM_EINVAL;
   if (!f->cfg.psm || f->cfg.sc != 1 || f->cfg.slots != 1 || f->cfg.collision != PSM_COLL_TRT)
     return set_error("psm_adjoint_step supports PSM fields with TRT, SC1 and one body slot"), PSM_EUNSUP;
@@ -955,6 +1043,7 @@ int psm_adjoint_step(psm_field *f, const void *fwd, int64_t step, const void *ai
 
 int psm_adjoint_omega(psm_field *f, double *out, void *stream) {
   if (!f || !out) return set_error("null argument"), PSM_EINVAL;
+  if (int r = work_usable(f)) return r;
   hipError_t e = launch_sum_accumulate(f->red, f->red_count, out, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "psm_adjoint_omega launch");
   return PSM_OK;
@@ -962,6 +1051,7 @@ int psm_adjoint_omega(psm_field *f, double *out, void *stream) {
 
 int psm_error_flags(psm_field *f, int32_t *out, void *stream) {
   if (!f || !out) return set_error("null argument"), PSM_EINVAL;
+  if (int r = work_usable(f)) return r;
   hipError_t e = launch_flags_copy(f->err, out, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "psm_error_flags launch");
   return PSM_OK;

@@ -214,6 +214,8 @@ struct psm_field {
   uint32_t *map_count;  // two sets of per-body counters, used in turn
   int map_parity;
   int map_list_cap;     // entries per body actually used (PSM_OPT_MAP_LIST)
+  int map_list_max;     // entries per body the work area holds
+  bool static_work;     // work area: the library's static array (pdf_field_create_noalloc)
   size_t red_count;
   int64_t N;
   int64_t dstride;  // direction stride of the PDF buffer, elements

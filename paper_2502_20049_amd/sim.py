@@ -112,7 +112,9 @@ class Field:
     """One lattice on the current device; ``wl`` is a psm_inputs.Workload."""
 
     def __init__(self, wl, storage=None, psm=True, slots=None, max_bodies=None, device="cuda", remap_every_step=True,
-                 fused=True):
+                 fused=True, noalloc=False):
+        """``noalloc``: create the handle with pdf_field_create_noalloc (the
+        library's static work area instead of a caller work buffer)."""
         self.wl = wl
         self.storage = storage or wl.storage
         self.cfg = make_config(wl, self.storage, psm, slots, max_bodies)
@@ -127,12 +129,18 @@ class Field:
         wb = required_bytes(self.cfg, capi.PSM_BUF_WORK)
         self.pdf = torch.empty(pb // self.dtype.itemsize, dtype=self.dtype, device=device)
         self.bbuf = torch.empty(max(16, bb), dtype=torch.uint8, device=device) if bb else None
-        self.work = torch.empty(wb, dtype=torch.uint8, device=device)
         self.handle = C.c_void_p()
-        check(lib.pdf_field_create(C.byref(self.cfg), C.c_void_p(self.pdf.data_ptr()), pb,
-                                   C.c_void_p(self.bbuf.data_ptr()) if bb else None, bb,
-                                   C.c_void_p(self.work.data_ptr()), wb, _stream(), C.byref(self.handle)),
-              "pdf_field_create")
+        if noalloc:
+            self.work = None
+            check(lib.pdf_field_create_noalloc(C.byref(self.cfg), C.c_void_p(self.pdf.data_ptr()), pb,
+                                               C.c_void_p(self.bbuf.data_ptr()) if bb else None, bb, _stream(),
+                                               C.byref(self.handle)), "pdf_field_create_noalloc")
+        else:
+            self.work = torch.empty(wb, dtype=torch.uint8, device=device)
+            check(lib.pdf_field_create(C.byref(self.cfg), C.c_void_p(self.pdf.data_ptr()), pb,
+                                       C.c_void_p(self.bbuf.data_ptr()) if bb else None, bb,
+                                       C.c_void_p(self.work.data_ptr()), wb, _stream(), C.byref(self.handle)),
+                  "pdf_field_create")
         self.psm = bool(psm)
         self.bodies = list(wl.bodies) if psm else []
         self.geoms = [Geometry(b.shape, b.s, device) for b in self.bodies]

@@ -71,6 +71,16 @@ def test_required_bytes(capi, sim):
     assert sim.required_bytes(cfg, capi.PSM_BUF_OBSTACLE) == 256 + ((N + 255) // 256) * 256 + 8 * N
 
 
+def test_noalloc_rejects_lattices_beyond_the_static_area(capi, sim):
+    """pdf_field_create_noalloc refuses (PSM_ESIZE, before any device call)
+    a lattice whose fixed part of the work area exceeds the static array."""
+    cfg = _cfg(sim, nx=1024, ny=1024, nz=520)
+    h = C.c_void_p()
+    assert capi.lib.pdf_field_create_noalloc(C.byref(cfg), None, 0, None, 0, None, C.byref(h)) == capi.PSM_ESIZE
+    assert "static" in capi.last_error() and not h.value
+    assert capi.lib.pdf_field_create_noalloc(None, None, 0, None, 0, None, C.byref(h)) == capi.PSM_EINVAL
+
+
 @pytest.mark.parametrize("field,value,code", [
     ("q", 15, -1), ("storage", 7, -1), ("sc", 4, -1), ("slots", 3, -1), ("tau", 0.5, -1),
     ("b_form", 2, -1), ("max_bodies", 9, -1), ("nx", 0, -1),
