@@ -74,7 +74,9 @@ def lib():
         L.or_geom_inside.argtypes = [C.POINTER(Geom), C.c_longlong, C.c_longlong, C.c_longlong]
         L.or_map_cell.argtypes = [C.POINTER(Geom), C.POINTER(Pose), C.c_int, C.c_int, C.c_int]
         L.or_map_cell.restype = C.c_double
-        L.or_map.argtypes = [C.POINTER(Config), C.POINTER(Geom), C.POINTER(Pose), C.c_int, dp]
+        L.or_map_cell_block.argtypes = [C.POINTER(Geom), C.POINTER(Pose), C.c_int, C.c_int, C.c_int]
+        L.or_map_cell_block.restype = C.c_double
+        L.or_map.argtypes = [C.POINTER(Config), C.POINTER(Geom), C.POINTER(Pose), C.c_int, C.c_int, dp]
         L.or_b_from_eps.argtypes = [C.c_double, C.c_double, C.c_int]
         L.or_b_from_eps.restype = C.c_float
         L.or_winding.argtypes = [dp, C.POINTER(C.c_int), C.c_longlong, dp]
@@ -249,7 +251,7 @@ def coupled_run(wl, states, steps: int, f0: np.ndarray | None = None):
     traj = []
     for _ in range(steps):
         poses = [rigid_pose(s) for s in states]
-        B = np.stack([map_body(cfg, g, p, wl.b_form) for g, p in zip(geoms, poses)])
+        B = np.stack([map_body(cfg, g, p, wl.b_form, wl.map_reading) for g, p in zip(geoms, poses)])
         rec = [{"X": s["X"].copy(), "V": s["V"].copy(), "W": s["W"].copy(), "R": s["R"].copy()} for s in states]
         ft = step(cfg, f, B, poses)
         for s, r, fb in zip(states, rec, ft):
@@ -323,14 +325,20 @@ class OracleGeometry:
         return np.array([lib().or_geom_inside(C.byref(self.g), int(a), int(b), int(c)) for a, b, c in m], dtype=bool)
 
 
-def map_body(cfg: Config, geom: OracleGeometry, pose: Pose, b_form: int = 0) -> np.ndarray:
+def map_body(cfg: Config, geom: OracleGeometry, pose: Pose, b_form: int = 0, reading: int = 0) -> np.ndarray:
+    """Dense B of one body (section III).  reading 0: every sub-sample of a
+    cell rotated to the body frame; reading 1: the cell centre rotated, the
+    axis-aligned block of geometry cells around it averaged."""
     N = cfg.nx * cfg.ny * cfg.nz
     out = np.zeros(N)
-    lib().or_map(C.byref(cfg), C.byref(geom.g), C.byref(pose), int(b_form), _dp(out))
+    if lib().or_map(C.byref(cfg), C.byref(geom.g), C.byref(pose), int(b_form), int(reading), _dp(out)) != 0:
+        raise ValueError(f"mapping reading {reading}")
     return out
 
 
-def map_cell(geom: OracleGeometry, pose: Pose, ix: int, iy: int, iz: int) -> float:
+def map_cell(geom: OracleGeometry, pose: Pose, ix: int, iy: int, iz: int, reading: int = 0) -> float:
+    if reading:
+        return lib().or_map_cell_block(C.byref(geom.g), C.byref(pose), ix, iy, iz)
     return lib().or_map_cell(C.byref(geom.g), C.byref(pose), ix, iy, iz)
 
 
@@ -386,7 +394,7 @@ class Run:
 
     def map(self, t):
         for k, (b, g) in enumerate(zip(self.wl.bodies, self.geoms)):
-            self.B[k] = map_body(self.cfg, g, pose_at(b.motion, t), self.b_form)
+            self.B[k] = map_body(self.cfg, g, pose_at(b.motion, t), self.b_form, self.wl.map_reading)
 
     def advance(self, steps: int, remap: bool = True):
         for _ in range(steps):
@@ -447,7 +455,7 @@ def sampled_steps(wl, cells, f_at, geoms, steps: int, b_form: int = 0, t0: int =
         key = (int(c[0]), int(c[1]), int(c[2]), t)
         if key not in bcache:
             poses = [pose_at(b.motion, t) for b in wl.bodies]
-            bcache[key] = np.array([b_from_eps(map_cell(g, P, *map(int, c)), wl.tau, b_form)
+            bcache[key] = np.array([b_from_eps(map_cell(g, P, *map(int, c), reading=wl.map_reading), wl.tau, b_form)
                                     for g, P in zip(geoms, poses)])
         return bcache[key]
 
@@ -496,7 +504,7 @@ def torque_forward(wl, f0, steps, weights, dB=None, omega_us=None, keep_states=F
     J = 0.0
     states, Bs = [], []
     for t in range(steps):
-        B = map_body(cfg, geom, pose_at(body.motion, t), wl.b_form)
+        B = map_body(cfg, geom, pose_at(body.motion, t), wl.b_form, wl.map_reading)
         if dB is not None:
             B = B + dB
         if keep_states:

@@ -574,9 +574,9 @@ static void rt_mul(const double *R, const double *v, double *p) {
   for (int a = 0; a < 3; ++a) p[a] = fma(R[0 * 3 + a], v[0], fma(R[1 * 3 + a], v[1], R[2 * 3 + a] * v[2]));
 }
 
-/* Solid fraction eps of lab cell (ix,iy,iz) for one body (reading of the
- * "average over all corresponding super-sampled cells" with the rotation
- * folded into the lookup): each of the (2^s)^3 sub-sample points of the cell,
+/* Solid fraction eps of lab cell (ix,iy,iz) for one body (section III: the
+ * cell's value is the mean over the geometry cells its sub-samples land in,
+ * with the rotation folded into the lookup): each of the (2^s)^3 sub-sample points of the cell,
  * at offsets delta_k = (k + 1/2) h - 1/2 from the cell centre, is taken to the
  * body frame, p_k = R^T (x_c - X) + R^T delta_k, and looked up in the
  * geometry lattice cell that contains it.  Coordinates are measured in
@@ -606,6 +606,34 @@ double or_map_cell(const or_geom *g, const or_pose *pose, int ix, int iy, int iz
   return (double)count / (double)((long long)n * n * n);
 }
 
+/* Solid fraction eps of lab cell (ix,iy,iz) for one body, the other reading
+ * of section III's mapping paragraph: only the cell centre is taken to the
+ * body frame, and eps is the mean of the inside flags of the axis-aligned
+ * (2^s)^3 block of geometry lattice cells nearest to the cell's extent there,
+ * i.e. the block whose lower corner is the multiple of the sub-cell size
+ * nearest to q - 2^(s-1) (q = the centre in sub-cell units):
+ *   j0 = floor(q - 2^(s-1) + 1/2),  cells j0 .. j0 + 2^s - 1 per axis.
+ * Same fixed point as or_map_cell: Q = rint(q * 2^32), so
+ *   j0 = floor((Q - 2^(s+31) + 2^31) / 2^32).
+ * At theta = 0 and for s = 0 this selects exactly the geometry cells of
+ * or_map_cell's sub-samples; under rotation the block is a cube rotated
+ * against the lab cell (larger per-cell error than or_map_cell). */
+double or_map_cell_block(const or_geom *g, const or_pose *pose, int ix, int iy, int iz) {
+  const int s = g->s, n = 1 << s;
+  double d[3] = {(ix + 0.5) - pose->X[0], (iy + 0.5) - pose->X[1], (iz + 0.5) - pose->X[2]};
+  double p[3];
+  rt_mul(pose->R, d, p);
+  long long j0[3];
+  const long long half = 2147483648LL; /* 2^31 */
+  const long long corner = (long long)1 << (s + 31);
+  for (int a = 0; a < 3; ++a) j0[a] = floor_div32(llrint(ldexp(p[a], s + 32)) - corner + half);
+  long long count = 0;
+  for (int kz = 0; kz < n; ++kz)
+    for (int ky = 0; ky < n; ++ky)
+      for (int kx = 0; kx < n; ++kx) count += or_geom_inside(g, j0[0] + kx, j0[1] + ky, j0[2] + kz);
+  return (double)count / (double)((long long)n * n * n);
+}
+
 /* B from eps: eq. (5) (b_form 0) or eq. (6) (b_form 1); stored as binary32 */
 float or_b_from_eps(double eps, double tau, int b_form) {
   if (b_form == 0) return (float)eps;
@@ -615,10 +643,15 @@ float or_b_from_eps(double eps, double tau, int b_form) {
   return (float)(num / den);
 }
 
-/* Dense B of one body.  Cells farther than r_bound + 2 from the body centre
- * cannot see an inside geometry cell (sub-samples lie within sqrt(3)/2 of the
- * cell centre, a lattice centre within sqrt(3)/2 h of the sample) and get 0. */
-int or_map(const or_config *cfg, const or_geom *g, const or_pose *pose, int b_form, double *B_out) {
+/* Dense B of one body; reading 0: or_map_cell (every sub-sample rotated),
+ * reading 1: or_map_cell_block (centre rotated, axis-aligned block).  Cells
+ * farther than r_bound + 2 from the body centre cannot see an inside geometry
+ * cell (sub-samples lie within sqrt(3)/2 of the cell centre and a lattice
+ * centre within sqrt(3)/2 h of the sample; a block's lattice centres lie
+ * within sqrt(3) (1/2 + h/2) <= sqrt(3) of it for s >= 1) and get 0. */
+int or_map(const or_config *cfg, const or_geom *g, const or_pose *pose, int b_form, int reading,
+           double *B_out) {
+  if (reading != 0 && reading != 1) return -1;
   const int nx = cfg->nx, ny = cfg->ny, nz = cfg->nz;
   const double rb = g->r_bound + 2.0;
 #pragma omp parallel for schedule(dynamic, 1)
@@ -631,7 +664,7 @@ int or_map(const or_config *cfg, const or_geom *g, const or_pose *pose, int b_fo
           B_out[n] = 0.0;
           continue;
         }
-        double eps = or_map_cell(g, pose, x, y, z);
+        double eps = reading ? or_map_cell_block(g, pose, x, y, z) : or_map_cell(g, pose, x, y, z);
         B_out[n] = (double)or_b_from_eps(eps, cfg->tau, b_form);
       }
   return 0;

@@ -17,7 +17,8 @@
  *   - hydrodynamic force / torque, eqs. (10)-(11), reported as the force ON
  *     the body (minus the printed fluid-side sum)
  *   - geometry field -> solid fraction mapping with rotation/translation,
- *     section III (supersampled body-frame lookup of every sub-sample)
+ *     section III (supersampled body-frame lookup of every sub-sample; the
+ *     other reading, centre transform + axis-aligned block average)
  *   - generalised winding number voxelisation, divergence-theorem volume
  *   - FP64 discrete adjoint of one step (explicit per-cell Jacobian)
  *   - cumulant fluid collision (D3Q27; shear rate 1/tau, every other rate
@@ -99,7 +100,8 @@ double or_mass(const or_config *cfg, const double *f);
 
 int or_geom_inside(const or_geom *g, long long mx, long long my, long long mz);
 double or_map_cell(const or_geom *g, const or_pose *pose, int ix, int iy, int iz);
-int or_map(const or_config *cfg, const or_geom *g, const or_pose *pose, int b_form,
+double or_map_cell_block(const or_geom *g, const or_pose *pose, int ix, int iy, int iz);
+int or_map(const or_config *cfg, const or_geom *g, const or_pose *pose, int b_form, int reading,
            double *B_out);
 float or_b_from_eps(double eps, double tau, int b_form);
 

@@ -363,6 +363,7 @@ class Workload:
     steps: int = 100
     bodies: list = field(default_factory=list)
     collision: str = "trt"    # "trt" or "cumulant" (D3Q27, no body force)
+    map_reading: int = 0      # 0: every sub-sample rotated; 1: centre rotated, axis-aligned block
 
     @property
     def n_cells(self):

@@ -426,6 +426,126 @@ def test_mapping_fixed_point_matches_exact_arithmetic(orc, s_depth, trials, cell
     assert checked >= 1  # at least one cell cuts the surface
 
 
+def _ellipsoid_inside_exact(m, h, abc):
+    """Exact test of lattice centre (m + 1/2) h against the ellipsoid with
+    semi-axes abc (rational arithmetic)."""
+    from fractions import Fraction as Fr
+
+    return sum((Fr(2 * int(mi) + 1) * h / 2 / Fr(a)) ** 2 for mi, a in zip(m, abc)) < 1
+
+
+@pytest.mark.parametrize("s_depth", [1, 2, 3])
+def test_mapping_block_reading_matches_exact_arithmetic(orc, s_depth):
+    """The block reading (centre rotated, axis-aligned block averaged): eps
+    equals the count over the (2^s)^3 lattice cells from j0 = floor(q - 2^(s-1)
+    + 1/2), q the body-frame centre in sub-cell units, computed here in
+    rational arithmetic from the same FP64 rotation with the analytic inside
+    test, except for centres within 2^-28 sub-cells of a rounding tie."""
+    from fractions import Fraction as Fr
+
+    n = 2 ** s_depth
+    abc = (3.0, 2.0, 1.5)
+    g = orc.OracleGeometry(pi.Shape("ellipsoid", abc), s_depth)
+    rng = np.random.default_rng(40 + s_depth)
+    X = (5.25, 4.75, 5.0)
+    mism = cut = 0
+    for trial in range(4):
+        ax = rng.normal(size=3)
+        ax /= np.linalg.norm(ax)
+        m = pi.Motion(axis=tuple(ax), omega=float(rng.uniform(0, 6)), x0=X)
+        pose = orc.pose_at(m, 1)
+        R = np.array(pose.R[:]).reshape(3, 3)
+        Rf = [[Fr(float(R[i, j])) for j in range(3)] for i in range(3)]
+        for (x, y, z) in [(5, 4, 5), (6, 5, 5), (3, 4, 6), (7, 6, 4), (4, 2, 5), (5, 5, 3)]:
+            d = [Fr(2 * x + 1, 2) - Fr(X[0]), Fr(2 * y + 1, 2) - Fr(X[1]), Fr(2 * z + 1, 2) - Fr(X[2])]
+            q = [sum(Rf[j][a] * d[j] for j in range(3)) * n for a in range(3)]
+            t = [v - Fr(n, 2) + Fr(1, 2) for v in q]
+            near = any(abs(v - round(v)) < Fr(1, 2 ** 28) for v in t)
+            j0 = [math.floor(v) for v in t]
+            cnt = sum(_ellipsoid_inside_exact((j0[0] + kx, j0[1] + ky, j0[2] + kz), Fr(1, n), abc)
+                      for kx, ky, kz in itertools.product(range(n), repeat=3))
+            cut += 0 < cnt < n ** 3
+            if Fr(cnt, n ** 3) != Fr(orc.map_cell(g, pose, x, y, z, reading=1)):
+                assert near
+                mism += 1
+    assert mism == 0
+    assert cut >= 3  # cells that cut the surface were checked
+
+
+@pytest.mark.parametrize("X", [(8.0, 7.0, 6.0), (8.3, 6.85, 6.6)])
+def test_mapping_block_reading_agrees_at_theta0_and_s0(orc, X):
+    """Both readings select the same geometry cells at theta = 0 (any centre,
+    any s) and for s = 0 (any rotation): the dense fields are equal."""
+    cfg = orc.make_config(nx=16, ny=14, nz=12, q=19, tau=0.8)
+    shp = pi.Shape("ellipsoid", (5.0, 3.5, 2.5))
+    for s_depth in (0, 1, 2, 3):
+        g = orc.OracleGeometry(shp, s_depth)
+        p0 = _pose_fixed(orc, np.eye(3), X)
+        Ba, Bb = orc.map_body(cfg, g, p0, reading=1), orc.map_body(cfg, g, p0, reading=0)
+        assert Bb.sum() > 50 and np.array_equal(Ba, Bb)
+    g = orc.OracleGeometry(shp, 0)
+    for t in (1, 3, 7):
+        pr = orc.pose_at(pi.Motion(axis=(0.36, 0.48, 0.8), omega=0.37, x0=X), t)
+        assert np.array_equal(orc.map_body(cfg, g, pr, reading=1), orc.map_body(cfg, g, pr, reading=0))
+
+
+def test_mapping_block_reading_quarter_turn_is_permutation(orc):
+    """A rotation by pi/2 about z through an integer point permutes the block
+    reading's field too (the rotated lab cell is again an axis-aligned block)."""
+    cfg = orc.make_config(nx=24, ny=24, nz=12, q=19, tau=0.8)
+    g = orc.OracleGeometry(pi.Shape("ellipsoid", (8.0, 4.0, 3.0)), 2)
+    X = (12.0, 12.0, 6.0)
+    B0 = orc.map_body(cfg, g, _pose_fixed(orc, np.eye(3), X), reading=1).reshape(12, 24, 24)
+    Rq = orc.pose_arrays(orc.pose_at(pi.Motion(axis=(0, 0, 1), omega=math.pi / 2), 1))[0]
+    B1 = orc.map_body(cfg, g, _pose_fixed(orc, Rq, X), reading=1).reshape(12, 24, 24)
+    assert B0.sum() > 100
+    assert np.array_equal(B1, np.rot90(B0, k=1, axes=(2, 1)))
+
+
+def _true_fractions(R, X, abc, cells, m=16):
+    """Overlap of each lab cell with the rotated ellipsoid, by m^3 midpoint
+    samples per cell (numpy, independent of the oracle's lookup)."""
+    k = (np.arange(m) + 0.5) / m
+    oz, oy, ox = np.meshgrid(k, k, k, indexing="ij")
+    off = np.stack([ox.ravel(), oy.ravel(), oz.ravel()], axis=1)
+    out = np.empty(len(cells))
+    for i, c in enumerate(cells):
+        pts = (c + off - np.asarray(X)) @ R  # rows: R^T (x - X)
+        out[i] = np.mean(np.sum((pts / np.asarray(abc)) ** 2, axis=1) < 1)
+    return out
+
+
+@pytest.mark.parametrize("axis,angle", [((0, 0, 1), math.pi / 4), ((1, 1, 1), 0.7)])
+def test_mapping_block_reading_error_under_rotation(orc, axis, angle):
+    """Turned by 45 degrees (and about a body diagonal) the block reading
+    samples a cube turned against the lab cell: at s = 2 and 3 its mean
+    per-cell error against the true overlap is more than twice that of the
+    rotated sub-samples (whose error is the sub-sampling error alone), while
+    both volumes stay within the surface bound (eq. 12)."""
+    abc = (6.0, 4.0, 3.0)
+    X = (10.0, 10.0, 8.0)
+    cfg = orc.make_config(nx=20, ny=20, nz=16, q=19, tau=0.8)
+    ax = np.asarray(axis, dtype=np.float64) / np.linalg.norm(axis)
+    pose = orc.pose_at(pi.Motion(axis=tuple(ax), omega=angle, x0=X), 1)
+    R = np.array(pose.R[:]).reshape(3, 3)
+    cells = np.array([(x, y, z) for z in range(16) for y in range(20) for x in range(20)])
+    ref = _true_fractions(R, X, abc, cells)
+    surf = (ref > 0) & (ref < 1)
+    vol = 4 / 3 * math.pi * np.prod(abc)
+    # Knud Thomsen's surface-area approximation (within ~1%)
+    area = 4 * math.pi * ((abc[0] * abc[1]) ** 1.6 + (abc[0] * abc[2]) ** 1.6 + (abc[1] * abc[2]) ** 1.6) ** (1 / 1.6) \
+        / 3 ** (1 / 1.6)
+    for s_depth in (2, 3):
+        g = orc.OracleGeometry(pi.Shape("ellipsoid", abc), s_depth)
+        Bb = orc.map_body(cfg, g, pose, reading=0)
+        Ba = orc.map_body(cfg, g, pose, reading=1)
+        eb, ea = np.abs(Bb - ref)[surf], np.abs(Ba - ref)[surf]
+        assert ea.mean() > 2.0 * eb.mean() and ea.max() > eb.max(), (s_depth, ea.max(), ea.mean(), eb.mean())
+        assert eb.max() < 0.1
+        for B in (Ba, Bb):
+            assert abs(B.sum() - vol) < area * math.sqrt(3) * 2.0 ** -s_depth
+
+
 def test_b_tau_weighted_form(orc):
     """Eq. (6) limits: eps 0 -> 0, eps 1 -> 1, monotone, below eps for tau < 1.5."""
     tau = 0.8
