@@ -148,20 +148,24 @@ def traffic_record(kname, wname):
 
 
 def s_sweep(steps=200):
-    """The channel workload at supersampling s = 0..3 (PSM + mapping every step)."""
+    """The channel workload at supersampling s = 0..3 (PSM + mapping every
+    step), with every sub-sample rotated (sN) and, for s >= 1, with the block
+    reading of the mapping (sN_block: centre rotated, axis-aligned block)."""
+    import dataclasses
+
     import torch
 
     import psm_inputs as pi
     from paper_2502_20049_amd import sim
 
     out = {}
-    for s in (0, 1, 2, 3):
-        wl = pi.workload_ellipsoid_channel(256, "f32", steps=steps, s=s)
+    for s, reading in ((0, 0), (1, 0), (2, 0), (3, 0), (1, 1), (2, 1), (3, 1)):
+        wl = dataclasses.replace(pi.workload_ellipsoid_channel(256, "f32", steps=steps, s=s), map_reading=reading)
         f = sim.Field(wl)
         wall, t = time_field(f, steps, 20)
         sc, mp = time_kernels(f, 100, t)
-        out[f"s{s}"] = {"mlups": round(wl.n_cells * steps / wall / 1e6, 1), "map_ms": round(mp, 5),
-                        "collide_ms": round(sc, 5)}
+        out[f"s{s}" + ("_block" if reading else "")] = {
+            "mlups": round(wl.n_cells * steps / wall / 1e6, 1), "map_ms": round(mp, 5), "collide_ms": round(sc, 5)}
         del f
         torch.cuda.empty_cache()
     return out
@@ -355,6 +359,8 @@ def main():
                     help="run only the two-way coupled settling sphere (section IV setup)")
     ap.add_argument("--cumulant-only", action="store_true",
                     help="run only the TRT / cumulant comparison on the counter-rotating rotor pair")
+    ap.add_argument("--sweep-only", action="store_true",
+                    help="run only the supersampling sweep (s = 0..3, both mapping readings) on the channel")
     ap.add_argument("--copy-only", action="store_true",
                     help="run only the device copy probe (1 GiB read + 1 GiB written per launch): the "
                          "calibration for rocprofv3 FETCH_SIZE / WRITE_SIZE")
@@ -380,6 +386,9 @@ def main():
         return
     if args.cumulant_only:
         print(json.dumps(cumulant_cror()), flush=True)
+        return
+    if args.sweep_only:
+        print(json.dumps(s_sweep()), flush=True)
         return
     if args.copy_only:
         bw = copy_probe(nbytes=1 << 30, reps=5)

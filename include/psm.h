@@ -59,6 +59,7 @@ enum { PSM_BUF_PDF = 0, PSM_BUF_B = 1, PSM_BUF_WORK = 2, PSM_BUF_ADJOINT = 3, PS
        PSM_BUF_OBSTACLE = 5 };
 enum { PSM_SHAPE_ELLIPSOID = 0, PSM_SHAPE_CUBE = 1 };
 enum { PSM_COLL_TRT = 0, PSM_COLL_CUMULANT = 1 };               /* fluid collision */
+enum { PSM_MAP_SUBSAMPLES = 0, PSM_MAP_BLOCK = 1 };             /* mapping reading */
 #define PSM_MAX_BODIES 8
 
 /* Simulation configuration (section II.A; readings of unstated details in the
@@ -83,6 +84,14 @@ enum { PSM_COLL_TRT = 0, PSM_COLL_CUMULANT = 1 };               /* fluid collisi
  *            section II.B), D3Q27 only and without body force: shear rate
  *            1/tau, every other rate one (second-order trace to 3 c_s^2,
  *            cumulants of orders 3..6 to zero); magic is unused
+ *   map_reading  how geometry_map_step reads section III's average over the
+ *            super-sampled geometry cells that correspond to a lab cell:
+ *            PSM_MAP_SUBSAMPLES: each of the cell's (2^s)^3 sub-sample points
+ *            is rotated to the body frame and looked up; PSM_MAP_BLOCK: the
+ *            cell centre alone is rotated and the axis-aligned (2^s)^3 block
+ *            of geometry cells nearest to the cell's extent is averaged
+ *            (cheaper; larger per-cell error under rotation).  The two agree
+ *            at zero rotation and for s = 0.
  */
 typedef struct psm_config {
   int32_t nx, ny, nz;
@@ -99,7 +108,7 @@ typedef struct psm_config {
   double force[3];
   double u_in[3];
   int32_t collision;
-  int32_t reserved;
+  int32_t map_reading;
 } psm_config;
 
 /* Pose and velocity of one rigid body at one step: a body-frame point p is at

@@ -18,6 +18,7 @@ PSM_PERIODIC, PSM_WALL, PSM_INLET, PSM_OUTLET = 0, 1, 2, 3
 PSM_BUF_PDF, PSM_BUF_B, PSM_BUF_WORK, PSM_BUF_ADJOINT, PSM_BUF_GRAD_B, PSM_BUF_OBSTACLE = 0, 1, 2, 3, 4, 5
 PSM_SHAPE_ELLIPSOID, PSM_SHAPE_CUBE = 0, 1
 PSM_COLL_TRT, PSM_COLL_CUMULANT = 0, 1
+PSM_MAP_SUBSAMPLES, PSM_MAP_BLOCK = 0, 1
 PSM_OPT_GENERAL_PATH, PSM_OPT_XCD_REMAP, PSM_OPT_MAP_LIST, PSM_OPT_SOLID_GRID = 1, 2, 4, 8
 PSM_MAX_BODIES = 8
 PSM_STATIC_WORK_BYTES = 16 << 20
@@ -45,7 +46,7 @@ class psm_config(C.Structure):
                 ("storage", C.c_int32), ("psm", C.c_int32), ("sc", C.c_int32), ("b_form", C.c_int32),
                 ("slots", C.c_int32), ("max_bodies", C.c_int32), ("bc", C.c_int32 * 6),
                 ("tau", C.c_double), ("magic", C.c_double), ("force", C.c_double * 3),
-                ("u_in", C.c_double * 3), ("collision", C.c_int32), ("reserved", C.c_int32)]
+                ("u_in", C.c_double * 3), ("collision", C.c_int32), ("map_reading", C.c_int32)]
 
 
 class psm_body(C.Structure):

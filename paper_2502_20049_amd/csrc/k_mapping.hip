@@ -7,6 +7,13 @@
 //   m = floor((rint(p * 2^(s+32)) + rint((R^T delta_k) * 2^(s+32))) / 2^32)
 // (signed 64-bit fixed point, 32 fraction bits, sub-cell units).
 //
+// The other reading of the section III average (per-body flag `block`, s >= 1):
+// only the centre is taken to the body frame, and the cell averages the
+// axis-aligned block of (2^s)^3 geometry cells whose lower corner is
+//   j0 = floor((P - 2^(s+31) + 2^31) / 2^32)
+// per axis (P the centre in the same fixed point); identical to the above at
+// theta = 0 and for s = 0.
+//
 // Cost control: a coarse map (one byte per 2^s-cube block of the geometry
 // lattice: all out / all in / mixed) classifies most cells exactly from the
 // <= 3x3x3 blocks their sub-samples can touch; only surface cells are sampled:
@@ -142,6 +149,54 @@ __device__ __forceinline__ int sample_cells(const MapBodyK &g, bool own_tab, con
   return count;
 }
 
+// Block reading, surface cells of a wave: each of a cell's (2^s)^2 rows of
+// 2^s geometry cells along x is one lane's (at most two word loads), so a
+// round takes 64 / 4^s cells (s = 1: 16, s = 2: 4, s = 3: 1).  A row holds at
+// most 8 inside flags; the four bit planes of the row counts are ballotted
+// and each group's lanes popcounted.  J: the block's lower corner relative
+// to the stored box; `mask`: the lanes whose cell needs counting.
+__device__ __forceinline__ int block_cells(const MapBodyK &g, unsigned long long mask, const int J[3], int lane,
+                                           int count) {
+  const int s = g.s, n = 1 << s;
+  const int rows = 1 << (2 * s);
+  const int cpr = 64 >> (2 * s);  // cells per round
+  const int grp = lane >> (2 * s), r = lane & (rows - 1);
+  const int dy = r & (n - 1), dz = r >> s;
+  const int d0 = g.dims[0], d1 = g.dims[1], d2 = g.dims[2];
+  while (mask) {
+    // this lane's group takes the grp-th remaining cell of the mask
+    unsigned long long mm = mask;
+    int src = -1;
+    for (int c = 0; c < cpr && mm; ++c) {
+      const int l = __ffsll((long long)mm) - 1;
+      mm &= mm - 1;
+      if (c == grp) src = l;
+    }
+    const int sl = src < 0 ? 0 : src;
+    const int jx = __shfl(J[0], sl), jy = __shfl(J[1], sl) + dy, jz = __shfl(J[2], sl) + dz;
+    const int xa = max(jx, 0), xb = min(jx + n, d0);
+    uint32_t c = 0;
+    if (src >= 0 && jy >= 0 && jy < d1 && jz >= 0 && jz < d2 && xa < xb) {
+      const uint32_t *row = g.bits + ((size_t)jz * d1 + jy) * (size_t)g.wx;
+      const int w0 = xa >> 5, w1 = (xb - 1) >> 5;
+      const uint64_t v = (uint64_t)row[w0] | (w1 != w0 ? (uint64_t)row[w1] << 32 : 0ull);
+      c = (uint32_t)__popcll((v >> (xa & 31)) & ((1ull << (xb - xa)) - 1ull));
+    }
+    const unsigned long long b0 = __ballot(c & 1u), b1 = __ballot(c & 2u), b2 = __ballot(c & 4u),
+                             b3 = __ballot(c & 8u);
+    mm = mask;
+    for (int cc = 0; cc < cpr && mm; ++cc) {
+      const int l = __ffsll((long long)mm) - 1;
+      mm &= mm - 1;
+      const unsigned long long gm = (rows == 64 ? ~0ull : ((1ull << rows) - 1ull)) << (cc * rows);
+      const int tot = __popcll(b0 & gm) + 2 * __popcll(b1 & gm) + 4 * __popcll(b2 & gm) + 8 * __popcll(b3 & gm);
+      if (lane == l) count = tot;
+    }
+    mask = mm;
+  }
+  return count;
+}
+
 // Solid fraction from the inside count: eq. (5) (B = eps) or eq. (6).
 __device__ __forceinline__ float fraction_of(const MapArgs &a, int count, int ns) {
   const double eps = (double)count / (double)ns;
@@ -208,12 +263,51 @@ __global__ __launch_bounds__(256) void k_map(const MapArgs a) {
   for (int bb = 0; bb < a.nb; ++bb) {
     const MapBodyK &g = a.body[bb];
     const bool inb = active && in_box(g.active, x, y, z);
-    const bool listing = a.list && g.s == 3;  // workgroup-uniform: every wave reaches its barriers
+    const bool listing = a.list && g.s == 3 && !g.block;  // workgroup-uniform: every wave reaches its barriers
     if (!__any(inb) && !listing) continue;
     const int s = g.s;
     const int ns = 1 << (3 * s);
     long long P[3] = {0, 0, 0};
     int state = 0;  // 0 all out, 1 all in, 2 sample
+    if (g.block) {
+      // block reading (s >= 1): the block lies within one coarse block of the
+      // centre's, and spans at most two coarse blocks per axis
+      int J[3] = {0, 0, 0};
+      if (inb) {
+        body_point(g, x, y, z, P);
+        const long long off = (1ll << 31) - (1ll << (s + 31));
+#pragma unroll
+        for (int c = 0; c < 3; ++c) J[c] = (int)((P[c] + off) >> 32);
+        if ((state = coarse_centre(g, P)) < 0) {
+          int vals[8];
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            const int bx = (J[0] + ((j & 1) ? (1 << s) - 1 : 0)) >> s;
+            const int by = (J[1] + ((j & 2) ? (1 << s) - 1 : 0)) >> s;
+            const int bz = (J[2] + ((j & 4) ? (1 << s) - 1 : 0)) >> s;
+            vals[j] = coarse_state(g, bx, by, bz);
+          }
+          int st = vals[0];
+#pragma unroll
+          for (int j = 1; j < 8; ++j) st = (st == vals[j]) ? st : 2;
+          state = st;
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) J[c] -= g.mmin[c];
+      }
+      int count = block_cells(g, __ballot(state == 2), J, lane, state == 1 ? ns : 0);
+      if (inb && count > 0) {
+        const float B = fraction_of(a, count, ns);
+        if (used < a.slots) {
+          Bv[used] = B;
+          id[used] = bb;
+          ++used;
+        } else {
+          overflow = true;
+        }
+      }
+      continue;
+    }
     if (inb) {
       body_point(g, x, y, z, P);
       if (s == 0) {
@@ -322,7 +416,7 @@ __global__ __launch_bounds__(256) void k_map_sample(const MapArgs a) {
   const int bb = blockIdx.y;
   const MapBodyK &G = a.body[bb];
   if (blockIdx.x == 0 && threadIdx.x == 0) a.count_next[bb] = 0u;
-  if (G.s != 3) return;
+  if (G.s != 3 || G.block) return;
   const uint32_t total = min(a.count[bb], a.cap);
   constexpr int NCS = 3;  // cells per wave and round: their gathers are in flight together
   if (blockIdx.x * 4u * NCS >= total) return;  // whole workgroup idle

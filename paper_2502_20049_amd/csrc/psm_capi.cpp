@@ -94,6 +94,8 @@ static int check_config(const psm_config *c) {
   if (c->psm != 0 && c->psm != 1) return set_error("psm must be 0 or 1"), PSM_EINVAL;
   if (c->sc < 1 || c->sc > 3) return set_error("sc must be 1, 2 or 3"), PSM_EINVAL;
   if (c->b_form != 0 && c->b_form != 1) return set_error("b_form must be 0 or 1"), PSM_EINVAL;
+  if (c->map_reading != PSM_MAP_SUBSAMPLES && c->map_reading != PSM_MAP_BLOCK)
+    return set_error("map_reading must be PSM_MAP_SUBSAMPLES or PSM_MAP_BLOCK"), PSM_EINVAL;
   if (c->slots != 1 && c->slots != 2) return set_error("slots must be 1 or 2"), PSM_EINVAL;
   if (c->psm && (c->max_bodies < 1 || c->max_bodies > PSM_MAX_BODIES))
     return set_error("max_bodies must be in 1..8"), PSM_EINVAL;
@@ -644,6 +646,7 @@ static int map_plan(psm_field *f, const psm_body *bodies, const psm_geom *const 
     m.bits = g->dev_bits;
     m.coarse = g->dev_coarse;
     m.s = g->s;
+    m.block = (f->cfg.map_reading == PSM_MAP_BLOCK && g->s >= 1) ? 1 : 0;
     m.wx = g->wx;
     for (int d = 0; d < 3; ++d) {
       m.mmin[d] = g->mmin[d];
@@ -656,7 +659,9 @@ static int map_plan(psm_field *f, const psm_body *bodies, const psm_geom *const 
     }
     // cells the body can touch at this pose: lab AABB of the rotated
     // geometry box (a cell [i, i+1] meets [lo, hi] iff floor(lo) <= i < hi),
-    // one cell of margin
+    // one cell of margin; two below and one above for the block reading,
+    // whose block reaches 1/2 + h/2 <= 3/4 per body axis from the centre
+    // (<= 3/4 sqrt(3) in the lab)
     double blo[3], bhi[3];
     {
       const double h = ldexp(1.0, -g->s);
@@ -677,7 +682,7 @@ static int map_plan(psm_field *f, const psm_body *bodies, const psm_geom *const 
     IBox A;
     bool empty = false;
     for (int d = 0; d < 3; ++d) {
-      const double lo = floor(blo[d]) - 1.0, hi = ceil(bhi[d]);
+      const double lo = floor(blo[d]) - (m.block ? 2.0 : 1.0), hi = ceil(bhi[d]) + (m.block ? 1.0 : 0.0);
       A.lo[d] = (int)std::max(0.0, std::min((double)n3[d], lo));
       A.hi[d] = (int)std::min((double)n3[d] - 1, std::max(-1.0, hi));
       if (A.hi[d] < A.lo[d]) empty = true;
@@ -701,7 +706,7 @@ static int map_plan(psm_field *f, const psm_body *bodies, const psm_geom *const 
   P.nb = nb;
   // the surface-cell list serves s = 3 bodies only
   bool any3 = false;
-  for (int b = 0; b < nb; ++b) any3 = any3 || geoms[b]->s == 3;
+  for (int b = 0; b < nb; ++b) any3 = any3 || (geoms[b]->s == 3 && !a.body[b].block);
   if (!any3) a.list = nullptr;
   return PSM_OK;
 }

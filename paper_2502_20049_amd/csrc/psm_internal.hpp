@@ -165,6 +165,7 @@ struct MapBodyK {
   int mmin[3], dims[3], wx;
   int cmin[3], cdims[3];
   int s;
+  int block;          // 1: the cell's centre only is rotated and the axis-aligned block averaged
   long long dabs[3];  // bound on |fixed-point sub-sample offset| per axis
   IBox region;        // cells rewritten this step (swept box now and before)
   IBox active;        // cells that can touch the body this step

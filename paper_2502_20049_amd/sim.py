@@ -48,6 +48,7 @@ def make_config(wl, storage=None, psm=True, slots=None, max_bodies=None) -> capi
     cfg.force = (C.c_double * 3)(*wl.force)
     cfg.u_in = (C.c_double * 3)(*wl.u_in)
     cfg.collision = {"trt": capi.PSM_COLL_TRT, "cumulant": capi.PSM_COLL_CUMULANT}[getattr(wl, "collision", "trt")]
+    cfg.map_reading = getattr(wl, "map_reading", 0)
     return cfg
 
 

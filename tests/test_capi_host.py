@@ -83,7 +83,7 @@ def test_noalloc_rejects_lattices_beyond_the_static_area(capi, sim):
 
 @pytest.mark.parametrize("field,value,code", [
     ("q", 15, -1), ("storage", 7, -1), ("sc", 4, -1), ("slots", 3, -1), ("tau", 0.5, -1),
-    ("b_form", 2, -1), ("max_bodies", 9, -1), ("nx", 0, -1),
+    ("b_form", 2, -1), ("max_bodies", 9, -1), ("nx", 0, -1), ("map_reading", 2, -1), ("map_reading", -1, -1),
 ])
 def test_config_validation(capi, sim, field, value, code):
     cfg = _cfg(sim)

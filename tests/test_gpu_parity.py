@@ -114,6 +114,18 @@ def test_two_steps_parity(orc, sim, gc, q, storage, bc):
     _two_step_compare(orc, sim, gc, wl)
 
 
+@pytest.mark.parametrize("bc", ["channel", "mixed"])
+@pytest.mark.parametrize("q", [19, 27])
+def test_block_reading_two_steps_parity(orc, sim, gc, q, bc):
+    """The block reading of the mapping (centre rotated, axis-aligned block)
+    feeding two PSM steps: B bit-exact, f and F/T against the oracle."""
+    import dataclasses
+
+    wl = dataclasses.replace(_workload(q, "f32", bc, two=True, s=2), map_reading=1)
+    _say(f"[two steps, block reading] q={q} bc={bc}")
+    _two_step_compare(orc, sim, gc, wl)
+
+
 @pytest.mark.parametrize("grid", [1, 2])
 @pytest.mark.parametrize("storage", ["f64", "f32"])
 @pytest.mark.parametrize("q", [19, 27])
@@ -386,14 +398,18 @@ def test_xcd_remap_bitwise_identical(sim, gc):
     assert torch.equal(res[0][0], res[1][0]) and torch.equal(res[0][1], res[1][1])
 
 
-@pytest.mark.parametrize("s,cap", [(0, None), (1, None), (2, None), (3, None), (2, 0), (3, 0), (2, 5), (3, 5)])
-def test_mapping_bit_exact(orc, sim, gc, s, cap):
+@pytest.mark.parametrize("s,cap,reading", [(0, None, 0), (1, None, 0), (2, None, 0), (3, None, 0), (2, 0, 0),
+                                           (3, 0, 0), (2, 5, 0), (3, 5, 0), (0, None, 1), (1, None, 1),
+                                           (2, None, 1), (3, None, 1), (3, 5, 1)])
+def test_mapping_bit_exact(orc, sim, gc, s, cap, reading):
     """B(t) of rotating analytic and mesh bodies, two slots, random poses.
     cap: capacity of the surface-cell list sampled by the second mapping
-    kernel (None: the default; 0: no list; 5: most cells overflow it)."""
+    kernel (None: the default; 0: no list; 5: most cells overflow it).
+    reading 0: every sub-sample rotated; 1: the centre rotated and the
+    axis-aligned block averaged (section III, both readings)."""
     import torch
 
-    _say(f"[mapping] s={s} list cap={cap}")
+    _say(f"[mapping] s={s} list cap={cap} reading={reading}")
     rotor = pi.rotor_mesh(pi.RotorSpec(n_blades=3, radius=7.0, hub_radius=1.75, hub_length=3.1, chord_root=2.1,
                                        chord_tip=1.05, n_chord=8, n_span=6, n_hub=16, seed=7))
     bodies = [pi.Body(pi.Shape("mesh", (), rotor), pi.Motion(axis=(1, 0, 0), theta0=0.2, omega=0.37,
@@ -403,7 +419,7 @@ def test_mapping_bit_exact(orc, sim, gc, s, cap):
               pi.Body(pi.Shape("ellipsoid", (4.0, 3.0, 2.0)), pi.Motion(axis=(0, 1, 0), omega=0.7,
                                                                        x0=(8.0, 20.0, 9.0)), s=max(0, s - 1))]
     wl = pi.Workload("map", 33, 30, 28, 19, "f32", 0.8, 3 / 16, (0, 0, 0), ("periodic",) * 6, (0, 0, 0), 1, 0, 2, 3,
-                     bodies)
+                     bodies, map_reading=reading)
     f = sim.Field(wl, max_bodies=3)
     if cap is not None:
         f.set_option(4, cap)
