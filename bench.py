@@ -13,7 +13,9 @@ rocprofv3 FETCH_SIZE/WRITE_SIZE record when the kernel source is unchanged
 since it was taken.
 
 The CPU baseline is the FP64 oracle timed on the host cores on a bounded
-sample (a few full-size steps) of the same workload.
+sample (a few full-size steps) of the same workload, on all threads and on
+one; the same steps run on the GPU with FP32 and FP16 storage give the
+accuracy fields (velocity rel. L2, torque series) against it.
 """
 from __future__ import annotations
 
@@ -221,9 +223,10 @@ def node_benchmark(steps=600):
 
 
 def cumulant_cror(steps=200):
-    """The counter-rotating rotor pair (768 x 384 x 384 D3Q27, FP16 storage, s = 2)
-    with the TRT fluid collision and with the cumulant one (the paper's
-    performance operator): whole-step MLUPS and the stream-collide launch."""
+    """The counter-rotating rotor pair (768 x 384 x 384 D3Q27, s = 2) with FP16
+    storage and the TRT fluid collision, the cumulant one (the paper's
+    performance operator), and TRT with FP32 storage: whole-step MLUPS and the
+    stream-collide launch."""
     import dataclasses
 
     import torch
@@ -233,17 +236,19 @@ def cumulant_cror(steps=200):
 
     out = {}
     base = pi.workload_cror(storage="f16")
-    for coll in ("trt", "cumulant"):
-        wl = dataclasses.replace(base, collision=coll)
+    for key, coll, storage in (("trt", "trt", "f16"), ("cumulant", "cumulant", "f16"), ("trt_f32_storage", "trt", "f32")):
+        wl = dataclasses.replace(base, collision=coll, storage=storage)
         f = sim.Field(wl)
         wall, t = time_field(f, steps, 10)
         sc, mp = time_kernels(f, 50, t)
-        out[coll] = {"mlups": round(wl.n_cells * steps / wall / 1e6, 1), "collide_ms": round(sc, 4),
-                     "collide_gbs": round(bytes_per_cell(wl.q, wl.storage) * wl.n_cells / sc / 1e6, 1),
-                     "map_ms": round(mp, 4)}
+        gbs = bytes_per_cell(wl.q, wl.storage) * wl.n_cells / sc / 1e6
+        out[key] = {"mlups": round(wl.n_cells * steps / wall / 1e6, 1), "collide_ms": round(sc, 4),
+                    "collide_gbs": round(gbs, 1), "collide_frac_of_8tbs": round(gbs / PEAK_HBM_GBS, 4),
+                    "map_ms": round(mp, 4), "storage": storage}
         del f
         torch.cuda.empty_cache()
-    out["case"] = base.name + ", FP16 storage, two counter-rotating 8-blade rotors, s=2"
+    out["case"] = base.name + ", two counter-rotating 8-blade rotors, s=2; TRT and cumulant with FP16 storage, " \
+                              "TRT with FP32 storage"
     return out
 
 
@@ -317,14 +322,28 @@ def adjoint_rate(steps=800, window=200):
             "backward_mcell_steps_per_s": round(N * steps / (t2 - t1) / 1e6, 1)}
 
 
-def cpu_baseline(wl, min_seconds=12.0):
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(wl, min_seconds=12.0, single_core_steps=2):
     """The FP64 oracle on the host cores, full-size steps of the same workload
-    (map + collide/stream + F/T), two at a time until about min_seconds have
-    passed."""
+    (map + collide/stream + F/T) from rest, two at a time until about
+    min_seconds have passed, on every thread the oracle gets (OMP_NUM_THREADS,
+    else all cores), then `single_core_steps` more on one thread.  Returns
+    the baseline record and the oracle state (for the accuracy check)."""
     import oracle
 
     oracle.build(force=False)
     run = oracle.Run(wl)
+    threads = oracle.threads()
     t0 = time.perf_counter()
     nsteps = 0
     while True:
@@ -333,10 +352,79 @@ def cpu_baseline(wl, min_seconds=12.0):
         dt = time.perf_counter() - t0
         if dt >= min_seconds:
             break
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": round(wl.n_cells * nsteps / dt / 1e6, 3), "unit": "MLUPS", "cores": threads,
-            "kind": "oracle",
-            "sample": f"{nsteps} full-size steps (map + collide/stream + F/T) of {wl.name}, FP64, {dt:.1f} s"}
+    oracle.set_threads(1)
+    t1 = time.perf_counter()
+    one = oracle.Run(wl)
+    one.advance(single_core_steps)
+    dt1 = time.perf_counter() - t1
+    del one
+    oracle.set_threads(threads)
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except AttributeError:
+        affinity = os.cpu_count()
+    rec = {"value": round(wl.n_cells * nsteps / dt / 1e6, 3), "unit": "MLUPS", "cores": threads, "kind": "oracle",
+           "sample": f"{nsteps} full-size steps (map + collide/stream + F/T) of {wl.name} from rest, FP64, "
+                     f"{dt:.1f} s on {threads} threads",
+           "single_core": {"value": round(wl.n_cells * single_core_steps / dt1 / 1e6, 3), "unit": "MLUPS",
+                           "sample": f"{single_core_steps} full-size steps on 1 thread, {dt1:.1f} s"},
+           "cpu_model": _cpu_model(), "nproc": os.cpu_count(), "cpus_available": affinity}
+    return rec, run, nsteps
+
+
+def accuracy_vs_oracle(wl, run, nsteps):
+    """The oracle's steps from rest (the CPU baseline's) repeated on the GPU
+    with FP32 and FP16 storage: velocity rel. L2 over all cells after the
+    last step and the torque series' max error relative to max |T|."""
+    import numpy as np
+    import torch
+
+    from paper_2502_20049_amd import sim
+
+    _, uo = run.macro()
+    To = np.array(run.ft)[:, 0, 3:]
+    out = {"steps": nsteps, "reference": "FP64 oracle, same steps from rest"}
+    for storage in ("f32", "f16"):
+        f = sim.Field(wl, storage=storage)
+        T = []
+        for t in range(nsteps):
+            f.step(t)
+            T.append(f.force_torque()[0, 3:].cpu().numpy().copy())
+        _, u = f.macroscopic(nsteps)
+        torch.cuda.synchronize()
+        u = u.cpu().numpy()
+        T = np.array(T)
+        out[storage] = {"u_rel_l2": float(f"{np.linalg.norm(u - uo) / np.linalg.norm(uo):.3e}"),
+                        "torque_rel_max": float(f"{np.abs(T - To).max() / np.abs(To).max():.3e}")}
+        del f
+        torch.cuda.empty_cache()
+    return out
+
+
+def capacity_run(steps=20, warmup=3):
+    """The 1024^3 capacity configuration (FP32 in place, two counter-rotating
+    6-blade rotors of radius 300, s = 2): whole-step MLUPS and the
+    stream-collide launch against the roofline."""
+    import torch
+
+    import psm_inputs as pi
+    from paper_2502_20049_amd import sim
+
+    wl = pi.workload_capacity()
+    t0 = time.perf_counter()
+    f = sim.Field(wl)
+    setup = time.perf_counter() - t0
+    wall, t = time_field(f, steps, warmup)
+    sc, mp = time_kernels(f, 6, t)
+    bpc = bytes_per_cell(wl.q, wl.storage)
+    out = {"case": f"{wl.name}, FP32 in place, two 6-blade rotors r=300, s=2, {steps} steps",
+           "mlups": round(wl.n_cells * steps / wall / 1e6, 1), "collide_ms": round(sc, 3), "map_ms": round(mp, 3),
+           "collide_gbs": round(bpc * wl.n_cells / sc / 1e6, 1),
+           "collide_frac_of_8tbs": round(bpc * wl.n_cells / sc / 1e6 / PEAK_HBM_GBS, 4),
+           "setup_s": round(setup, 1)}
+    del f
+    torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -440,15 +528,17 @@ def main():
         extras["psm_static_geometry"] = {"mlups": round(N * min(args.steps, 500) / wall_s / 1e6, 1)}
         del fs
         torch.cuda.empty_cache()
-        alt = "f16" if storage != "f16" else "f32"
-        fa = sim.Field(wl, storage=alt)
-        wall_a, ta = time_field(fa, min(args.steps, 500), 20)
-        sc_a, _ = time_kernels(fa, 100, ta)
-        extras[f"psm_{alt}_storage"] = {"mlups": round(N * min(args.steps, 500) / wall_a / 1e6, 1),
-                                        "kernel_ms": round(sc_a, 5),
-                                        "gbs": round(bytes_per_cell(wl.q, alt) * N / sc_a / 1e6, 1)}
-        del fa
-        torch.cuda.empty_cache()
+        for alt in [a for a in ("f16", "f32", "f64") if a != storage]:
+            fa = sim.Field(wl, storage=alt)
+            wall_a, ta = time_field(fa, min(args.steps, 500), 20)
+            sc_a, _ = time_kernels(fa, 100, ta)
+            gbs_a = bytes_per_cell(wl.q, alt) * N / sc_a / 1e6
+            extras[f"psm_{alt}_storage"] = {"mlups": round(N * min(args.steps, 500) / wall_a / 1e6, 1),
+                                            "kernel_ms": round(sc_a, 5), "gbs": round(gbs_a, 1),
+                                            "frac_of_8tbs": round(gbs_a / PEAK_HBM_GBS, 4),
+                                            "algorithmic_bytes_per_cell": bytes_per_cell(wl.q, alt)}
+            del fa
+            torch.cuda.empty_cache()
         bw = copy_probe()
         extras["copy_probe_gbs"] = round(bw, 1)
         extras["psm_frac_of_copy_bw"] = round(achieved / bw, 4)
@@ -457,9 +547,13 @@ def main():
         extras["adjoint_rotor_128"] = adjoint_rate()
         extras["settling_sphere"] = settling_sphere()
         extras["cumulant_vs_trt_cror"] = cumulant_cror()
+        extras["capacity_1024"] = capacity_run()
         line["extras"] = extras
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(wl)
+        rec, run, nsteps = cpu_baseline(wl)
+        line["cpu_baseline"] = rec
+        line["accuracy_vs_fp64_oracle"] = accuracy_vs_oracle(wl, run, nsteps)
+        del run
     else:
         line["cpu_baseline"] = None
     print(json.dumps(line), flush=True)

@@ -88,6 +88,10 @@ def lib():
         L.or_adjoint_step.argtypes = [C.POINTER(Config), dp, dp, dp, dp, C.POINTER(Pose), dp, C.c_double, dp, dp]
         L.or_mesh_volume.argtypes = [dp, C.POINTER(C.c_int), C.c_longlong]
         L.or_mesh_volume.restype = C.c_double
+        L.or_set_threads.argtypes = [C.c_int]
+        L.or_set_threads.restype = None
+        L.or_threads.argtypes = []
+        L.or_threads.restype = C.c_int
         _lib = L
     return _lib
 
@@ -363,6 +367,15 @@ def voxelize(verts, tris, s, mmin, dims) -> np.ndarray:
     return out
 
 
+def set_threads(n: int) -> None:
+    """Thread count of the oracle's parallel loops (timing only)."""
+    lib().or_set_threads(int(n))
+
+
+def threads() -> int:
+    return int(lib().or_threads())
+
+
 def mesh_volume(verts, tris) -> float:
     v = np.ascontiguousarray(verts, dtype=np.float64)
     t = np.ascontiguousarray(tris, dtype=np.int32)
@@ -493,18 +506,22 @@ def _pose_with_rate(motion, t, omega_us):
     return p
 
 
-def torque_forward(wl, f0, steps, weights, dB=None, omega_us=None, keep_states=False):
+def torque_forward(wl, f0, steps, weights, dB=None, omega_us=None, keep_states=False, geom=None, sums=None):
     """J = sum_t weights[t] * a . T_0(t) for the single body of ``wl``, with
-    B_eff = B_map(t) + dB and u_s from ``omega_us`` (mapping from the motion)."""
+    B_eff = B_map(t) + dB and u_s from ``omega_us`` (mapping from the motion).
+    ``geom``: the body's OracleGeometry when already built; ``sums``: a dict
+    that receives sum(B_map(t)) per step."""
     cfg = make_config(wl)
     body = wl.bodies[0]
-    geom = OracleGeometry(body.shape, body.s)
+    geom = OracleGeometry(body.shape, body.s) if geom is None else geom
     f = np.ascontiguousarray(f0, dtype=np.float64).copy()
     axis = np.asarray(body.motion.axis, dtype=np.float64)
     J = 0.0
     states, Bs = [], []
     for t in range(steps):
         B = map_body(cfg, geom, pose_at(body.motion, t), wl.b_form, wl.map_reading)
+        if sums is not None:
+            sums[t] = float(B.sum())
         if dB is not None:
             B = B + dB
         if keep_states:

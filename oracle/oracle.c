@@ -11,6 +11,7 @@
 
 #include <complex.h>
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -916,3 +917,11 @@ int or_adjoint_step(const or_config *cfg, const double *f, const double *ghat_ne
   free(gpost);
   return 0;
 }
+
+/* Thread count of the parallel loops (for timing the oracle on one core or
+ * on all of them); or_threads returns the count the loops will use. */
+void or_set_threads(int n) {
+  if (n > 0) omp_set_num_threads(n);
+}
+
+int or_threads(void) { return omp_get_max_threads(); }

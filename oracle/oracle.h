@@ -116,6 +116,9 @@ int or_voxelize(const double *v, const int *t, long long nt, int s, const int mm
                 const int dims[3], unsigned char *out);
 double or_mesh_volume(const double *v, const int *t, long long nt);
 
+void or_set_threads(int n);
+int or_threads(void);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,5 +1,6 @@
-// Host-side geometry field construction (run once per body, section III:
-// "voxelised once ... populated on the CPU and transferred to the GPU once").
+// Host-side geometry field construction (run once per body, section III: the
+// body-frame field is built on the host a single time and copied to the
+// device once; only its mapping runs every step).
 //
 // Geometry lattice: spacing h = 2^-s LBM cells in the body frame, cell m has
 // its centre at (m + 1/2) h; a bit is set when that centre is inside the

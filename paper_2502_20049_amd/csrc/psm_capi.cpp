@@ -111,9 +111,6 @@ static int check_config(const psm_config *c) {
   if (c->collision == PSM_COLL_CUMULANT &&
       (c->q != 27 || c->force[0] != 0.0 || c->force[1] != 0.0 || c->force[2] != 0.0))
     return set_error("the cumulant collision is D3Q27 without body force"), PSM_EUNSUP;
-  const int64_t NS = N * (int64_t)storage_size(c->storage);
-  if (NS > ((int64_t)1 << 32) && c->sc != 1 && c->psm)
-    return set_error("direction arrays over 4 GiB support sc=1 only"), PSM_EUNSUP;
   return PSM_OK;
 }
 

@@ -166,6 +166,30 @@ def test_capacity_1024_full_size(orc, sim):
     assert np.isfinite(mass)
 
 
+def test_direction_arrays_over_4gib_sc2(orc, sim):
+    """A 1056 x 1024 x 1024 channel in FP32 (4.4 GB per direction array, so
+    byte offsets past 2^32 inside each array) with SC2 and a rotating
+    ellipsoid at the top of the lattice, where the offsets are largest: two
+    steps against the oracle's one-cell updates on sampled cells, including
+    the body's surface cells."""
+    import torch
+
+    free, total = torch.cuda.mem_get_info()
+    if free < 100 * 2**30:
+        pytest.skip(f"needs ~92 GiB of device memory, {free / 2**30:.0f} GiB free")
+    _say("[full-size] 1056x1024x1024 channel, SC2, FP32 (direction arrays over 4 GiB)")
+    ell = pi.Body(pi.Shape("ellipsoid", (12.0, 8.0, 6.0)),
+                  pi.Motion(axis=(0.0, 0.6, 0.8), theta0=0.4, omega=0.05, x0=(528.0, 512.0, 1000.0)), s=1)
+    wl = pi.Workload("channel_1056x1024x1024_sc2", 1056, 1024, 1024, 19, "f32", 0.8, 3 / 16, (0, 0, 0),
+                     ("inlet", "outlet", "wall", "wall", "wall", "wall"), (0.05, 0, 0), 2, 0, 1, 2, [ell])
+    assert 4 * wl.n_cells > 2**32
+    rng = np.random.default_rng(9)
+    cells = _edge_cells(wl, rng, 8)
+    cells += [(528 + 12, 512, 1000), (528 - 12, 511, 1000), (528, 512 + 7, 1001), (527, 512, 1000 + 6),
+              (520, 505, 997), (533, 516, 1003), (528, 512, 1000)]
+    _run(orc, sim, wl, 11, cells, lambda d: np.full_like(d, 2e-6))
+
+
 def test_cror_768_cumulant_full_size(orc, sim):
     """The rotor pair with the cumulant collision (FP16 storage, the odd steps
     on the one-cell-per-lane kernel): sampled cells against the oracle's
