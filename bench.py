@@ -30,6 +30,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "MLUPS + % HBM roofline, PSM vs plain LBM, FP32/FP16 vs FP64 oracle"
+LAYOUT = "blocked"  # PDF buffer layout of every field the benchmark builds (--layout)
+
+
+def lay(wl):
+    """The workload with the benchmark's PDF layout."""
+    import dataclasses
+
+    return dataclasses.replace(wl, layout=LAYOUT)
 PEAK_HBM_GBS = 8000.0
 KERNEL_SOURCES = ["paper_2502_20049_amd/csrc/k_stream_collide.hpp", "paper_2502_20049_amd/csrc/k_sc_launch.inc",
                   "paper_2502_20049_amd/csrc/psm_internal.hpp"]
@@ -47,11 +55,11 @@ def workload(name):
     import psm_inputs as pi
 
     if name == "ellipsoid_channel_256":
-        return pi.workload_ellipsoid_channel(256, "f32", steps=2000, s=3)
+        return lay(pi.workload_ellipsoid_channel(256, "f32", steps=2000, s=3))
     if name == "cror_768x384x384":
-        return pi.workload_cror(storage="f16")
+        return lay(pi.workload_cror(storage="f16"))
     if name == "capacity_1024":
-        return pi.workload_capacity()
+        return lay(pi.workload_capacity())
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -162,7 +170,7 @@ def s_sweep(steps=200):
 
     out = {}
     for s, reading in ((0, 0), (1, 0), (2, 0), (3, 0), (1, 1), (2, 1), (3, 1)):
-        wl = dataclasses.replace(pi.workload_ellipsoid_channel(256, "f32", steps=steps, s=s), map_reading=reading)
+        wl = dataclasses.replace(lay(pi.workload_ellipsoid_channel(256, "f32", steps=steps, s=s)), map_reading=reading)
         f = sim.Field(wl)
         wall, t = time_field(f, steps, 20)
         sc, mp = time_kernels(f, 100, t)
@@ -193,8 +201,8 @@ def node_benchmark(steps=600):
         return round(wl.n_cells * steps / wall / 1e6, 1)
 
     out = {}
-    scenes = {"B_ellipsoid_channel_256": pi.workload_ellipsoid_channel(256, "f32", steps=steps, s=3),
-              "A_rotor_box_256": pi.workload_rotor_box(steps=steps)}
+    scenes = {"B_ellipsoid_channel_256": lay(pi.workload_ellipsoid_channel(256, "f32", steps=steps, s=3)),
+              "A_rotor_box_256": lay(pi.workload_rotor_box(steps=steps))}
     for name, wl in scenes.items():
         wl = dataclasses.replace(wl, bc=("periodic",) * 6, u_in=(0.0, 0.0, 0.0))
         r = {}
@@ -235,7 +243,7 @@ def cumulant_cror(steps=200):
     from paper_2502_20049_amd import sim
 
     out = {}
-    base = pi.workload_cror(storage="f16")
+    base = lay(pi.workload_cror(storage="f16"))
     for key, coll, storage in (("trt", "trt", "f16"), ("cumulant", "cumulant", "f16"), ("trt_f32_storage", "trt", "f32")):
         wl = dataclasses.replace(base, collision=coll, storage=storage)
         f = sim.Field(wl)
@@ -263,6 +271,7 @@ def settling_sphere(steps=4000):
     from paper_2502_20049_amd import sim
 
     wl, rg = pi.workload_settling_sphere(steps=steps)
+    wl = lay(wl)
     f = sim.Field(wl)
     states = sim.rigid_states([rg])
     vz = []
@@ -302,7 +311,7 @@ def adjoint_rate(steps=800, window=200):
     import psm_inputs as pi
     from paper_2502_20049_amd import adjoint
 
-    wl = pi.workload_adjoint_rotor(steps=steps)
+    wl = lay(pi.workload_adjoint_rotor(steps=steps))
     w = np.zeros(steps)
     w[-window:] = 1.0 / window
     obj = adjoint.TorqueAdjoint(wl, steps, w)
@@ -410,6 +419,8 @@ def capacity_run(steps=20, warmup=3):
     import psm_inputs as pi
     from paper_2502_20049_amd import sim
 
+    # SoA: on 1024^3 the blocked layout measured 2-7% slower (rows per block
+    # 1-16, one process), unlike the 256^3 and 768-wide lattices
     wl = pi.workload_capacity()
     t0 = time.perf_counter()
     f = sim.Field(wl)
@@ -417,7 +428,7 @@ def capacity_run(steps=20, warmup=3):
     wall, t = time_field(f, steps, warmup)
     sc, mp = time_kernels(f, 6, t)
     bpc = bytes_per_cell(wl.q, wl.storage)
-    out = {"case": f"{wl.name}, FP32 in place, two 6-blade rotors r=300, s=2, {steps} steps",
+    out = {"case": f"{wl.name}, FP32 in place (SoA layout), two 6-blade rotors r=300, s=2, {steps} steps",
            "mlups": round(wl.n_cells * steps / wall / 1e6, 1), "collide_ms": round(sc, 3), "map_ms": round(mp, 3),
            "collide_gbs": round(bpc * wl.n_cells / sc / 1e6, 1),
            "collide_frac_of_8tbs": round(bpc * wl.n_cells / sc / 1e6 / PEAK_HBM_GBS, 4),
@@ -435,6 +446,8 @@ def main():
     ap.add_argument("--workload", default="ellipsoid_channel_256")
     ap.add_argument("--storage", choices=["f64", "f32", "f16"], default=None,
                     help="PDF storage type (default: the workload's)")
+    ap.add_argument("--layout", choices=["soa", "blocked"], default="blocked",
+                    help="PDF buffer layout of every field (default: blocked)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the variants, the copy probe and the other workloads")
     ap.add_argument("--only-psm", action="store_true", help="time the PSM path only (for profiling)")
@@ -453,6 +466,8 @@ def main():
                     help="run only the device copy probe (1 GiB read + 1 GiB written per launch): the "
                          "calibration for rocprofv3 FETCH_SIZE / WRITE_SIZE")
     args = ap.parse_args()
+    global LAYOUT
+    LAYOUT = args.layout
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the PSM hot path here is single-GPU (no sharding or collectives); "
               "run with --gpus 1", file=sys.stderr)
@@ -501,7 +516,8 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": {"f32": "f32", "f16": "f32 (f16 storage)",
                                                             "f64": "f64"}[storage],
         "data": "synthetic",
-        "config": {"workload": wl.name, "cells": N, "q": wl.q, "storage": storage, "bodies": len(wl.bodies),
+        "config": {"workload": wl.name, "cells": N, "q": wl.q, "storage": storage, "layout": wl.layout,
+                   "bodies": len(wl.bodies),
                    "supersampling_s": [b.s for b in wl.bodies], "bc": list(wl.bc), "parallelism": "1 GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4),

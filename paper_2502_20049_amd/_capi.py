@@ -19,6 +19,7 @@ PSM_BUF_PDF, PSM_BUF_B, PSM_BUF_WORK, PSM_BUF_ADJOINT, PSM_BUF_GRAD_B, PSM_BUF_O
 PSM_SHAPE_ELLIPSOID, PSM_SHAPE_CUBE = 0, 1
 PSM_COLL_TRT, PSM_COLL_CUMULANT = 0, 1
 PSM_MAP_SUBSAMPLES, PSM_MAP_BLOCK = 0, 1
+PSM_LAYOUT_SOA, PSM_LAYOUT_BLOCKED = 0, 1
 PSM_OPT_GENERAL_PATH, PSM_OPT_XCD_REMAP, PSM_OPT_MAP_LIST, PSM_OPT_SOLID_GRID = 1, 2, 4, 8
 PSM_MAX_BODIES = 8
 PSM_STATIC_WORK_BYTES = 16 << 20
@@ -31,7 +32,7 @@ EXPORTS = [
     "psm_stream_collide", "body_force_torque", "psm_mass_fp64", "psm_macroscopic", "psm_error_flags",
     "psm_set_option", "psm_stream_copy", "psm_set_fraction_offset", "psm_adjoint_step", "psm_adjoint_omega",
     "psm_step", "lbm_set_obstacle", "psm_rigid_body", "psm_rigid_advance", "psm_coupled_step", "psm_pdf_stride",
-    "pdf_field_create_noalloc",
+    "pdf_field_create_noalloc", "psm_pdf_layout", "psm_pdf_gather", "psm_pdf_scatter",
 ]
 
 
@@ -46,7 +47,8 @@ class psm_config(C.Structure):
                 ("storage", C.c_int32), ("psm", C.c_int32), ("sc", C.c_int32), ("b_form", C.c_int32),
                 ("slots", C.c_int32), ("max_bodies", C.c_int32), ("bc", C.c_int32 * 6),
                 ("tau", C.c_double), ("magic", C.c_double), ("force", C.c_double * 3),
-                ("u_in", C.c_double * 3), ("collision", C.c_int32), ("map_reading", C.c_int32)]
+                ("u_in", C.c_double * 3), ("collision", C.c_int32), ("map_reading", C.c_int32),
+                ("layout", C.c_int32), ("block_rows", C.c_int32)]
 
 
 class psm_body(C.Structure):
@@ -102,6 +104,9 @@ def _load():
         "psm_rigid_advance": (C.c_int, [C.POINTER(psm_rigid), dp, C.c_double]),
         "psm_coupled_step": (C.c_int, [vp, C.POINTER(psm_rigid), C.POINTER(vp), C.c_int, i64, vp, dp, vp]),
         "psm_pdf_stride": (C.c_int, [C.POINTER(psm_config), C.POINTER(i64)]),
+        "psm_pdf_layout": (C.c_int, [C.POINTER(psm_config), i32p, C.POINTER(i64), C.POINTER(i64)]),
+        "psm_pdf_gather": (C.c_int, [vp, vp, vp]),
+        "psm_pdf_scatter": (C.c_int, [vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)

@@ -10,9 +10,11 @@ is not differentiated (it is piecewise constant in the angle).
 
 Reverse mode uses sqrt(T) checkpointing: the forward keeps the lattice every
 L steps (L even, so checkpoints sit in the standard in-place layout); the
-backward recomputes each segment, storing its L states, then runs L adjoint
-steps (psm_adjoint_step, one HIP kernel per step) from the last to the first.
-All arithmetic runs in the library's kernels; torch only owns the buffers.
+backward recomputes each segment, storing its L states (in the standard
+layout, psm_pdf_gather) and the solid fractions B(t) the recompute mapped, then runs L adjoint steps
+(psm_adjoint_step, one HIP kernel per step) from the last to the first with
+each step's stored B(t) put back (no second mapping).  All arithmetic and
+copies run in the library's kernels; torch only owns the buffers.
 """
 from __future__ import annotations
 
@@ -44,7 +46,9 @@ class TorqueAdjoint:
         self.axis = (C.c_double * 3)(*self.body.motion.axis)
         self.device = device
         self._ckpt = {}
+        self._ckpt_pool = []
         self._store = None
+        self._bstore = None
         self.omega = self.body.motion.omega
         self.dB = None
         self.ft = torch.zeros((self.steps, 6), dtype=torch.float64, device=device)
@@ -76,11 +80,16 @@ class TorqueAdjoint:
         self._set_offset(dB)
         self.field.reset()
         if f0 is not None:
-            self.field.pdf_view().copy_(f0.to(self.field.dtype))
+            self.field.load_pdf_std(f0)
         self._ckpt = {}
+        nck = (self.steps + self.L - 1) // self.L
+        while len(self._ckpt_pool) < nck:
+            self._ckpt_pool.append(torch.empty_like(self.field.pdf))
         for t in range(self.steps):
             if t % self.L == 0:
-                self._ckpt[t] = self.field.pdf.clone()
+                ck = self._ckpt_pool[t // self.L]
+                sim.stream_copy(self.field.pdf, ck)
+                self._ckpt[t] = ck
             self._step(t, ft=self.ft[t])
         a = torch.tensor(list(self.body.motion.axis), dtype=torch.float64, device=self.device)
         w = torch.tensor(self.weights, dtype=torch.float64, device=self.device)
@@ -91,7 +100,8 @@ class TorqueAdjoint:
         q, N = self.q, self.N
         f = self.field
         if self._store is None or len(self._store) < self.L:
-            self._store = [torch.empty_like(f.pdf) for _ in range(self.L)]
+            self._store = [torch.empty((q, N), dtype=f.dtype, device=self.device) for _ in range(self.L)]
+            self._bstore = [torch.empty_like(f.bbuf) for _ in range(self.L)]
         ahat = [torch.zeros((q, N), dtype=self.adt, device=self.device),
                 torch.empty((q, N), dtype=self.adt, device=self.device)]
         gB = torch.zeros(N, dtype=self.adt, device=self.device)
@@ -99,13 +109,17 @@ class TorqueAdjoint:
         stream = sim._stream()
         for s0 in sorted(self._ckpt.keys(), reverse=True):
             s1 = min(s0 + self.L, self.steps)
-            f.pdf.copy_(self._ckpt[s0])
+            # B is put back from the store below, outside the mapping's
+            # bookkeeping: restart the mapping from a cleared field
+            f.reset()
+            sim.stream_copy(self._ckpt[s0], f.pdf)
             for t in range(s0, s1):
-                self._store[t - s0].copy_(f.pdf)
+                f.pdf_std(out=self._store[t - s0])
                 self._step(t)
+                sim.stream_copy(f.bbuf, self._bstore[t - s0])
             for t in range(s1 - 1, s0 - 1, -1):
                 pm, pu = self._poses(t)
-                f.map(t, pm)
+                sim.stream_copy(self._bstore[t - s0], f.bbuf)
                 check(lib.psm_adjoint_step(f.handle, C.c_void_p(self._store[t - s0].data_ptr()), t,
                                            C.c_void_p(ahat[0].data_ptr()), C.c_void_p(ahat[1].data_ptr()),
                                            C.c_void_p(gB.data_ptr()), pu, self.axis, self.weights[t], stream),

@@ -96,7 +96,7 @@ __global__ __launch_bounds__(256) void k_adjoint(const AdjArgs A) {
     // forward state before the step, as deviations d_k = f_k - w_k, and the
     // adjoint gh of the post-collision values (transpose of the streaming)
     const T *fwd = (const T *)A.fwd;
-    const uint64_t FS = a.dS;  // the forward state has the PDF buffer's layout
+    const uint64_t FS = (uint64_t)a.N;  // the forward state is in the standard layout [q][N]
     const R *ain = (const R *)A.ain;
     R d[Q], gh[Q];
     if (bcm == 0) {  // no face direction: plain pulls / pushes with periodic wrap

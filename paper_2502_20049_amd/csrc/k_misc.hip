@@ -25,9 +25,10 @@ template <int Q, typename T>
 __device__ double read_f(const SCArgs &a, int parity, int k, int x, int y, int z, uint64_t n) {
   const uint64_t N = a.dS;  // direction stride
   const T *A = (const T *)a.pdf;
-  if (parity == 0) return (double)A[(uint64_t)k * N + n];
+  const uint64_t e = pdf_row(a, (uint32_t)y + (uint32_t)a.ny * (uint32_t)z) + (uint64_t)x;  // the cell's element
+  if (parity == 0) return (double)A[(uint64_t)k * N + e];
   // obstacle cells are never updated: their own slots hold their values
-  if (a.ocls && a.ocls[n] == 2) return (double)A[(uint64_t)k * N + n];
+  if (a.ocls && a.ocls[n] == 2) return (double)A[(uint64_t)k * N + e];
   const int ex = cx<Q>(k), ey = cy<Q>(k), ez = cz<Q>(k);
   int sx = x - ex, sy = y - ey, sz = z - ez;
   int kd = K_NONE;
@@ -45,10 +46,11 @@ __device__ double read_f(const SCArgs &a, int parity, int k, int x, int y, int z
   }
   if (kd == K_NONE) {
     const uint64_t src = (uint64_t)sx + (uint64_t)a.nx * ((uint64_t)sy + (uint64_t)a.ny * (uint64_t)sz);
-    if (!(a.ocls && a.ocls[src] == 2)) return (double)A[(uint64_t)opp<Q>(k) * N + src];
+    const uint64_t es = pdf_row(a, (uint32_t)sy + (uint32_t)a.ny * (uint32_t)sz) + (uint64_t)sx;
+    if (!(a.ocls && a.ocls[src] == 2)) return (double)A[(uint64_t)opp<Q>(k) * N + es];
     kd = K_WALL;  // link into an obstacle cell: bounce-back, the wall rule
   }
-  double v = (double)A[(uint64_t)k * N + n];
+  double v = (double)A[(uint64_t)k * N + e];
   if (kd == K_INLET) v += 6.0 * wt<Q>(k) * (ex * a.u_in_d[0] + ey * a.u_in_d[1] + ez * a.u_in_d[2]);
   return v;
 }
@@ -132,6 +134,43 @@ hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t st) {
   if (blocks == 0) blocks = 1;
   hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)blocks), dim3(256), 0, st, (uint4 *)p, n16,
                      (unsigned char *)p + n16 * 16, ntail);
+  return hipGetLastError();
+}
+
+// The PDF buffer to (to_std) or from the standard layout [q][N]: one thread
+// per (cell, direction), the cell index running fastest, so both sides are
+// row-contiguous.
+template <typename T>
+__global__ __launch_bounds__(256) void k_pdf_convert(const SCArgs a, int q, T *dst, const T *src, int to_std) {
+  const uint64_t N = a.N, total = N * (uint64_t)q, stride = (uint64_t)gridDim.x * 256u;
+  for (uint64_t i = (uint64_t)blockIdx.x * 256u + threadIdx.x; i < total; i += stride) {
+    const uint32_t k = (uint32_t)(i / N);
+    const uint32_t n = (uint32_t)(i - (uint64_t)k * N);
+    const uint32_t r = n / (uint32_t)a.nx, x = n - r * (uint32_t)a.nx;
+    const uint64_t e = (uint64_t)k * a.dS + pdf_row(a, r) + x;
+    if (to_std) dst[i] = src[e];
+    else dst[e] = src[i];
+  }
+}
+
+hipError_t launch_pdf_gather(const psm_field &f, void *dst, const void *src, int to_std, hipStream_t st) {
+  const SCArgs a = make_sc_args(f);
+  const uint64_t total = (uint64_t)f.N * (uint64_t)f.cfg.q;
+  const uint64_t nblk = (total + 255) / 256;
+  const dim3 g((unsigned)(nblk < (1u << 20) ? nblk : (1u << 20)));
+  switch (f.cfg.storage) {
+    case PSM_F64:
+      hipLaunchKernelGGL(k_pdf_convert<double>, g, dim3(256), 0, st, a, f.cfg.q, (double *)dst, (const double *)src,
+                         to_std);
+      break;
+    case PSM_F32:
+      hipLaunchKernelGGL(k_pdf_convert<float>, g, dim3(256), 0, st, a, f.cfg.q, (float *)dst, (const float *)src,
+                         to_std);
+      break;
+    default:
+      hipLaunchKernelGGL(k_pdf_convert<_Float16>, g, dim3(256), 0, st, a, f.cfg.q, (_Float16 *)dst,
+                         (const _Float16 *)src, to_std);
+  }
   return hipGetLastError();
 }
 

@@ -464,8 +464,10 @@ __device__ __forceinline__ void classify(const SCArgs &a, int x, int y, int z, u
 template <int Q, typename T, int PAR>
 __device__ __forceinline__ char *slot_general(const SCArgs &a, char *pdf, int k, int x, int y, int z, uint64_t n,
                                               uint32_t bcm) {
+  (void)n;
   const size_t NS = (size_t)a.dS * sizeof(T);
-  if (PAR == 0 || ((bcm >> k) & 1u)) return pdf + (size_t)k * NS + (size_t)n * sizeof(T);
+  if (PAR == 0 || ((bcm >> k) & 1u))
+    return pdf + (size_t)k * NS + (pdf_row(a, (uint32_t)y + (uint32_t)a.ny * (uint32_t)z) + (uint64_t)x) * sizeof(T);
   int sx = x - cx<Q>(k), sy = y - cy<Q>(k), sz = z - cz<Q>(k);
   if (sx < 0) sx += a.nx;
   if (sx >= a.nx) sx -= a.nx;
@@ -473,7 +475,7 @@ __device__ __forceinline__ char *slot_general(const SCArgs &a, char *pdf, int k,
   if (sy >= a.ny) sy -= a.ny;
   if (sz < 0) sz += a.nz;
   if (sz >= a.nz) sz -= a.nz;
-  const uint64_t src = (uint64_t)sx + (uint64_t)a.nx * ((uint64_t)sy + (uint64_t)a.ny * (uint64_t)sz);
+  const uint64_t src = pdf_row(a, (uint32_t)sy + (uint32_t)a.ny * (uint32_t)sz) + (uint64_t)sx;
   return pdf + (size_t)opp<Q>(k) * NS + (size_t)src * sizeof(T);
 }
 
@@ -541,6 +543,7 @@ struct RowCell {
   static constexpr uint32_t S = sizeof(T);
   const SCArgs &a;
   int y, z;
+  uint32_t row;  // y + ny z
   bool lo_face, hi_face, xface;
   uint32_t o0, om, op;
   size_t NS, nxy;
@@ -563,7 +566,9 @@ struct RowCell {
     om = (uint32_t)xm * S;
     op = (uint32_t)xp * S;
     NS = (size_t)a.dS * S;
-    own_row = a.pdf + rowbase * S;
+    (void)rowbase;
+    row = (uint32_t)y + (uint32_t)ny * (uint32_t)z;
+    own_row = a.pdf + pdf_row(a, row) * S;
     // y/z face rules of this row (wave-uniform)
     if constexpr (EDGE) {
       const bool py = a.periodic[1] != 0, pz = a.periodic[2] != 0;
@@ -592,18 +597,19 @@ struct RowCell {
   __device__ __forceinline__ char *src_base(K) const {
     constexpr int k = K::value;
     constexpr int ey = cy<Q>(k), ez = cz<Q>(k);
-    char *row;
+    char *rp;
     if constexpr (!EDGE) {
-      row = own_row - ((long long)ey * a.nx + (long long)ez * (long long)nxy) * (long long)S;
+      // interior rows: the source row never wraps
+      rp = a.pdf + pdf_row(a, row - (uint32_t)(ey + ez * a.ny)) * S;
     } else {
       int sy = y - ey, sz = z - ez;
       if (sy < 0) sy += a.ny;
       if (sy >= a.ny) sy -= a.ny;
       if (sz < 0) sz += a.nz;
       if (sz >= a.nz) sz -= a.nz;
-      row = a.pdf + ((size_t)a.nx * (size_t)sy + nxy * (size_t)sz) * S;
+      rp = a.pdf + pdf_row(a, (uint32_t)sy + (uint32_t)a.ny * (uint32_t)sz) * S;
     }
-    return row + (size_t)opp<Q>(k) * NS;
+    return rp + (size_t)opp<Q>(k) * NS;
   }
   template <typename K>
   __device__ __forceinline__ uint32_t src_lane(K) const {

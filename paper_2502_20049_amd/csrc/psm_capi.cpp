@@ -60,12 +60,51 @@ constexpr size_t OFF_MAP_COUNT = 64;
 // consecutive arrays start 4 KiB past a 4 KiB multiple apart (the 19 or 27
 // streams of a step then do not all fall at the same offset modulo a large
 // power of two: measured 1-4% faster on 256^3 than back-to-back arrays).
-static int64_t pdf_stride_elems(const psm_config &c) {
+//
+// Blocked layout: rows (r = y + ny z) in blocks of RB = 2^m rows (by default
+// the largest power of two with RB nx sizeof(storage) <= 16 KiB, at least
+// one row); each block holds its q direction arrays of RB nx cells back to
+// back.
+struct PdfLayout {
+  int lrb;           // log2 RB (SoA: 31)
+  uint32_t rbm;      // RB - 1 (SoA: all ones)
+  int64_t rb;        // rows per block (SoA: ny nz)
+  int64_t dstride;   // elements between direction arrays (within a block)
+  int64_t bstride;   // elements between blocks (SoA: 0)
+  int64_t elems;     // elements of the whole buffer
+};
+
+static PdfLayout pdf_layout_of(const psm_config &c) {
+  PdfLayout L{};
   const int64_t N = (int64_t)c.nx * c.ny * c.nz;
+  const int64_t rows = (int64_t)c.ny * c.nz;
   const int64_t sz = (int64_t)storage_size(c.storage);
-  const int64_t bytes = ((N * sz + 4095) / 4096) * 4096 + 4096;
-  return bytes / sz;
+  if (c.layout == PSM_LAYOUT_BLOCKED) {
+    int m = 0;
+    if (c.block_rows > 0) {
+      while ((1 << m) < c.block_rows) ++m;
+    } else {
+      while (((int64_t)c.nx << (m + 1)) * sz <= 16384 && (1ll << (m + 1)) <= rows) ++m;
+    }
+    L.lrb = m;
+    L.rbm = (1u << m) - 1u;
+    L.rb = 1ll << m;
+    L.dstride = L.rb * c.nx;
+    L.bstride = L.dstride * c.q;
+    L.elems = ((rows + L.rb - 1) >> m) * L.bstride;
+  } else {
+    const int64_t bytes = ((N * sz + 4095) / 4096) * 4096 + 4096;
+    L.lrb = 31;
+    L.rbm = 0xffffffffu;
+    L.rb = rows;
+    L.dstride = bytes / sz;
+    L.bstride = 0;
+    L.elems = L.dstride * c.q;
+  }
+  return L;
 }
+
+static int64_t pdf_stride_elems(const psm_config &c) { return pdf_layout_of(c).dstride; }
 
 static Layout layout_of(const psm_config &c) {
   Layout L{};
@@ -96,6 +135,15 @@ static int check_config(const psm_config *c) {
   if (c->b_form != 0 && c->b_form != 1) return set_error("b_form must be 0 or 1"), PSM_EINVAL;
   if (c->map_reading != PSM_MAP_SUBSAMPLES && c->map_reading != PSM_MAP_BLOCK)
     return set_error("map_reading must be PSM_MAP_SUBSAMPLES or PSM_MAP_BLOCK"), PSM_EINVAL;
+  if (c->layout != PSM_LAYOUT_SOA && c->layout != PSM_LAYOUT_BLOCKED)
+    return set_error("layout must be PSM_LAYOUT_SOA or PSM_LAYOUT_BLOCKED"), PSM_EINVAL;
+  if (c->block_rows != 0) {
+    if (c->layout != PSM_LAYOUT_BLOCKED) return set_error("block_rows needs PSM_LAYOUT_BLOCKED"), PSM_EINVAL;
+    const int64_t rows = (int64_t)c->ny * c->nz;
+    if (c->block_rows < 0 || (c->block_rows & (c->block_rows - 1)) != 0 || c->block_rows > 2 * rows ||
+        (int64_t)c->block_rows * c->nx * c->q > ((int64_t)1 << 32))
+      return set_error("block_rows must be a power of two, at most twice the row count"), PSM_EINVAL;
+  }
   if (c->slots != 1 && c->slots != 2) return set_error("slots must be 1 or 2"), PSM_EINVAL;
   if (c->psm && (c->max_bodies < 1 || c->max_bodies > PSM_MAX_BODIES))
     return set_error("max_bodies must be in 1..8"), PSM_EINVAL;
@@ -128,6 +176,9 @@ SCArgs make_sc_args(const psm_field &f) {
   a.nz = c.nz;
   a.N = (uint32_t)f.N;
   a.dS = (uint64_t)f.dstride;
+  a.lrb = f.lrb;
+  a.rbm = f.rbm;
+  a.bst = (uint64_t)f.bstride;
   a.TX = f.TX;
   a.TY = f.TY;
   a.lTX = f.lTX;
@@ -243,7 +294,7 @@ int psm_required_bytes(const psm_config *cfg, int which, size_t *out) {
   const Layout L = layout_of(*cfg);
   switch (which) {
     case PSM_BUF_PDF:
-      *out = (size_t)cfg->q * (size_t)pdf_stride_elems(*cfg) * storage_size(cfg->storage);
+      *out = (size_t)pdf_layout_of(*cfg).elems * storage_size(cfg->storage);
       return PSM_OK;
     case PSM_BUF_B:
       *out = cfg->psm ? (size_t)L.N * 4 * cfg->slots + (size_t)L.N : 0;
@@ -269,6 +320,16 @@ int psm_pdf_stride(const psm_config *cfg, int64_t *elems) {
   if (r) return r;
   if (!elems) return set_error("null output"), PSM_EINVAL;
   *elems = pdf_stride_elems(*cfg);
+  return PSM_OK;
+}
+
+int psm_pdf_layout(const psm_config *cfg, int32_t *rows_per_block, int64_t *dir_stride, int64_t *block_stride) {
+  int r = check_config(cfg);
+  if (r) return r;
+  const PdfLayout L = pdf_layout_of(*cfg);
+  if (rows_per_block) *rows_per_block = (int32_t)L.rb;
+  if (dir_stride) *dir_stride = L.dstride;
+  if (block_stride) *block_stride = L.bstride;
   return PSM_OK;
 }
 
@@ -335,7 +396,13 @@ static int field_create(const psm_config *cfg, void *pdf, size_t pdf_bytes, void
   f->pdf = pdf;
   f->pdf_bytes = pdf_bytes;
   f->N = L.N;
-  f->dstride = pdf_stride_elems(*cfg);
+  {
+    const PdfLayout PL = pdf_layout_of(*cfg);
+    f->dstride = PL.dstride;
+    f->lrb = PL.lrb;
+    f->rbm = PL.rbm;
+    f->bstride = PL.bstride;
+  }
   if (cfg->psm) {
     f->B0 = (float *)b;
     f->B1 = cfg->slots == 2 ? (float *)b + L.N : nullptr;
@@ -1049,6 +1116,26 @@ int psm_adjoint_omega(psm_field *f, double *out, void *stream) {
   hipError_t e = launch_sum_accumulate(f->red, f->red_count, out, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "psm_adjoint_omega launch");
   return PSM_OK;
+}
+
+static int pdf_convert(psm_field *f, void *dst, const void *src, int to_std, void *stream) {
+  if (!f || !dst || !src) return set_error("null argument"), PSM_EINVAL;
+  const size_t bytes = (size_t)f->cfg.q * (size_t)f->N * storage_size(f->cfg.storage);
+  const char *p = (const char *)f->pdf, *o = (const char *)(to_std ? dst : src);
+  size_t pb;
+  psm_required_bytes(&f->cfg, PSM_BUF_PDF, &pb);
+  if (o < p + pb && p < o + bytes) return set_error("the standard-layout array overlaps the PDF buffer"), PSM_EINVAL;
+  hipError_t e = launch_pdf_gather(*f, dst, src, to_std, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "psm_pdf_gather / psm_pdf_scatter launch");
+  return PSM_OK;
+}
+
+int psm_pdf_gather(psm_field *f, void *dst, void *stream) {
+  return pdf_convert(f, dst, f ? f->pdf : nullptr, 1, stream);
+}
+
+int psm_pdf_scatter(psm_field *f, const void *src, void *stream) {
+  return pdf_convert(f, f ? f->pdf : nullptr, src, 0, stream);
 }
 
 int psm_error_flags(psm_field *f, int32_t *out, void *stream) {

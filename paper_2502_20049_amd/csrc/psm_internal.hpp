@@ -99,7 +99,12 @@ struct SCArgs {
   double *ftp;      // [solid workgroup][max_bodies][6]
   int nx, ny, nz;
   uint32_t N;
-  uint64_t dS;  // elements between consecutive direction arrays of the PDF buffer
+  uint64_t dS;  // elements between consecutive direction arrays of the PDF buffer (within a block)
+  // PDF layout: row r = y + ny z starts at element (r >> lrb) * bst + (r & rbm) * nx
+  // of direction array 0 (SoA: lrb = 31, rbm = all ones, bst = 0)
+  int lrb;
+  uint32_t rbm;
+  uint64_t bst;
   int TX, TY, lTX;  // tile shape of the interior kernel, log2(TX)
   int ntx;
   int nty_i;          // tile rows over the interior rows 1..ny-2
@@ -136,6 +141,11 @@ struct SCArgs {
   IBox obox;              // bounding box of the class-1 and class-2 cells
 };
 
+// element offset of row r (= y + ny z) in direction array 0 of the PDF buffer
+__host__ __device__ __forceinline__ uint64_t pdf_row(const SCArgs &a, uint32_t r) {
+  return (uint64_t)(r >> a.lrb) * a.bst + (uint64_t)(r & a.rbm) * (uint64_t)(uint32_t)a.nx;
+}
+
 // header of the obstacle buffer (set-up counters)
 struct ObstHdr {
   uint32_t count;
@@ -146,7 +156,7 @@ struct ObstHdr {
 // arguments of the adjoint step kernel
 struct AdjArgs {
   SCArgs s;           // field geometry, faces, rates, B pointers
-  const char *fwd;    // forward state before step t (storage type, parity t&1)
+  const char *fwd;    // forward state before step t (storage type, parity t&1), [q][N]
   int parity;
   const void *ain;    // fhat(t+1), [q][N], adjoint precision
   void *aout;         // fhat(t)
@@ -219,7 +229,10 @@ struct psm_field {
   bool static_work;     // work area: the library's static array (pdf_field_create_noalloc)
   size_t red_count;
   int64_t N;
-  int64_t dstride;  // direction stride of the PDF buffer, elements
+  int64_t dstride;  // direction stride of the PDF buffer, elements (within a block)
+  int lrb;          // PDF layout: log2 rows per block (SoA: 31), row mask, block stride
+  uint32_t rbm;
+  int64_t bstride;
   int TX, TY, lTX, ntx, nty;
   int64_t ntiles;
   int nb_mapped;
@@ -265,6 +278,7 @@ hipError_t launch_macro(const psm_field &f, int parity, double *rho, double *u, 
 hipError_t launch_mass_final(const double *partials, uint32_t n, double *out, hipStream_t st);
 hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t st);
 hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t st);
+hipError_t launch_pdf_gather(const psm_field &f, void *dst, const void *src, int to_std, hipStream_t st);
 hipError_t launch_flags_copy(const int32_t *src, int32_t *dst, hipStream_t st);
 uint32_t macro_blocks(const psm_field &f);
 hipError_t launch_sum_accumulate(const double *p, uint32_t n, double *out, hipStream_t st);

@@ -49,6 +49,8 @@ def make_config(wl, storage=None, psm=True, slots=None, max_bodies=None) -> capi
     cfg.u_in = (C.c_double * 3)(*wl.u_in)
     cfg.collision = {"trt": capi.PSM_COLL_TRT, "cumulant": capi.PSM_COLL_CUMULANT}[getattr(wl, "collision", "trt")]
     cfg.map_reading = getattr(wl, "map_reading", 0)
+    cfg.layout = {"soa": capi.PSM_LAYOUT_SOA, "blocked": capi.PSM_LAYOUT_BLOCKED}[getattr(wl, "layout", "soa")]
+    cfg.block_rows = getattr(wl, "block_rows", 0)
     return cfg
 
 
@@ -156,8 +158,27 @@ class Field:
     # -- buffers ---------------------------------------------------------
     def pdf_view(self):
         """(q, N) view of the stored deviations f_k - w_k (library direction
-        order); rows are psm_pdf_stride elements apart in the buffer."""
+        order) of a SoA field; rows are psm_pdf_stride elements apart in the
+        buffer.  Blocked fields have no such view: use pdf_std / load_pdf_std."""
+        if self.cfg.layout != capi.PSM_LAYOUT_SOA:
+            raise ValueError("a blocked PDF buffer has no (q, N) view; use pdf_std() / load_pdf_std()")
         return self.pdf.as_strided((self.q, self.N), (self.dstride, 1))
+
+    def pdf_std(self, out=None):
+        """The stored slots as a (q, N) tensor in the standard layout
+        (psm_pdf_gather; a copy, either layout)."""
+        out = torch.empty((self.q, self.N), dtype=self.dtype, device=self.pdf.device) if out is None else out
+        assert out.is_contiguous() and out.dtype == self.dtype and tuple(out.shape) == (self.q, self.N)
+        check(lib.psm_pdf_gather(self.handle, C.c_void_p(out.data_ptr()), _stream()), "psm_pdf_gather")
+        return out
+
+    def load_pdf_std(self, src):
+        """Set the stored slots from a (q, N) tensor in the standard layout
+        (psm_pdf_scatter; either layout)."""
+        src = src.to(device=self.pdf.device, dtype=self.dtype).contiguous()
+        assert tuple(src.shape) == (self.q, self.N)
+        check(lib.psm_pdf_scatter(self.handle, C.c_void_p(src.data_ptr()), _stream()), "psm_pdf_scatter")
+        torch.cuda.current_stream().synchronize()
 
     def b_view(self):
         """(slots, N) float32 solid fractions and (N,) uint8 body ids."""

@@ -364,6 +364,8 @@ class Workload:
     bodies: list = field(default_factory=list)
     collision: str = "trt"    # "trt" or "cumulant" (D3Q27, no body force)
     map_reading: int = 0      # 0: every sub-sample rotated; 1: centre rotated, axis-aligned block
+    layout: str = "soa"       # PDF buffer layout: "soa" or "blocked"
+    block_rows: int = 0       # rows per block of the blocked layout (0: the library's choice)
 
     @property
     def n_cells(self):

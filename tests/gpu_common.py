@@ -24,7 +24,7 @@ def load_random_state(field, seed, amp=8.0):
     sim = lib_sim()
     c, _, _ = sim.lattice(field.q)
     st = pi.random_state_torch(seed, c, field.N, field.pdf.device, field.dtype, amp)
-    field.pdf_view().copy_(st)
+    field.load_pdf_std(st)
     torch.cuda.synchronize()
 
 
@@ -39,7 +39,7 @@ def gpu_state_oracle_order(field, orc, sim):
     call after an even number of steps)."""
     idx = perm_to_oracle(orc, sim, field.q)
     _, ow, _ = orc.lattice(field.q)
-    d = field.pdf_view().double().cpu().numpy()
+    d = field.pdf_std().double().cpu().numpy()
     return ow[:, None] + d[idx]
 
 

@@ -84,6 +84,7 @@ def test_noalloc_rejects_lattices_beyond_the_static_area(capi, sim):
 @pytest.mark.parametrize("field,value,code", [
     ("q", 15, -1), ("storage", 7, -1), ("sc", 4, -1), ("slots", 3, -1), ("tau", 0.5, -1),
     ("b_form", 2, -1), ("max_bodies", 9, -1), ("nx", 0, -1), ("map_reading", 2, -1), ("map_reading", -1, -1),
+    ("layout", 2, -1), ("block_rows", 4, -1),
 ])
 def test_config_validation(capi, sim, field, value, code):
     cfg = _cfg(sim)
@@ -272,3 +273,33 @@ def test_new_entry_points_reject_null_arguments(capi, sim):
     assert capi.lib.psm_rigid_body(None, None) == capi.PSM_EINVAL
     s = capi.psm_rigid()
     assert capi.lib.psm_rigid_advance(C.byref(s), None, 1.0) == capi.PSM_EINVAL
+
+
+@pytest.mark.parametrize("shape,storage,rows", [((70, 22, 13), 1, 0), ((256, 256, 256), 1, 0), ((256, 8, 8), 2, 0),
+                                                ((1024, 4, 4), 0, 0), ((70, 22, 13), 1, 8), ((5, 3, 2), 2, 8)])
+def test_blocked_layout_sizes(capi, sim, shape, storage, rows):
+    """psm_pdf_layout and the PDF buffer size agree: blocks of RB rows (a
+    power of two; by default RB*nx*sizeof <= 16 KiB), q*RB*nx elements
+    each, the last block padded."""
+    cfg = _cfg(sim)
+    cfg.nx, cfg.ny, cfg.nz = shape
+    cfg.storage = storage
+    cfg.layout = capi.PSM_LAYOUT_BLOCKED
+    cfg.block_rows = rows
+    rb, ds, bs = C.c_int32(), C.c_int64(), C.c_int64()
+    assert capi.lib.psm_pdf_layout(C.byref(cfg), C.byref(rb), C.byref(ds), C.byref(bs)) == 0
+    nx, ny, nz = shape
+    sz = {0: 8, 1: 4, 2: 2}[storage]
+    RB = rb.value
+    assert RB & (RB - 1) == 0
+    if rows:
+        assert RB == rows
+    else:
+        assert RB == 1 or RB * nx * sz <= 16384
+        assert 2 * RB > ny * nz or 2 * RB * nx * sz > 16384
+    assert ds.value == RB * nx and bs.value == cfg.q * RB * nx
+    n = C.c_size_t()
+    assert capi.lib.psm_required_bytes(C.byref(cfg), capi.PSM_BUF_PDF, C.byref(n)) == 0
+    assert n.value == -(-(ny * nz) // RB) * bs.value * sz
+    st = C.c_int64()
+    assert capi.lib.psm_pdf_stride(C.byref(cfg), C.byref(st)) == 0 and st.value == ds.value
