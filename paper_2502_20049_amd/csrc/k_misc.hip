@@ -137,41 +137,54 @@ hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t st) {
   return hipGetLastError();
 }
 
-// The PDF buffer to (to_std) or from the standard layout [q][N]: one thread
-// per (cell, direction), the cell index running fastest, so both sides are
-// row-contiguous.
+// The PDF buffer to (to_std) or from the standard layout [q][N]: a workgroup
+// per 256-cell piece of one row and direction (blockIdx.y = direction), so
+// both sides are contiguous along the row.
 template <typename T>
-__global__ __launch_bounds__(256) void k_pdf_convert(const SCArgs a, int q, T *dst, const T *src, int to_std) {
-  const uint64_t N = a.N, total = N * (uint64_t)q, stride = (uint64_t)gridDim.x * 256u;
-  for (uint64_t i = (uint64_t)blockIdx.x * 256u + threadIdx.x; i < total; i += stride) {
-    const uint32_t k = (uint32_t)(i / N);
-    const uint32_t n = (uint32_t)(i - (uint64_t)k * N);
-    const uint32_t r = n / (uint32_t)a.nx, x = n - r * (uint32_t)a.nx;
-    const uint64_t e = (uint64_t)k * a.dS + pdf_row(a, r) + x;
-    if (to_std) dst[i] = src[e];
-    else dst[e] = src[i];
-  }
+__global__ __launch_bounds__(256) void k_pdf_convert(const SCArgs a, uint32_t ntx, T *dst, const T *src, int to_std) {
+  const uint32_t k = blockIdx.y;
+  const uint32_t r = blockIdx.x / ntx;  // row y + ny z
+  const uint32_t x = (blockIdx.x - r * ntx) * 256u + threadIdx.x;
+  if (x >= (uint32_t)a.nx) return;
+  const uint64_t i = (uint64_t)k * a.N + (uint64_t)r * (uint32_t)a.nx + x;
+  const uint64_t e = (uint64_t)k * a.dS + pdf_row(a, r) + x;
+  if (to_std) dst[i] = src[e];
+  else dst[e] = src[i];
 }
 
 hipError_t launch_pdf_gather(const psm_field &f, void *dst, const void *src, int to_std, hipStream_t st) {
   const SCArgs a = make_sc_args(f);
-  const uint64_t total = (uint64_t)f.N * (uint64_t)f.cfg.q;
-  const uint64_t nblk = (total + 255) / 256;
-  const dim3 g((unsigned)(nblk < (1u << 20) ? nblk : (1u << 20)));
-  switch (f.cfg.storage) {
-    case PSM_F64:
-      hipLaunchKernelGGL(k_pdf_convert<double>, g, dim3(256), 0, st, a, f.cfg.q, (double *)dst, (const double *)src,
-                         to_std);
-      break;
-    case PSM_F32:
-      hipLaunchKernelGGL(k_pdf_convert<float>, g, dim3(256), 0, st, a, f.cfg.q, (float *)dst, (const float *)src,
-                         to_std);
-      break;
-    default:
-      hipLaunchKernelGGL(k_pdf_convert<_Float16>, g, dim3(256), 0, st, a, f.cfg.q, (_Float16 *)dst,
-                         (const _Float16 *)src, to_std);
+  const uint32_t ntx = (uint32_t)((f.cfg.nx + 255) / 256);
+  const uint64_t rows = (uint64_t)f.cfg.ny * (uint64_t)f.cfg.nz;
+  // one launch per slab of rows so that the grid's x dimension stays below 2^31
+  uint64_t per = ((1ull << 31) - 1) / ntx;
+  if (a.bst != 0) per &= ~((1ull << a.lrb) - 1ull);  // whole blocks per launch
+  for (uint64_t r0 = 0; r0 < rows; r0 += per) {
+    const uint64_t nr = rows - r0 < per ? rows - r0 : per;
+    SCArgs b = a;
+    // rows r0 .. r0 + nr - 1: shift the views so the kernel's row index starts at 0
+    const size_t sz = f.cfg.storage == PSM_F64 ? 8 : (f.cfg.storage == PSM_F32 ? 4 : 2);
+    const uint64_t std_off = r0 * (uint64_t)f.cfg.nx;
+    if (r0 % (1ull << a.lrb) != 0 && a.bst != 0) return hipErrorInvalidValue;  // slabs start on block boundaries
+    const uint64_t lay_off = pdf_row(a, (uint32_t)r0);
+    const char *s = (const char *)src + (to_std ? lay_off : std_off) * sz;
+    char *d = (char *)dst + (to_std ? std_off : lay_off) * sz;
+    const dim3 g((unsigned)(nr * ntx), (unsigned)f.cfg.q);
+    switch (f.cfg.storage) {
+      case PSM_F64:
+        hipLaunchKernelGGL(k_pdf_convert<double>, g, dim3(256), 0, st, b, ntx, (double *)d, (const double *)s, to_std);
+        break;
+      case PSM_F32:
+        hipLaunchKernelGGL(k_pdf_convert<float>, g, dim3(256), 0, st, b, ntx, (float *)d, (const float *)s, to_std);
+        break;
+      default:
+        hipLaunchKernelGGL(k_pdf_convert<_Float16>, g, dim3(256), 0, st, b, ntx, (_Float16 *)d, (const _Float16 *)s,
+                           to_std);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
   }
-  return hipGetLastError();
+  return hipSuccess;
 }
 
 __global__ __launch_bounds__(256) void k_copy(const uint4 *__restrict__ s, uint4 *__restrict__ d, size_t n16) {

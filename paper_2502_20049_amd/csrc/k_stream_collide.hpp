@@ -875,6 +875,39 @@ __device__ __forceinline__ void fluid_seg_h2(const SCArgs &a, int x0, int y, int
     sfor<Q>([&](auto K) { o[(int)K].y = (T)f[opp<Q>((int)K)]; });
     if (cb.xface && actb) face_store(cb, f, chb);
   }
+  // every cell of the segment is a fluid cell away from the x faces (the
+  // common case): the stores need no per-lane conditions but the wave's edges
+  if (__all(acta && actb && !ca.xface && !cb.xface)) {
+    sfor<Q>([&](auto K) {
+      constexpr int k = K;
+      constexpr int ex = cx<Q>(k);
+      char *const rowk = ca.src_base(K);
+      if constexpr (ex == 0) {
+        *(H2 *)(rowk + oa) = o[k];
+      } else if constexpr (ex == 1) {
+        // element xa <- cell b, element xa + 1 <- cell a of the next lane
+        // (lane 63: the next wave's, which stores it), element x0 - 1 <- cell a of lane 0
+        const H2 nx_ = shl_pair(o[k]);
+        H2 v;
+        v.x = o[k].y;
+        v.y = nx_.x;
+        if (lane < 63) *(H2 *)(rowk + oa) = v;
+        else *(T *)(rowk + oa) = o[k].y;
+        if (lane == 0) *(T *)(rowk + om0) = o[k].x;
+      } else {
+        // element xa <- cell b of the previous lane (lane 0: the previous
+        // wave's), element xa + 1 <- cell a, element x0 + 128 <- cell b of lane 63
+        const H2 pv = shr_pair(o[k]);
+        H2 v;
+        v.x = pv.y;
+        v.y = o[k].x;
+        if (lane > 0) *(H2 *)(rowk + oa) = v;
+        else *(T *)(rowk + oa + sizeof(T)) = o[k].x;
+        if (lane == 63) *(T *)(rowk + op63) = o[k].y;
+      }
+    });
+    return;
+  }
   const bool acta_n = wave_shl1(acta), actb_p = wave_shr1(actb);
   auto put2 = [&](char *q, T lo, bool lo_ok, T hi, bool hi_ok) {
     if (lo_ok && hi_ok) {
