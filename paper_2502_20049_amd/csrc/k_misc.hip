@@ -137,51 +137,61 @@ hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t st) {
   return hipGetLastError();
 }
 
-// The PDF buffer to (to_std) or from the standard layout [q][N]: a workgroup
-// per 256-cell piece of one row and direction (blockIdx.y = direction), so
-// both sides are contiguous along the row.
-template <typename T>
-__global__ __launch_bounds__(256) void k_pdf_convert(const SCArgs a, uint32_t ntx, T *dst, const T *src, int to_std) {
+// The PDF buffer to (to_std) or from the standard layout [q][N]: thread t of
+// direction blockIdx.y takes the t-th run of V cells of a slab of rows (row
+// t / (nx/V)), so both sides are contiguous along the rows; V elements per
+// access (16 bytes when every row start is 16-byte aligned).
+template <typename T, int V>
+__global__ __launch_bounds__(256) void k_pdf_convert(const SCArgs a, uint32_t total, T *dst, const T *src, int to_std) {
+  typedef T vec __attribute__((ext_vector_type(V)));
   const uint32_t k = blockIdx.y;
-  const uint32_t r = blockIdx.x / ntx;  // row y + ny z
-  const uint32_t x = (blockIdx.x - r * ntx) * 256u + threadIdx.x;
-  if (x >= (uint32_t)a.nx) return;
-  const uint64_t i = (uint64_t)k * a.N + (uint64_t)r * (uint32_t)a.nx + x;
-  const uint64_t e = (uint64_t)k * a.dS + pdf_row(a, r) + x;
-  if (to_std) dst[i] = src[e];
-  else dst[e] = src[i];
+  const uint32_t nx = (uint32_t)a.nx, nxv = nx / V;
+  const uint32_t stride = gridDim.x * 256u;
+  for (uint32_t t = blockIdx.x * 256u + threadIdx.x; t < total; t += stride) {
+    const uint32_t r = t / nxv;  // row y + ny z within the slab
+    const uint32_t x = (t - r * nxv) * V;
+    const uint64_t i = (uint64_t)k * a.N + (uint64_t)r * nx + x;
+    const uint64_t e = (uint64_t)k * a.dS + pdf_row(a, r) + x;
+    if (to_std) *(vec *)(dst + i) = *(const vec *)(src + e);
+    else *(vec *)(dst + e) = *(const vec *)(src + i);
+  }
+}
+
+template <typename T>
+static hipError_t convert_slab(const SCArgs &a, int q, uint64_t nr, T *d, const T *s, int to_std, hipStream_t st) {
+  // 16-byte accesses when a row is a whole number of them (every row start,
+  // in either layout and in the standard array, is a multiple of nx elements
+  // from a 256-byte aligned base)
+  constexpr int V = 16 / (int)sizeof(T);
+  const bool vec = ((size_t)a.nx * sizeof(T)) % 16 == 0 && ((uintptr_t)d % 16) == 0 && ((uintptr_t)s % 16) == 0;
+  const uint32_t total = (uint32_t)(nr * (uint64_t)(a.nx / (vec ? V : 1)));
+  const uint32_t blocks = (total + 255) / 256;
+  const dim3 g(blocks < 4096u ? blocks : 4096u, (unsigned)q);
+  if (vec) hipLaunchKernelGGL((k_pdf_convert<T, V>), g, dim3(256), 0, st, a, total, d, s, to_std);
+  else hipLaunchKernelGGL((k_pdf_convert<T, 1>), g, dim3(256), 0, st, a, total, d, s, to_std);
+  return hipGetLastError();
 }
 
 hipError_t launch_pdf_gather(const psm_field &f, void *dst, const void *src, int to_std, hipStream_t st) {
   const SCArgs a = make_sc_args(f);
-  const uint32_t ntx = (uint32_t)((f.cfg.nx + 255) / 256);
   const uint64_t rows = (uint64_t)f.cfg.ny * (uint64_t)f.cfg.nz;
-  // one launch per slab of rows so that the grid's x dimension stays below 2^31
-  uint64_t per = ((1ull << 31) - 1) / ntx;
-  if (a.bst != 0) per &= ~((1ull << a.lrb) - 1ull);  // whole blocks per launch
+  // slabs of rows whose thread count fits 32 bits, starting on block boundaries
+  uint64_t per = ((1ull << 31) - 1) / (uint64_t)f.cfg.nx;
+  if (a.bst != 0) per &= ~((1ull << a.lrb) - 1ull);
+  const size_t sz = f.cfg.storage == PSM_F64 ? 8 : (f.cfg.storage == PSM_F32 ? 4 : 2);
   for (uint64_t r0 = 0; r0 < rows; r0 += per) {
     const uint64_t nr = rows - r0 < per ? rows - r0 : per;
-    SCArgs b = a;
-    // rows r0 .. r0 + nr - 1: shift the views so the kernel's row index starts at 0
-    const size_t sz = f.cfg.storage == PSM_F64 ? 8 : (f.cfg.storage == PSM_F32 ? 4 : 2);
+    // rows r0 .. r0 + nr - 1: shift the pointers so the kernel's row index starts at 0
     const uint64_t std_off = r0 * (uint64_t)f.cfg.nx;
-    if (r0 % (1ull << a.lrb) != 0 && a.bst != 0) return hipErrorInvalidValue;  // slabs start on block boundaries
     const uint64_t lay_off = pdf_row(a, (uint32_t)r0);
     const char *s = (const char *)src + (to_std ? lay_off : std_off) * sz;
     char *d = (char *)dst + (to_std ? std_off : lay_off) * sz;
-    const dim3 g((unsigned)(nr * ntx), (unsigned)f.cfg.q);
+    hipError_t e;
     switch (f.cfg.storage) {
-      case PSM_F64:
-        hipLaunchKernelGGL(k_pdf_convert<double>, g, dim3(256), 0, st, b, ntx, (double *)d, (const double *)s, to_std);
-        break;
-      case PSM_F32:
-        hipLaunchKernelGGL(k_pdf_convert<float>, g, dim3(256), 0, st, b, ntx, (float *)d, (const float *)s, to_std);
-        break;
-      default:
-        hipLaunchKernelGGL(k_pdf_convert<_Float16>, g, dim3(256), 0, st, b, ntx, (_Float16 *)d, (const _Float16 *)s,
-                           to_std);
+      case PSM_F64: e = convert_slab<double>(a, f.cfg.q, nr, (double *)d, (const double *)s, to_std, st); break;
+      case PSM_F32: e = convert_slab<float>(a, f.cfg.q, nr, (float *)d, (const float *)s, to_std, st); break;
+      default: e = convert_slab<_Float16>(a, f.cfg.q, nr, (_Float16 *)d, (const _Float16 *)s, to_std, st);
     }
-    hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
