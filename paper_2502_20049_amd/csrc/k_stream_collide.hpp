@@ -948,7 +948,8 @@ __device__ __forceinline__ void fluid_seg_h2(const SCArgs &a, int x0, int y, int
 template <int Q, bool PSM, int CM = 0>
 __global__ __launch_bounds__(256) void k_fluid_h2odd(const SCArgs a) {
   const int nsx = a.nx / 128;
-  const uint32_t seg = blockIdx.x * 4u + (threadIdx.x >> 6);
+  // wave-uniform (one segment per wave): the row arithmetic stays scalar
+  const uint32_t seg = (uint32_t)__builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4u + (threadIdx.x >> 6)));
   const uint32_t nseg = (uint32_t)nsx * (uint32_t)(a.ny - 2) * (uint32_t)(a.nz - 2);
   if (seg >= nseg) return;  // wave-uniform
   const int sx = (int)(seg % (uint32_t)nsx);
