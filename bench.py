@@ -303,8 +303,12 @@ def settling_sphere(steps=4000):
 
 def adjoint_rate(steps=800, window=200):
     """Torque-gradient sweep on the 128^3 4-blade rotor: J = mean axial torque
-    over the last 200 of 800 steps; forward (with checkpoints) and backward
-    (recompute + adjoint) wall times."""
+    over the last 200 of 800 steps, in both trajectory modes: sqrt(T)
+    checkpoints (forward with checkpoints; backward = recompute + store +
+    adjoint, about 472 B per cell-step) and, where the device holds it, the
+    whole trajectory kept by the forward (forward + state copies; backward =
+    adjoint steps only, about 250 B per cell-step).  Wall times of a second
+    sweep; the two modes' J and gradients are bit-identical."""
     import numpy as np
     import torch
 
@@ -314,21 +318,44 @@ def adjoint_rate(steps=800, window=200):
     wl = lay(pi.workload_adjoint_rotor(steps=steps))
     w = np.zeros(steps)
     w[-window:] = 1.0 / window
-    obj = adjoint.TorqueAdjoint(wl, steps, w)
-    obj.forward()
-    obj.backward()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    J = obj.forward()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    _, gW, _ = obj.backward()
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
     N = wl.n_cells
-    return {"case": f"{wl.name}, {steps} steps, window {window}, checkpoint segment {obj.L}",
-            "J": J, "dJ_dOmega": gW, "forward_s": round(t1 - t0, 4), "backward_s": round(t2 - t1, 4),
-            "backward_mcell_steps_per_s": round(N * steps / (t2 - t1) / 1e6, 1)}
+    out = {"case": f"{wl.name}, {steps} steps, window {window}"}
+    res = {}
+    for mode in ("sqrtT", "whole"):
+        torch.cuda.empty_cache()
+        obj = adjoint.TorqueAdjoint(wl, steps, w, store_all=None if mode == "whole" else False)
+        if mode == "whole" and not obj.store_all:
+            out[mode] = {"skipped": "trajectory larger than half the free device memory"}
+            continue
+        obj.forward()
+        obj.backward()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        J = obj.forward()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        gB, gW, _ = obj.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        res[mode] = (J, gW, gB.clone())
+        bpcs = 472 if mode == "sqrtT" else 250
+        rate = N * steps / (t2 - t1)
+        out[mode] = {"J": J, "dJ_dOmega": gW, "forward_s": round(t1 - t0, 4), "backward_s": round(t2 - t1, 4),
+                     "backward_mcell_steps_per_s": round(rate / 1e6, 1),
+                     "backward_bytes_per_cell_step": bpcs,
+                     "backward_frac_of_8TBs": round(rate * bpcs / 8e12, 3)}
+        if mode == "sqrtT":
+            out[mode]["checkpoint_segment"] = obj.L
+        else:
+            out[mode]["trajectory_GB"] = round(obj.trajectory_bytes / 1e9, 1)
+        del obj, gB
+    if len(res) == 2:
+        a, b = res["sqrtT"], res["whole"]
+        out["modes_bit_identical"] = bool(a[0] == b[0] and a[1] == b[1] and torch.equal(a[2], b[2]))
+    out["sqrtT_ceiling_mcell_steps_per_s"] = round(8e12 / 472 / 1e6, 0)
+    del res
+    torch.cuda.empty_cache()
+    return out
 
 
 def _cpu_model():

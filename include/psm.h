@@ -163,8 +163,9 @@ const char *psm_last_error(void);
  *   WORK flags + force/torque partials (max_bodies*6 doubles per solid-kernel
  *        workgroup, 2048 of them) + reduction scratch + the mapping's lists
  *        of surface cells (psm ? max_bodies * 2^21 * 4 bytes : 0)
- *   ADJOINT  one adjoint PDF buffer of psm_adjoint_step: q*N values in the
- *        adjoint precision (FP64 for PSM_F64 fields, else FP32)
+ *   ADJOINT  one adjoint PDF buffer of psm_adjoint_step: q arrays of N
+ *        adjoint-precision values (FP64 for PSM_F64 fields, else FP32),
+ *        psm_adjoint_stride elements apart
  *   GRAD_B   the dJ/dB accumulator of psm_adjoint_step: N adjoint-precision
  *        values
  *   OBSTACLE  lbm_set_obstacle's buffer (plain-LBM fields; 0 for psm = 1):
@@ -177,6 +178,11 @@ int psm_required_bytes(const psm_config *cfg, int which, size_t *out_bytes);
  * 4 KiB (so the arrays do not all start at the same offset modulo a large
  * power of two).  PSM_LAYOUT_BLOCKED: RB*nx, within a block. */
 int psm_pdf_stride(const psm_config *cfg, int64_t *elems);
+
+/* Elements between the starts of consecutive direction arrays of an adjoint
+ * buffer (PSM_BUF_ADJOINT): N rounded up to a 4 KiB multiple in bytes of the
+ * adjoint precision, plus 4 KiB.  Element (k, n) is at k*stride + n. */
+int psm_adjoint_stride(const psm_config *cfg, int64_t *elems);
 
 /* The PDF buffer layout of cfg (see psm_config.layout): rows per block RB
  * (SoA: ny*nz, one block), the direction stride in elements (as
@@ -405,11 +411,13 @@ int psm_pdf_scatter(psm_field *f, const void *src, void *stream);
  * convention: the fractions B(t) are inputs (call geometry_map_step for this
  * step first); the rotation rate enters through u_s = V + W x (x - X) only.
  * Needs a PSM field with TRT collision, sc = 1, slots = 1 and one mapped body.
- *   fwd_pdf   the forward state before step `step` (parity step&1) as q
- *             arrays of N values, element k*N + n, in the field's storage
- *             type: what psm_pdf_gather writes from the PDF buffer
- *   ahat_in   adjoint of f(step+1): [q][N] (element k*N + n, unpadded),
- *             standard layout, adjoint precision
+ *   fwd_pdf   the forward state before step `step` (parity step&1): a copy
+ *             of the field's PDF buffer (psm_required_bytes PSM_BUF_PDF
+ *             bytes, the field's layout and storage type), e.g. made by
+ *             psm_stream_copy before the step
+ *   ahat_in   adjoint of f(step+1): q arrays of N values in the adjoint
+ *             precision, psm_adjoint_stride elements apart (element
+ *             k*stride + n, n = x + nx*(y + ny*z)); the padding is not read
  *   ahat_out  adjoint of f(step) (written; must not alias ahat_in)
  *   dJdB      accumulated: dJdB[n] += dJ/dB(n, step)
  *   body      the pose/velocity of body 0 used by the forward step (W may

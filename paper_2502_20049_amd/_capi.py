@@ -31,7 +31,7 @@ EXPORTS = [
     "geometry_field_create", "geometry_field_create_analytic", "geometry_field_destroy", "geometry_map_step",
     "psm_stream_collide", "body_force_torque", "psm_mass_fp64", "psm_macroscopic", "psm_error_flags",
     "psm_set_option", "psm_stream_copy", "psm_set_fraction_offset", "psm_adjoint_step", "psm_adjoint_omega",
-    "psm_step", "lbm_set_obstacle", "psm_rigid_body", "psm_rigid_advance", "psm_coupled_step", "psm_pdf_stride",
+    "psm_step", "lbm_set_obstacle", "psm_rigid_body", "psm_rigid_advance", "psm_coupled_step", "psm_pdf_stride", "psm_adjoint_stride",
     "pdf_field_create_noalloc", "psm_pdf_layout", "psm_pdf_gather", "psm_pdf_scatter",
 ]
 
@@ -104,6 +104,7 @@ def _load():
         "psm_rigid_advance": (C.c_int, [C.POINTER(psm_rigid), dp, C.c_double]),
         "psm_coupled_step": (C.c_int, [vp, C.POINTER(psm_rigid), C.POINTER(vp), C.c_int, i64, vp, dp, vp]),
         "psm_pdf_stride": (C.c_int, [C.POINTER(psm_config), C.POINTER(i64)]),
+        "psm_adjoint_stride": (C.c_int, [C.POINTER(psm_config), C.POINTER(i64)]),
         "psm_pdf_layout": (C.c_int, [C.POINTER(psm_config), i32p, C.POINTER(i64), C.POINTER(i64)]),
         "psm_pdf_gather": (C.c_int, [vp, vp, vp]),
         "psm_pdf_scatter": (C.c_int, [vp, vp, vp]),

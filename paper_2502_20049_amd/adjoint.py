@@ -8,13 +8,19 @@ rate Omega, which enters the solid velocity u_s = V + Omega a x (x - X).
 Frozen-B convention: the mapping B_map(t) follows the prescribed motion and
 is not differentiated (it is piecewise constant in the angle).
 
-Reverse mode uses sqrt(T) checkpointing: the forward keeps the lattice every
-L steps (L even, so checkpoints sit in the standard in-place layout); the
-backward recomputes each segment, storing its L states (in the standard
-layout, psm_pdf_gather) and the solid fractions B(t) the recompute mapped, then runs L adjoint steps
+Reverse mode keeps the forward trajectory in one of two ways.  sqrt(T)
+checkpointing: the forward keeps the lattice every L steps (L even, so
+checkpoints sit in the standard in-place layout); the backward recomputes each
+segment, storing its L states (copies of the PDF buffer) and the solid
+fractions B(t) the recompute mapped, then runs L adjoint steps
 (psm_adjoint_step, one HIP kernel per step) from the last to the first with
-each step's stored B(t) put back (no second mapping).  All arithmetic and
-copies run in the library's kernels; torch only owns the buffers.
+each step's stored B(t) put back (no second mapping).  Whole trajectory (when
+T states and T copies of B fit the memory budget, e.g. the 128^3 FP32 rotor's
+800 steps in about 136 GB of HBM): the forward stores every state and B(t)
+itself and the backward runs the adjoint steps only, with no recompute.  Both
+feed the adjoint step the same states and fractions, so their results are
+bit-identical.  All arithmetic and copies run in the library's kernels; torch
+only owns the buffers.
 """
 from __future__ import annotations
 
@@ -29,7 +35,12 @@ from ._capi import check, lib
 
 
 class TorqueAdjoint:
-    def __init__(self, wl, steps: int, weights, storage=None, segment: int | None = None, device="cuda"):
+    def __init__(self, wl, steps: int, weights, storage=None, segment: int | None = None, device="cuda",
+                 store_all: bool | None = None, memory_budget: int | None = None):
+        """``store_all``: keep the whole trajectory (True), checkpoint every
+        ``segment`` steps (False), or decide by size (None: the whole
+        trajectory if it needs at most ``memory_budget`` bytes, default half
+        of the device's free memory)."""
         if len(wl.bodies) != 1:
             raise ValueError("the torque objective takes exactly one body")
         self.wl = wl
@@ -39,6 +50,9 @@ class TorqueAdjoint:
             raise ValueError("one weight per step")
         self.field = sim.Field(wl, storage=storage, slots=1, device=device)
         self.q, self.N = wl.q, wl.n_cells
+        st = C.c_int64()
+        check(lib.psm_adjoint_stride(C.byref(self.field.cfg), C.byref(st)), "psm_adjoint_stride")
+        self.astride = st.value  # elements between the adjoint buffers' direction arrays
         L = segment or int(math.ceil(math.sqrt(self.steps)))
         self.L = max(2, L + (L & 1))
         self.adt = torch.float64 if self.field.storage == "f64" else torch.float32
@@ -50,6 +64,14 @@ class TorqueAdjoint:
         self._store = None
         self._bstore = None
         self.omega = self.body.motion.omega
+        need = self.steps * (self.field.pdf.numel() * self.field.pdf.element_size() + self.field.bbuf.numel())
+        if store_all is None:
+            budget = memory_budget if memory_budget is not None else torch.cuda.mem_get_info(device)[0] // 2
+            store_all = need <= budget
+        self.store_all = bool(store_all)
+        self.trajectory_bytes = need if self.store_all else 0
+        self._states = []
+        self._bst = []
         self.dB = None
         self.ft = torch.zeros((self.steps, 6), dtype=torch.float64, device=device)
 
@@ -82,31 +104,55 @@ class TorqueAdjoint:
         if f0 is not None:
             self.field.load_pdf_std(f0)
         self._ckpt = {}
-        nck = (self.steps + self.L - 1) // self.L
-        while len(self._ckpt_pool) < nck:
-            self._ckpt_pool.append(torch.empty_like(self.field.pdf))
-        for t in range(self.steps):
-            if t % self.L == 0:
-                ck = self._ckpt_pool[t // self.L]
-                sim.stream_copy(self.field.pdf, ck)
-                self._ckpt[t] = ck
-            self._step(t, ft=self.ft[t])
+        if self.store_all:
+            f = self.field
+            while len(self._states) < self.steps:
+                self._states.append(torch.empty_like(f.pdf))
+                self._bst.append(torch.empty_like(f.bbuf))
+            for t in range(self.steps):
+                sim.stream_copy(f.pdf, self._states[t])
+                self._step(t, ft=self.ft[t])
+                sim.stream_copy(f.bbuf, self._bst[t])
+        else:
+            nck = (self.steps + self.L - 1) // self.L
+            while len(self._ckpt_pool) < nck:
+                self._ckpt_pool.append(torch.empty_like(self.field.pdf))
+            for t in range(self.steps):
+                if t % self.L == 0:
+                    ck = self._ckpt_pool[t // self.L]
+                    sim.stream_copy(self.field.pdf, ck)
+                    self._ckpt[t] = ck
+                self._step(t, ft=self.ft[t])
         a = torch.tensor(list(self.body.motion.axis), dtype=torch.float64, device=self.device)
         w = torch.tensor(self.weights, dtype=torch.float64, device=self.device)
         return float((w * (self.ft[:, 3:] @ a)).sum().item())
 
     def backward(self):
-        """(dJ/d dB (N,), dJ/dOmega, dJ/d f0 (q, N)) for the last forward."""
+        """(dJ/d dB (N,), dJ/dOmega, dJ/d f0 (q, N), a strided view) for the
+        last forward."""
         q, N = self.q, self.N
         f = self.field
-        if self._store is None or len(self._store) < self.L:
-            self._store = [torch.empty((q, N), dtype=f.dtype, device=self.device) for _ in range(self.L)]
+        if not self.store_all and (self._store is None or len(self._store) < self.L):
+            self._store = [torch.empty_like(f.pdf) for _ in range(self.L)]
             self._bstore = [torch.empty_like(f.bbuf) for _ in range(self.L)]
-        ahat = [torch.zeros((q, N), dtype=self.adt, device=self.device),
-                torch.empty((q, N), dtype=self.adt, device=self.device)]
+        ahat = [torch.zeros((q, self.astride), dtype=self.adt, device=self.device),
+                torch.empty((q, self.astride), dtype=self.adt, device=self.device)]
         gB = torch.zeros(N, dtype=self.adt, device=self.device)
         gW = torch.zeros(1, dtype=torch.float64, device=self.device)
         stream = sim._stream()
+
+        def adjoint_step(t, state, bstore):
+            pm, pu = self._poses(t)
+            sim.stream_copy(bstore, f.bbuf)
+            check(lib.psm_adjoint_step(f.handle, C.c_void_p(state.data_ptr()), t, C.c_void_p(ahat[0].data_ptr()),
+                                       C.c_void_p(ahat[1].data_ptr()), C.c_void_p(gB.data_ptr()), pu, self.axis,
+                                       self.weights[t], stream), "psm_adjoint_step")
+            check(lib.psm_adjoint_omega(f.handle, C.c_void_p(gW.data_ptr()), stream), "psm_adjoint_omega")
+            ahat.reverse()
+
+        if self.store_all:
+            for t in range(self.steps - 1, -1, -1):
+                adjoint_step(t, self._states[t], self._bst[t])
         for s0 in sorted(self._ckpt.keys(), reverse=True):
             s1 = min(s0 + self.L, self.steps)
             # B is put back from the store below, outside the mapping's
@@ -114,19 +160,12 @@ class TorqueAdjoint:
             f.reset()
             sim.stream_copy(self._ckpt[s0], f.pdf)
             for t in range(s0, s1):
-                f.pdf_std(out=self._store[t - s0])
+                sim.stream_copy(f.pdf, self._store[t - s0])
                 self._step(t)
                 sim.stream_copy(f.bbuf, self._bstore[t - s0])
             for t in range(s1 - 1, s0 - 1, -1):
-                pm, pu = self._poses(t)
-                sim.stream_copy(self._bstore[t - s0], f.bbuf)
-                check(lib.psm_adjoint_step(f.handle, C.c_void_p(self._store[t - s0].data_ptr()), t,
-                                           C.c_void_p(ahat[0].data_ptr()), C.c_void_p(ahat[1].data_ptr()),
-                                           C.c_void_p(gB.data_ptr()), pu, self.axis, self.weights[t], stream),
-                      "psm_adjoint_step")
-                check(lib.psm_adjoint_omega(f.handle, C.c_void_p(gW.data_ptr()), stream), "psm_adjoint_omega")
-                ahat.reverse()
-        return gB, float(gW.item()), ahat[0]
+                adjoint_step(t, self._store[t - s0], self._bstore[t - s0])
+        return gB, float(gW.item()), ahat[0][:, :N]
 
 
 class PSMTorque(torch.autograd.Function):

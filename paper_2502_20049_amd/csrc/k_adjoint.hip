@@ -13,7 +13,8 @@
 //   sum_i b_i dfeq_i/df_j = G_rho + G_u . (c_j - u)/rho,
 //   dfeq_i/drho = feq_i/rho,  dfeq_i/du = w_i rho [3 c_i + 9 (c_i.u) c_i - 3 u],
 //   dS_i/du = w_i [-3 F + 9 (c_i.F) c_i].
-// The adjoint PDFs are stored in the standard layout, two buffers.
+// The forward state is read in the field's own PDF layout (a copy of the PDF
+// buffer); the adjoint PDFs are q arrays of N values a padded stride apart.
 #include "k_stream_collide.hpp"
 
 namespace psm {
@@ -50,21 +51,6 @@ __device__ __forceinline__ void cacc(R &vx, R &vy, R &vz, R k) {
   if constexpr (EZ == -1) vz -= k;
 }
 
-// Index of the neighbour n + e (periodic wrap; w holds the per-cell wrap
-// corrections for +x, -x, +y, -y, +z, -z, zero away from the faces).  uint32
-// arithmetic: every field has fewer than 2^32 cells.
-template <int EX, int EY, int EZ>
-__device__ __forceinline__ uint32_t nbr(uint32_t n, uint32_t nx, uint32_t nxy, const uint32_t (&w)[6]) {
-  uint32_t m = n;
-  if constexpr (EX == 1) m += 1u + w[0];
-  if constexpr (EX == -1) m += w[1] - 1u;
-  if constexpr (EY == 1) m += nx + w[2];
-  if constexpr (EY == -1) m += w[3] - nx;
-  if constexpr (EZ == 1) m += nxy + w[4];
-  if constexpr (EZ == -1) m += w[5] - nxy;
-  return m;
-}
-
 // The step is written over opposite pairs (i, ib): for any per-direction
 // vectors a, b, a_i b_i + a_ib b_ib = 2 (a+ b+ + a- b-) with a+- = (a_i +- a_ib)/2,
 // and feq, the Guo term and their u-derivatives split into even and odd parts
@@ -77,152 +63,183 @@ __device__ __forceinline__ uint32_t nbr(uint32_t n, uint32_t nx, uint32_t nxy, c
 // dS_i/du = w (-3 F + 9 (c.F) c) is even.  Collecting terms,
 //   fhat_j = gh_j - (1 - B) b_j + (sh_jb - sh_j) + C0 + V . c_j
 // with one scalar C0 and one vector V per cell, both sums over the pairs.
-template <int Q, typename T, int PAR>
-__global__ __launch_bounds__(256) void k_adjoint(const AdjArgs A) {
+//
+// One cell: x per lane, the row (y, z) shared by the wave.  Returns the
+// cell's dJ/dOmega term.
+template <int Q, typename T, int PAR, bool O32>
+__device__ __forceinline__ double adjoint_cell(const AdjArgs &A, uint32_t row, uint32_t yy, uint32_t zz,
+                                               uint32_t xx) {
   using R = typename Comp<T>::type;
   constexpr int H = Lat<Q>::H;
   const SCArgs &a = A.s;
-  const uint64_t n64 = (uint64_t)blockIdx.x * 256u + threadIdx.x;
+  const uint32_t nx = (uint32_t)a.nx, ny = (uint32_t)a.ny, nz = (uint32_t)a.nz;
+  const uint32_t n = row * nx + xx;
+  const int x = (int)xx, y = (int)yy, z = (int)zz;
+  // periodic neighbours (used only where the direction is not a face
+  // direction of this cell): rows are wave-uniform, x per lane
+  const uint32_t ym = yy == 0 ? ny - 1 : yy - 1, yp = yy + 1 == ny ? 0u : yy + 1;
+  const uint32_t zm = zz == 0 ? nz - 1 : zz - 1, zp = zz + 1 == nz ? 0u : zz + 1;
+  const uint32_t xm = xx == 0 ? nx - 1 : xx - 1, xp = xx + 1 == nx ? 0u : xx + 1;
+  auto rowof = [&](int ey, int ez) -> uint32_t {
+    return (ey < 0 ? ym : ey > 0 ? yp : yy) + ny * (ez < 0 ? zm : ez > 0 ? zp : zz);
+  };
+  auto xof = [&](int ex) -> uint32_t { return ex < 0 ? xm : ex > 0 ? xp : xx; };
+  uint32_t bcm, outm, inm;
+  classify<Q>(a, x, y, z, bcm, outm, inm);
+  // forward state before the step, as deviations d_k = f_k - w_k, and the
+  // adjoint gh of the post-collision values (transpose of the streaming)
+  // Element offsets in 32 bits when every array spans fewer than 2^32 bytes
+  // (a uniform base plus a 32-bit lane offset per access), else 64.
+  using Off = typename std::conditional<O32, uint32_t, uint64_t>::type;
+  const Off AS = (Off)A.as, DS = (Off)a.dS, NX = (Off)nx;
+  auto frow = [&](uint32_t r) -> Off { return (Off)(r >> a.lrb) * (Off)a.bst + (Off)(r & a.rbm) * NX; };
+  auto F = [&](int k, uint32_t r, uint32_t xe) -> const T * {
+    return (const T *)((const char *)A.fwd + (uint64_t)((frow(r) + (Off)k * DS + (Off)xe) * (Off)sizeof(T)));
+  };
+  auto G = [&](int k, uint32_t r, uint32_t xe) -> R {
+    return *(const R *)((const char *)A.ain + (uint64_t)(((Off)k * AS + (Off)r * NX + (Off)xe) * (Off)sizeof(R)));
+  };
+  auto O = [&](int k) -> R * { return (R *)((char *)A.aout + (uint64_t)(((Off)k * AS + (Off)n) * (Off)sizeof(R))); };
+  R d[Q], gh[Q];
+  if (bcm == 0) {  // no face direction: plain pulls / pushes with periodic wrap
+    sfor<Q>([&](auto K) {
+      constexpr int k = K;
+      constexpr int ex = cx<Q>(k), ey = cy<Q>(k), ez = cz<Q>(k);
+      if constexpr (PAR == 0 || k == 0) d[k] = (R)*F(k, row, xx);
+      else d[k] = (R)*F(opp<Q>(k), rowof(-ey, -ez), xof(-ex));
+      if constexpr (k == 0) gh[k] = G(0, row, xx);
+      else gh[k] = G(k, rowof(ey, ez), xof(ex));
+    });
+  } else {
+    sfor<Q>([&](auto K) {
+      constexpr int k = K;
+      constexpr int ex = cx<Q>(k), ey = cy<Q>(k), ez = cz<Q>(k);
+      const T *own = F(k, row, xx);
+      R v;
+      if constexpr (PAR == 0 || k == 0) {
+        v = (R)*own;
+      } else {
+        const T *p = ((bcm >> k) & 1u) ? own : F(opp<Q>(k), rowof(-ey, -ez), xof(-ex));
+        v = (R)*p;
+        if ((inm >> k) & 1u) v += inlet_term<Q, R>(a, k);
+      }
+      d[k] = v;
+    });
+    sfor<Q>([&](auto K) {
+      constexpr int i = K;
+      constexpr int ib = opp<Q>(i);
+      constexpr int ex = cx<Q>(i), ey = cy<Q>(i), ez = cz<Q>(i);
+      R g = 0;
+      if constexpr (i == 0) {
+        g = G(0, row, xx);
+      } else {
+        // f*_i(x) streams to x + c_i unless that neighbour's source (x) is
+        // outside for it, i.e. unless direction ib is a face direction here
+        if (!((bcm >> ib) & 1u)) g += G(i, rowof(ey, ez), xof(ex));
+        else if (!((outm >> ib) & 1u)) g += G(ib, row, xx);  // bounced back into direction ib
+        if ((outm >> i) & 1u) g += G(i, row, xx);              // outlet: f_i(x) = f*_i(x)
+      }
+      gh[i] = g;
+    });
+  }
+  // forward recompute: rho, u, and the per-cell constants
+  R drho = d[0], jx = 0, jy = 0, jz = 0;
+  sfor<H>([&](auto P) {
+    constexpr int i = P + 1, ib = opp<Q>(i);
+    drho += d[i] + d[ib];
+    cacc<cx<Q>(i), cy<Q>(i), cz<Q>(i)>(jx, jy, jz, d[i] - d[ib]);
+  });
+  const R rho = R(1) + drho, ir = R(1) / rho;
+  const R Fx = (R)a.force[0], Fy = (R)a.force[1], Fz = (R)a.force[2];
+  const R ux = (jx + R(0.5) * Fx) * ir, uy = (jy + R(0.5) * Fy) * ir, uz = (jz + R(0.5) * Fz) * ir;
+  const R Frx = Fx * ir, Fry = Fy * ir, Frz = Fz * ir;
+  const R usq = ux * ux + uy * uy + uz * uz, uF = ux * Fx + uy * Fy + uz * Fz;
+  const R B = solid_fraction<R>(a, n), fl = R(1) - B;
+  const double rx = x + 0.5 - A.X[0], ry = y + 0.5 - A.X[1], rz = z + 0.5 - A.X[2];
+  const R usx = (R)(A.V[0] + (A.W[1] * rz - A.W[2] * ry));
+  const R usy = (R)(A.V[1] + (A.W[2] * rx - A.W[0] * rz));
+  const R usz = (R)(A.V[2] + (A.W[0] * ry - A.W[1] * rx));
+  const R uss = usx * usx + usy * usy + usz * usz;
+  // a x r: torque lever per unit force along c_i
+  const R arx = (R)(A.axis[1] * rz - A.axis[2] * ry), ary = (R)(A.axis[2] * rx - A.axis[0] * rz),
+          arz = (R)(A.axis[0] * ry - A.axis[1] * rx);
+  const R wtt = (R)A.wt;
+  const R le = (R)a.lam_e, lo = (R)a.lam_o;
+  const R ge = R(1) - R(0.5) * le, go = R(1) - R(0.5) * lo;
+  const R dus = R(1.5) * (uss - usq);
+  // rest direction
+  R Wg, dJ;
+  {
+    const R w0 = (R)wt<Q>(0);
+    const R fe = d[0] - w0 * (drho - rho * R(1.5) * usq);
+    const R OF = -le * fe - ge * R(3) * w0 * uF;
+    const R OS = -w0 * rho * dus;
+    Wg = w0 * gh[0];
+    dJ = R(0.5) * gh[0] * (OS - OF);
+  }
+  R Vx = 0, Vy = 0, Vz = 0, C0 = 0, dS = 0, Wg2 = 0;
+  sfor<H>([&](auto P) {
+    constexpr int i = P + 1, ib = opp<Q>(i);
+    constexpr int ex = cx<Q>(i), ey = cy<Q>(i), ez = cz<Q>(i);
+    const R wi = (R)wt<Q>(i);
+    const R gp = R(0.5) * (gh[i] + gh[ib]), gm = R(0.5) * (gh[i] - gh[ib]);
+    const R dp = R(0.5) * (d[i] + d[ib]), dm = R(0.5) * (d[i] - d[ib]);
+    const R cu = cdot<ex, ey, ez>(ux, uy, uz), cs = cdot<ex, ey, ez>(usx, usy, usz);
+    const R cF = cdot<ex, ey, ez>(Fx, Fy, Fz), cFr = cdot<ex, ey, ez>(Frx, Fry, Frz);
+    const R m = cdot<ex, ey, ez>(arx, ary, arz);
+    const R cu2 = cu * cu, cs2 = cs * cs;
+    // TRT + Guo (even / odd parts) and SC1 collision of the pair
+    const R fpe = dp - wi * (drho + rho * (R(4.5) * cu2 - R(1.5) * usq));
+    const R fme = dm - R(3) * wi * rho * cu;
+    const R OFp = -le * fpe + ge * wi * (R(9) * cu * cF - R(3) * uF);
+    const R OFm = -lo * fme + go * R(3) * wi * cF;
+    const R OSp = wi * rho * (R(4.5) * (cs2 - cu2) - dus);
+    const R OSm = R(-2) * dm + R(3) * wi * rho * (cu + cs);
+    const R qm = gm - wtt * m;
+    dJ += gp * (OSp - OFp) + qm * OSm - gm * OFm;
+    const R shp = B * gp, shm = B * qm;
+    const R kap = wi * (fl * (R(6) * lo * gm + R(18) * gp * (le * cu + ge * cFr)) + R(6) * shm - R(18) * shp * cu);
+    cacc<ex, ey, ez>(Vx, Vy, Vz, kap);
+    C0 += wi * (R(9) * shp * (cu2 + cs2) + R(6) * shm * cs - fl * gp * cu * (R(9) * le * cu + R(18) * ge * cFr));
+    dS += wi * (R(6) * shm + R(18) * shp * cs) * m;
+    Wg2 += wi * gp;
+  });
+  Wg += R(2) * Wg2;
+  const R Ws = B * Wg;
+  C0 += fl * Wg * (le * (R(1) + R(1.5) * usq) + R(3) * ge * (Frx * ux + Fry * uy + Frz * uz)) -
+        R(1.5) * (usq + uss) * Ws;
+  Vx -= R(3) * (fl * Wg * (le * ux + ge * Frx) - ux * Ws);
+  Vy -= R(3) * (fl * Wg * (le * uy + ge * Fry) - uy * Ws);
+  Vz -= R(3) * (fl * Wg * (le * uz + ge * Frz) - uz * Ws);
+  *O(0) = gh[0] - fl * le * gh[0] + C0;
+  sfor<H>([&](auto P) {
+    constexpr int i = P + 1, ib = opp<Q>(i);
+    constexpr int ex = cx<Q>(i), ey = cy<Q>(i), ez = cz<Q>(i);
+    const R gp = R(0.5) * (gh[i] + gh[ib]), gm = R(0.5) * (gh[i] - gh[ib]);
+    const R shm = B * (gm - wtt * cdot<ex, ey, ez>(arx, ary, arz));
+    const R vc = cdot<ex, ey, ez>(Vx, Vy, Vz);
+    const R bp = le * gp, bm = lo * gm;
+    *O(i) = gh[i] - fl * (bp + bm) - R(2) * shm + C0 + vc;
+    *O(ib) = gh[ib] - fl * (bp - bm) + R(2) * shm + C0 - vc;
+  });
+  R *gB = (R *)A.dJdB;
+  gB[n] += R(2) * dJ;
+  return (double)(rho * (dS - R(3) * (arx * usx + ary * usy + arz * usz) * Ws));
+}
+
+// One wave per work unit of up to 64 cells of one row (ceil(nx / 64) units
+// per row); one FP64 dJ/dOmega partial per workgroup.
+template <int Q, typename T, int PAR, bool O32>
+__global__ __launch_bounds__(256) void k_adjoint(const AdjArgs A) {
+  const SCArgs &a = A.s;
+  const uint32_t nx = (uint32_t)a.nx, ny = (uint32_t)a.ny;
+  const uint32_t segs = (nx + 63u) >> 6, units = ny * (uint32_t)a.nz * segs;
+  const uint32_t u = __builtin_amdgcn_readfirstlane(blockIdx.x * 4u + (threadIdx.x >> 6));
   double dom = 0.0;
-  if (n64 < (uint64_t)a.N) {
-    const uint32_t n = (uint32_t)n64, N = (uint32_t)a.N;
-    const uint32_t nx = (uint32_t)a.nx, ny = (uint32_t)a.ny, nz = (uint32_t)a.nz, nxy = nx * ny;
-    const uint32_t zz = n / nxy, rr = n - zz * nxy, yy = rr / nx, xx = rr - yy * nx;
-    const int x = (int)xx, y = (int)yy, z = (int)zz;
-    const uint32_t w[6] = {xx == nx - 1 ? 0u - nx : 0u, xx == 0 ? nx : 0u, yy == ny - 1 ? 0u - nxy : 0u,
-                           yy == 0 ? nxy : 0u,          zz == nz - 1 ? 0u - N : 0u, zz == 0 ? N : 0u};
-    uint32_t bcm, outm, inm;
-    classify<Q>(a, x, y, z, bcm, outm, inm);
-    // forward state before the step, as deviations d_k = f_k - w_k, and the
-    // adjoint gh of the post-collision values (transpose of the streaming)
-    const T *fwd = (const T *)A.fwd;
-    const uint64_t FS = (uint64_t)a.N;  // the forward state is in the standard layout [q][N]
-    const R *ain = (const R *)A.ain;
-    R d[Q], gh[Q];
-    if (bcm == 0) {  // no face direction: plain pulls / pushes with periodic wrap
-      sfor<Q>([&](auto K) {
-        constexpr int k = K;
-        if constexpr (PAR == 0 || k == 0) d[k] = (R)fwd[(size_t)k * FS + n];
-        else d[k] = (R)fwd[(size_t)opp<Q>(k) * FS + nbr<-cx<Q>(k), -cy<Q>(k), -cz<Q>(k)>(n, nx, nxy, w)];
-        if constexpr (k == 0) gh[k] = ain[n];
-        else gh[k] = ain[(size_t)k * N + nbr<cx<Q>(k), cy<Q>(k), cz<Q>(k)>(n, nx, nxy, w)];
-      });
-    } else {
-      sfor<Q>([&](auto K) {
-        constexpr int k = K;
-        const T *own = fwd + (size_t)k * FS + n;
-        R v;
-        if constexpr (PAR == 0 || k == 0) {
-          v = (R)*own;
-        } else {
-          const uint32_t src = nbr<-cx<Q>(k), -cy<Q>(k), -cz<Q>(k)>(n, nx, nxy, w);
-          const T *p = ((bcm >> k) & 1u) ? own : fwd + (size_t)opp<Q>(k) * FS + src;
-          v = (R)*p;
-          if ((inm >> k) & 1u) v += inlet_term<Q, R>(a, k);
-        }
-        d[k] = v;
-      });
-      sfor<Q>([&](auto K) {
-        constexpr int i = K;
-        constexpr int ib = opp<Q>(i);
-        const R *ai = ain + (size_t)i * N;
-        R g = 0;
-        if constexpr (i == 0) {
-          g = ai[n];
-        } else {
-          // f*_i(x) streams to x + c_i unless that neighbour's source (x) is
-          // outside for it, i.e. unless direction ib is a face direction here
-          if (!((bcm >> ib) & 1u)) g += ai[nbr<cx<Q>(i), cy<Q>(i), cz<Q>(i)>(n, nx, nxy, w)];
-          else if (!((outm >> ib) & 1u)) g += ain[(size_t)ib * N + n];  // bounced back into direction ib
-          if ((outm >> i) & 1u) g += ai[n];                             // outlet: f_i(x) = f*_i(x)
-        }
-        gh[i] = g;
-      });
-    }
-    // forward recompute: rho, u, and the per-cell constants
-    R drho = d[0], jx = 0, jy = 0, jz = 0;
-    sfor<H>([&](auto P) {
-      constexpr int i = P + 1, ib = opp<Q>(i);
-      drho += d[i] + d[ib];
-      cacc<cx<Q>(i), cy<Q>(i), cz<Q>(i)>(jx, jy, jz, d[i] - d[ib]);
-    });
-    const R rho = R(1) + drho, ir = R(1) / rho;
-    const R Fx = (R)a.force[0], Fy = (R)a.force[1], Fz = (R)a.force[2];
-    const R ux = (jx + R(0.5) * Fx) * ir, uy = (jy + R(0.5) * Fy) * ir, uz = (jz + R(0.5) * Fz) * ir;
-    const R Frx = Fx * ir, Fry = Fy * ir, Frz = Fz * ir;
-    const R usq = ux * ux + uy * uy + uz * uz, uF = ux * Fx + uy * Fy + uz * Fz;
-    const R B = solid_fraction<R>(a, n), fl = R(1) - B;
-    const double rx = x + 0.5 - A.X[0], ry = y + 0.5 - A.X[1], rz = z + 0.5 - A.X[2];
-    const R usx = (R)(A.V[0] + (A.W[1] * rz - A.W[2] * ry));
-    const R usy = (R)(A.V[1] + (A.W[2] * rx - A.W[0] * rz));
-    const R usz = (R)(A.V[2] + (A.W[0] * ry - A.W[1] * rx));
-    const R uss = usx * usx + usy * usy + usz * usz;
-    // a x r: torque lever per unit force along c_i
-    const R arx = (R)(A.axis[1] * rz - A.axis[2] * ry), ary = (R)(A.axis[2] * rx - A.axis[0] * rz),
-            arz = (R)(A.axis[0] * ry - A.axis[1] * rx);
-    const R wtt = (R)A.wt;
-    const R le = (R)a.lam_e, lo = (R)a.lam_o;
-    const R ge = R(1) - R(0.5) * le, go = R(1) - R(0.5) * lo;
-    const R dus = R(1.5) * (uss - usq);
-    // rest direction
-    R Wg, dJ;
-    {
-      const R w0 = (R)wt<Q>(0);
-      const R fe = d[0] - w0 * (drho - rho * R(1.5) * usq);
-      const R OF = -le * fe - ge * R(3) * w0 * uF;
-      const R OS = -w0 * rho * dus;
-      Wg = w0 * gh[0];
-      dJ = R(0.5) * gh[0] * (OS - OF);
-    }
-    R Vx = 0, Vy = 0, Vz = 0, C0 = 0, dS = 0, Wg2 = 0;
-    sfor<H>([&](auto P) {
-      constexpr int i = P + 1, ib = opp<Q>(i);
-      constexpr int ex = cx<Q>(i), ey = cy<Q>(i), ez = cz<Q>(i);
-      const R wi = (R)wt<Q>(i);
-      const R gp = R(0.5) * (gh[i] + gh[ib]), gm = R(0.5) * (gh[i] - gh[ib]);
-      const R dp = R(0.5) * (d[i] + d[ib]), dm = R(0.5) * (d[i] - d[ib]);
-      const R cu = cdot<ex, ey, ez>(ux, uy, uz), cs = cdot<ex, ey, ez>(usx, usy, usz);
-      const R cF = cdot<ex, ey, ez>(Fx, Fy, Fz), cFr = cdot<ex, ey, ez>(Frx, Fry, Frz);
-      const R m = cdot<ex, ey, ez>(arx, ary, arz);
-      const R cu2 = cu * cu, cs2 = cs * cs;
-      // TRT + Guo (even / odd parts) and SC1 collision of the pair
-      const R fpe = dp - wi * (drho + rho * (R(4.5) * cu2 - R(1.5) * usq));
-      const R fme = dm - R(3) * wi * rho * cu;
-      const R OFp = -le * fpe + ge * wi * (R(9) * cu * cF - R(3) * uF);
-      const R OFm = -lo * fme + go * R(3) * wi * cF;
-      const R OSp = wi * rho * (R(4.5) * (cs2 - cu2) - dus);
-      const R OSm = R(-2) * dm + R(3) * wi * rho * (cu + cs);
-      const R qm = gm - wtt * m;
-      dJ += gp * (OSp - OFp) + qm * OSm - gm * OFm;
-      const R shp = B * gp, shm = B * qm;
-      const R kap = wi * (fl * (R(6) * lo * gm + R(18) * gp * (le * cu + ge * cFr)) + R(6) * shm - R(18) * shp * cu);
-      cacc<ex, ey, ez>(Vx, Vy, Vz, kap);
-      C0 += wi * (R(9) * shp * (cu2 + cs2) + R(6) * shm * cs - fl * gp * cu * (R(9) * le * cu + R(18) * ge * cFr));
-      dS += wi * (R(6) * shm + R(18) * shp * cs) * m;
-      Wg2 += wi * gp;
-    });
-    Wg += R(2) * Wg2;
-    const R Ws = B * Wg;
-    C0 += fl * Wg * (le * (R(1) + R(1.5) * usq) + R(3) * ge * (Frx * ux + Fry * uy + Frz * uz)) -
-          R(1.5) * (usq + uss) * Ws;
-    Vx -= R(3) * (fl * Wg * (le * ux + ge * Frx) - ux * Ws);
-    Vy -= R(3) * (fl * Wg * (le * uy + ge * Fry) - uy * Ws);
-    Vz -= R(3) * (fl * Wg * (le * uz + ge * Frz) - uz * Ws);
-    R *aout = (R *)A.aout;
-    aout[n] = gh[0] - fl * le * gh[0] + C0;
-    sfor<H>([&](auto P) {
-      constexpr int i = P + 1, ib = opp<Q>(i);
-      constexpr int ex = cx<Q>(i), ey = cy<Q>(i), ez = cz<Q>(i);
-      const R gp = R(0.5) * (gh[i] + gh[ib]), gm = R(0.5) * (gh[i] - gh[ib]);
-      const R shm = B * (gm - wtt * cdot<ex, ey, ez>(arx, ary, arz));
-      const R vc = cdot<ex, ey, ez>(Vx, Vy, Vz);
-      const R bp = le * gp, bm = lo * gm;
-      aout[(size_t)i * N + n] = gh[i] - fl * (bp + bm) - R(2) * shm + C0 + vc;
-      aout[(size_t)ib * N + n] = gh[ib] - fl * (bp - bm) + R(2) * shm + C0 - vc;
-    });
-    R *gB = (R *)A.dJdB;
-    gB[n] += R(2) * dJ;
-    dom = (double)(rho * (dS - R(3) * (arx * usx + ary * usy + arz * usz) * Ws));
+  if (u < units) {
+    const uint32_t row = u / segs, xx = (u - row * segs) * 64u + (threadIdx.x & 63u);
+    const uint32_t zz = row / ny, yy = row - zz * ny;
+    if (xx < nx) dom = adjoint_cell<Q, T, PAR, O32>(A, row, yy, zz, xx);
   }
   __shared__ double sh4[4];
   double v = wave_sum(dom);
@@ -231,14 +248,20 @@ __global__ __launch_bounds__(256) void k_adjoint(const AdjArgs A) {
   if (threadIdx.x == 0) A.part[blockIdx.x] = ((sh4[0] + sh4[1]) + sh4[2]) + sh4[3];
 }
 
+template <int Q, typename T, bool O32>
+static void go_adjoint(const AdjArgs &A, dim3 g, hipStream_t st) {
+  if (A.parity == 0) hipLaunchKernelGGL((k_adjoint<Q, T, 0, O32>), g, dim3(256), 0, st, A);
+  else hipLaunchKernelGGL((k_adjoint<Q, T, 1, O32>), g, dim3(256), 0, st, A);
+}
+
 template <int Q, typename T>
 static void go_adjoint(const AdjArgs &A, dim3 g, hipStream_t st) {
-  if (A.parity == 0) hipLaunchKernelGGL((k_adjoint<Q, T, 0>), g, dim3(256), 0, st, A);
-  else hipLaunchKernelGGL((k_adjoint<Q, T, 1>), g, dim3(256), 0, st, A);
+  if (A.o32) go_adjoint<Q, T, true>(A, g, st);
+  else go_adjoint<Q, T, false>(A, g, st);
 }
 
 hipError_t launch_adjoint(const psm_field &f, const AdjArgs &A, hipStream_t st) {
-  const dim3 g((unsigned)((f.N + 255) / 256));
+  const dim3 g(adjoint_blocks(f.cfg.nx, f.cfg.ny, f.cfg.nz));
   const int q = f.cfg.q, sto = f.cfg.storage;
   if (q == 19 && sto == PSM_F64) go_adjoint<19, double>(A, g, st);
   else if (q == 19 && sto == PSM_F32) go_adjoint<19, float>(A, g, st);

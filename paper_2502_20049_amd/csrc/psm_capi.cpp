@@ -106,6 +106,14 @@ static PdfLayout pdf_layout_of(const psm_config &c) {
 
 static int64_t pdf_stride_elems(const psm_config &c) { return pdf_layout_of(c).dstride; }
 
+// Adjoint arrays: N values per direction, the start of each rounded up to a
+// 4 KiB boundary plus 4 KiB (no common offset modulo a large power of two).
+static size_t adjoint_elem_size(const psm_config &c) { return c.storage == PSM_F64 ? 8 : 4; }
+static int64_t adjoint_stride_elems(const psm_config &c) {
+  const int64_t N = (int64_t)c.nx * c.ny * c.nz, sz = (int64_t)adjoint_elem_size(c);
+  return (((N * sz + 4095) / 4096) * 4096 + 4096) / sz;
+}
+
 static Layout layout_of(const psm_config &c) {
   Layout L{};
   L.N = (int64_t)c.nx * c.ny * c.nz;
@@ -118,7 +126,9 @@ static Layout layout_of(const psm_config &c) {
   L.off_ftp = 256;
   L.off_red = L.off_ftp + (size_t)SOLID_BLOCKS * mb * 6 * sizeof(double);
   L.red_count = (uint32_t)((L.N + 255) / 256);
-  L.off_list = ((L.off_red + (size_t)L.red_count * sizeof(double) + 64 + 255) / 256) * 256;
+  // the slots also hold the adjoint step's per-workgroup partials
+  const size_t red_slots = std::max<size_t>(L.red_count, adjoint_blocks(c.nx, c.ny, c.nz));
+  L.off_list = ((L.off_red + red_slots * sizeof(double) + 64 + 255) / 256) * 256;
   L.work_bytes = L.off_list + (size_t)mb * MAP_LIST_CAP * sizeof(uint32_t);
   return L;
 }
@@ -303,7 +313,7 @@ int psm_required_bytes(const psm_config *cfg, int which, size_t *out) {
       *out = L.work_bytes;
       return PSM_OK;
     case PSM_BUF_ADJOINT:
-      *out = (size_t)cfg->q * (size_t)L.N * (cfg->storage == PSM_F64 ? 8 : 4);
+      *out = (size_t)cfg->q * (size_t)adjoint_stride_elems(*cfg) * adjoint_elem_size(*cfg);
       return PSM_OK;
     case PSM_BUF_GRAD_B:
       *out = (size_t)L.N * (cfg->storage == PSM_F64 ? 8 : 4);
@@ -320,6 +330,14 @@ int psm_pdf_stride(const psm_config *cfg, int64_t *elems) {
   if (r) return r;
   if (!elems) return set_error("null output"), PSM_EINVAL;
   *elems = pdf_stride_elems(*cfg);
+  return PSM_OK;
+}
+
+int psm_adjoint_stride(const psm_config *cfg, int64_t *elems) {
+  int r = check_config(cfg);
+  if (r) return r;
+  if (!elems) return set_error("null output"), PSM_EINVAL;
+  *elems = adjoint_stride_elems(*cfg);
   return PSM_OK;
 }
 
@@ -1094,6 +1112,11 @@ int psm_adjoint_step(psm_field *f, const void *fwd, int64_t step, const void *ai
   A.s = make_sc_args(*f);
   A.fwd = (const char *)fwd;
   A.parity = (int)(step & 1);
+  A.as = (uint64_t)adjoint_stride_elems(f->cfg);
+  size_t pb = 0, ab = 0;
+  psm_required_bytes(&f->cfg, PSM_BUF_PDF, &pb);
+  psm_required_bytes(&f->cfg, PSM_BUF_ADJOINT, &ab);
+  A.o32 = pb < (1ull << 32) && ab < (1ull << 32);
   A.ain = ain;
   A.aout = aout;
   A.dJdB = dJdB;
@@ -1113,7 +1136,8 @@ int psm_adjoint_step(psm_field *f, const void *fwd, int64_t step, const void *ai
 int psm_adjoint_omega(psm_field *f, double *out, void *stream) {
   if (!f || !out) return set_error("null argument"), PSM_EINVAL;
   if (int r = work_usable(f)) return r;
-  hipError_t e = launch_sum_accumulate(f->red, f->red_count, out, (hipStream_t)stream);
+  hipError_t e = launch_sum_accumulate(f->red, adjoint_blocks(f->cfg.nx, f->cfg.ny, f->cfg.nz), out,
+                                       (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "psm_adjoint_omega launch");
   return PSM_OK;
 }

@@ -141,6 +141,12 @@ struct SCArgs {
   IBox obox;              // bounding box of the class-1 and class-2 cells
 };
 
+// workgroups of the adjoint step: four waves of 64 cells of one row each
+__host__ __device__ __forceinline__ uint32_t adjoint_blocks(int nx, int ny, int nz) {
+  const uint64_t units = (uint64_t)ny * (uint64_t)nz * (uint64_t)((nx + 63) / 64);
+  return (uint32_t)((units + 3) / 4);
+}
+
 // element offset of row r (= y + ny z) in direction array 0 of the PDF buffer
 __host__ __device__ __forceinline__ uint64_t pdf_row(const SCArgs &a, uint32_t r) {
   return (uint64_t)(r >> a.lrb) * a.bst + (uint64_t)(r & a.rbm) * (uint64_t)(uint32_t)a.nx;
@@ -156,9 +162,11 @@ struct ObstHdr {
 // arguments of the adjoint step kernel
 struct AdjArgs {
   SCArgs s;           // field geometry, faces, rates, B pointers
-  const char *fwd;    // forward state before step t (storage type, parity t&1), [q][N]
+  const char *fwd;    // forward state before step t (storage type, parity t&1), the PDF buffer's layout
   int parity;
-  const void *ain;    // fhat(t+1), [q][N], adjoint precision
+  uint64_t as;        // elements between the direction arrays of ain / aout
+  int o32;            // the PDF copy and both adjoint arrays each span < 2^32 bytes
+  const void *ain;    // fhat(t+1), q arrays of N values, adjoint precision
   void *aout;         // fhat(t)
   void *dJdB;         // accumulated, [N], adjoint precision
   double X[3], V[3], W[3], axis[3];

@@ -162,8 +162,8 @@ def _v_field(rec, n):
 def test_adjoint_rotor_128_full_size(sim, storage):
     """The adjoint configuration at full size (128^3, 4-blade rotor of ~41k
     triangles, 800 steps, torque averaged over the last 200): J, dJ/dOmega and
-    dJ/dB along a seeded direction from the hand-written adjoint with sqrt(T)
-    checkpointing, against the FP64 oracle's J and its central differences
+    dJ/dB along a seeded direction from the hand-written adjoint (the whole
+    trajectory kept, or sqrt(T) checkpoints, as memory allows), against the FP64 oracle's J and its central differences
     (frozen B; tests/golden/make_adjoint_rotor_128.py).  The GPU mapping's sums
     of B equal the oracle's exactly."""
     import torch
@@ -183,7 +183,10 @@ def test_adjoint_rotor_128_full_size(sim, storage):
     T, win = rec["steps"], rec["window"]
     w = np.zeros(T)
     w[-win:] = 1.0 / win
+    # FP32: the whole trajectory (about 136 GB) where the device holds it,
+    # else sqrt(T) checkpoints; FP64 (twice that): checkpoints
     obj = adjoint.TorqueAdjoint(wl, T, w)
+    _say(f"[adjoint rotor 128^3] {storage}: store_all={obj.store_all}")
     J = obj.forward()
     gB, gW, _ = obj.backward()
     torch.cuda.synchronize()
@@ -194,6 +197,8 @@ def test_adjoint_rotor_128_full_size(sim, storage):
     eB = abs(gBv - rec["dJ_dB_dot_v_fd"]) / abs(rec["dJ_dB_dot_v_fd"])
     _say(f"[adjoint rotor 128^3] {storage}: J {J:.9e} vs {rec['J']:.9e} ({eJ:.1e}); dJ/dOmega {gW:.6e} vs FD "
          f"{rec['dJ_dOmega_fd']:.6e} ({eW:.1e}); dJ/dB.v {gBv:.6e} vs FD {rec['dJ_dB_dot_v_fd']:.6e} ({eB:.1e})")
+    del obj, gB
+    torch.cuda.empty_cache()
     if storage == "f64":
         assert eJ < 1e-10 and eW < 1e-5 and eB < 1e-5
     else:

@@ -55,20 +55,24 @@ BCS = {"periodic": ("periodic",) * 6, "channel": ("inlet", "outlet", "wall", "wa
        "box": ("wall", "wall", "inlet", "outlet", "wall", "wall")}
 
 
+@pytest.mark.parametrize("store_all", [False, True], ids=["sqrtT", "whole"])
 @pytest.mark.parametrize("bc", list(BCS))
 @pytest.mark.parametrize("storage", ["f64", "f32"])
-def test_adjoint_matches_oracle(orc, adjmod, bc, storage):
+def test_adjoint_matches_oracle(orc, adjmod, bc, storage, store_all):
+    """Both trajectory modes (sqrt(T) checkpoints with recompute, and the
+    whole trajectory kept by the forward) against the oracle's adjoint."""
     import torch
 
     adjoint, sim = adjmod
-    _say(f"[adjoint] {storage} {bc}")
+    _say(f"[adjoint] {storage} {bc} store_all={store_all}")
     wl, f0, dev, dB, wts = _small(orc, storage, BCS[bc])
     om = wl.bodies[0].motion.omega
     Jo, gBo, gWo, gFo = orc.torque_adjoint(wl, f0, 6, wts, dB=dB, omega_us=om)
     idx = _perm(orc, sim, 19)
     dev_lib = np.empty_like(dev)
     dev_lib[idx] = dev
-    adj = adjoint.TorqueAdjoint(wl, 6, wts, storage=storage, segment=2)
+    adj = adjoint.TorqueAdjoint(wl, 6, wts, storage=storage, segment=2, store_all=store_all)
+    assert adj.store_all == store_all
     J = adj.forward(dB=torch.tensor(dB, dtype=torch.float32), omega=om,
                     f0=torch.tensor(dev_lib, device="cuda"))
     gB, gW, gF = adj.backward()
@@ -87,19 +91,26 @@ def test_adjoint_matches_oracle(orc, adjmod, bc, storage):
 
 
 def test_checkpoint_segment_does_not_change_gradients(orc, adjmod):
+    """Segments of 2, 4 and 6 steps and the whole-trajectory mode give the
+    same J and gradients bit for bit (the same states and B(t) reach the
+    adjoint steps); the size rule picks the whole trajectory only within
+    the budget."""
     import torch
 
     adjoint, sim = adjmod
     wl, f0, dev, dB, wts = _small(orc, "f32", BCS["channel"])
     res = []
-    for L in (2, 4, 6):
-        adj = adjoint.TorqueAdjoint(wl, 6, wts, segment=L)
+    for L, whole in ((2, False), (4, False), (6, False), (2, True)):
+        adj = adjoint.TorqueAdjoint(wl, 6, wts, segment=L, store_all=whole)
         adj.forward(dB=torch.tensor(dB, dtype=torch.float32), omega=0.05)
         gB, gW, gF = adj.backward()
         torch.cuda.synchronize()
         res.append((gB.cpu(), gW, gF.cpu()))
     for r in res[1:]:
         assert torch.equal(r[0], res[0][0]) and r[1] == res[0][1] and torch.equal(r[2], res[0][2])
+    assert adjoint.TorqueAdjoint(wl, 6, wts, memory_budget=0).store_all is False
+    big = adjoint.TorqueAdjoint(wl, 6, wts, memory_budget=1 << 40)
+    assert big.store_all is True and big.trajectory_bytes > 0
 
 
 def test_autograd_rotor_gradient(orc, adjmod):
