@@ -108,19 +108,27 @@ def time_field(field, steps, warmup, t0=0):
 
 
 def time_kernels(field, steps, t0):
-    """Average launch times (ms) of psm_stream_collide and geometry_map_step,
-    from HIP events on the launch stream, over `steps` steps run as separate
-    calls."""
+    """Average launch times (ms) of psm_stream_collide and geometry_map_step:
+    HIP events on the launch stream around `steps` back-to-back calls of
+    each (stream-collide for steps t .. t+steps-1 on the fractions of the
+    last mapping, then the mapping of the same steps)."""
     import torch
 
     t = run_steps(field, t0, 5, fused=False)
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
-    mev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    steps += steps & 1  # as many even as odd steps
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
     torch.cuda.synchronize()
-    run_steps(field, t, steps, ev, mev if field.nb and field.remap_every_step else None, fused=False)
+    e[0].record()
+    for i in range(steps):
+        field.collide(t + i, field.poses(t + i) if field.nb else None)
+    e[1].record()
+    if field.nb and field.remap_every_step:
+        for i in range(steps):
+            field.map(t + i, field.poses(t + i))
+    e[2].record()
     torch.cuda.synchronize()
-    sc_ms = sum(a.elapsed_time(b) for a, b in ev) / steps
-    map_ms = (sum(a.elapsed_time(b) for a, b in mev) / steps) if field.nb and field.remap_every_step else 0.0
+    sc_ms = e[0].elapsed_time(e[1]) / steps
+    map_ms = e[1].elapsed_time(e[2]) / steps if field.nb and field.remap_every_step else 0.0
     return sc_ms, map_ms
 
 
@@ -476,6 +484,8 @@ def main():
     ap.add_argument("--layout", choices=["soa", "blocked"], default="blocked",
                     help="PDF buffer layout of every field (default: blocked)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--sequential", action="store_true",
+                    help="run every launch of a step on one stream (PSM_OPT_CONCURRENT = 0)")
     ap.add_argument("--no-extras", action="store_true", help="skip the variants, the copy probe and the other workloads")
     ap.add_argument("--only-psm", action="store_true", help="time the PSM path only (for profiling)")
     ap.add_argument("--adjoint-only", action="store_true",
@@ -502,6 +512,7 @@ def main():
 
     import torch
 
+    from paper_2502_20049_amd import _capi as capi
     from paper_2502_20049_amd import sim
 
     torch.cuda.set_device(0)
@@ -530,6 +541,8 @@ def main():
         wl.storage = args.storage
     storage = wl.storage
     f = sim.Field(wl)
+    if args.sequential:
+        f.set_option(capi.PSM_OPT_CONCURRENT, 0)
     wall, t_end = time_field(f, args.steps, args.warmup)
     sc_ms, map_ms = time_kernels(f, min(args.steps, 300), t_end)
     N = wl.n_cells
@@ -544,6 +557,7 @@ def main():
                                                             "f64": "f64"}[storage],
         "data": "synthetic",
         "config": {"workload": wl.name, "cells": N, "q": wl.q, "storage": storage, "layout": wl.layout,
+                   "launches": "one stream" if args.sequential else "solid and face rows on a second stream",
                    "bodies": len(wl.bodies),
                    "supersampling_s": [b.s for b in wl.bodies], "bc": list(wl.bc), "parallelism": "1 GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
@@ -552,7 +566,8 @@ def main():
                      "kernel": "psm_stream_collide", "algorithmic_bytes_per_cell": bpc,
                      "avg_launch_ms": round(sc_ms, 5)},
         "kernels_ms": {"psm_stream_collide": round(sc_ms, 5), "geometry_map_step": round(map_ms, 5),
-                       "note": "launch times from separate calls after the timed steps (which run psm_step)"},
+                       "note": "HIP events around back-to-back calls of each after the timed steps (which "
+                               "run psm_step)"},
     }
     del f
     torch.cuda.empty_cache()

@@ -163,9 +163,9 @@ const char *psm_last_error(void);
  *   WORK flags + force/torque partials (max_bodies*6 doubles per solid-kernel
  *        workgroup, 2048 of them) + reduction scratch + the mapping's lists
  *        of surface cells (psm ? max_bodies * 2^21 * 4 bytes : 0)
- *   ADJOINT  one adjoint PDF buffer of psm_adjoint_step: q arrays of N
- *        adjoint-precision values (FP64 for PSM_F64 fields, else FP32),
- *        psm_adjoint_stride elements apart
+ *   ADJOINT  one adjoint PDF buffer of psm_adjoint_step: the PDF buffer's
+ *        layout (psm_pdf_layout, in elements) with adjoint-precision
+ *        elements (FP64 for PSM_F64 fields, else FP32)
  *   GRAD_B   the dJ/dB accumulator of psm_adjoint_step: N adjoint-precision
  *        values
  *   OBSTACLE  lbm_set_obstacle's buffer (plain-LBM fields; 0 for psm = 1):
@@ -178,11 +178,6 @@ int psm_required_bytes(const psm_config *cfg, int which, size_t *out_bytes);
  * 4 KiB (so the arrays do not all start at the same offset modulo a large
  * power of two).  PSM_LAYOUT_BLOCKED: RB*nx, within a block. */
 int psm_pdf_stride(const psm_config *cfg, int64_t *elems);
-
-/* Elements between the starts of consecutive direction arrays of an adjoint
- * buffer (PSM_BUF_ADJOINT): N rounded up to a 4 KiB multiple in bytes of the
- * adjoint precision, plus 4 KiB.  Element (k, n) is at k*stride + n. */
-int psm_adjoint_stride(const psm_config *cfg, int64_t *elems);
 
 /* The PDF buffer layout of cfg (see psm_config.layout): rows per block RB
  * (SoA: ny*nz, one block), the direction stride in elements (as
@@ -415,9 +410,10 @@ int psm_pdf_scatter(psm_field *f, const void *src, void *stream);
  *             of the field's PDF buffer (psm_required_bytes PSM_BUF_PDF
  *             bytes, the field's layout and storage type), e.g. made by
  *             psm_stream_copy before the step
- *   ahat_in   adjoint of f(step+1): q arrays of N values in the adjoint
- *             precision, psm_adjoint_stride elements apart (element
- *             k*stride + n, n = x + nx*(y + ny*z)); the padding is not read
+ *   ahat_in   adjoint of f(step+1), direction k of cell x at the PDF
+ *             buffer's element of direction k, cell x (psm_pdf_layout), in
+ *             the adjoint precision (PSM_BUF_ADJOINT bytes); elements outside
+ *             the lattice are not read
  *   ahat_out  adjoint of f(step) (written; must not alias ahat_in)
  *   dJdB      accumulated: dJdB[n] += dJ/dB(n, step)
  *   body      the pose/velocity of body 0 used by the forward step (W may
@@ -429,6 +425,10 @@ int psm_pdf_scatter(psm_field *f, const void *src, void *stream);
 int psm_adjoint_step(psm_field *f, const void *fwd_pdf, int64_t step, const void *ahat_in, void *ahat_out,
                      void *dJdB, const psm_body *body, const double axis[3], double wt, void *stream);
 int psm_adjoint_omega(psm_field *f, double *out_dev, void *stream);
+/* An adjoint buffer (PSM_BUF_ADJOINT, the PDF buffer's layout) to the
+ * standard layout: q arrays of N adjoint-precision values, element k*N + n,
+ * on `stream`; dst must not overlap adj. */
+int psm_adjoint_gather(psm_field *f, const void *adj, void *dst, void *stream);
 
 /* ---- diagnostics ------------------------------------------------------------ */
 /* Total mass sum_x rho(x) in FP64 (fixed-order tree) into out_dev[0];
@@ -453,8 +453,21 @@ int psm_error_flags(psm_field *f, int32_t *out_dev, void *stream);
  *                             2048, 0 = default); fewer make each workgroup walk
  *                             more groups of chunks.  PDFs are identical; the
  *                             F/T partials are grouped differently (FP64
- *                             rounding only).  Meant for tests. */
-enum { PSM_OPT_GENERAL_PATH = 1, PSM_OPT_XCD_REMAP = 2, PSM_OPT_MAP_LIST = 4, PSM_OPT_SOLID_GRID = 8 };
+ *                             rounding only).  Meant for tests.
+ *   PSM_OPT_CONCURRENT   [1]  1: in steps with a separate face-row launch
+ *                             (odd steps, and every D3Q27 step),
+ *                             psm_stream_collide / psm_step run the solid-cell
+ *                             launch, the F/T sum and the face-row launch on a
+ *                             second stream of the field (default priority,
+ *                             made at pdf_field_create), beside the interior
+ *                             launch on the caller's stream, which waits for
+ *                             them before the call returns its later work;
+ *                             0: all on the caller's stream.  Results are
+ *                             bitwise identical.  Fields made by
+ *                             pdf_field_create_noalloc have no second stream
+ *                             and always run on the caller's stream. */
+enum { PSM_OPT_GENERAL_PATH = 1, PSM_OPT_XCD_REMAP = 2, PSM_OPT_MAP_LIST = 4, PSM_OPT_SOLID_GRID = 8,
+       PSM_OPT_CONCURRENT = 16 };
 int psm_set_option(psm_field *f, int option, int value);
 /* Device-to-device copy kernel (measured-bandwidth probe); 16-byte aligned
  * src and dst. */

@@ -20,7 +20,7 @@ PSM_SHAPE_ELLIPSOID, PSM_SHAPE_CUBE = 0, 1
 PSM_COLL_TRT, PSM_COLL_CUMULANT = 0, 1
 PSM_MAP_SUBSAMPLES, PSM_MAP_BLOCK = 0, 1
 PSM_LAYOUT_SOA, PSM_LAYOUT_BLOCKED = 0, 1
-PSM_OPT_GENERAL_PATH, PSM_OPT_XCD_REMAP, PSM_OPT_MAP_LIST, PSM_OPT_SOLID_GRID = 1, 2, 4, 8
+PSM_OPT_GENERAL_PATH, PSM_OPT_XCD_REMAP, PSM_OPT_MAP_LIST, PSM_OPT_SOLID_GRID, PSM_OPT_CONCURRENT = 1, 2, 4, 8, 16
 PSM_MAX_BODIES = 8
 PSM_STATIC_WORK_BYTES = 16 << 20
 
@@ -31,7 +31,7 @@ EXPORTS = [
     "geometry_field_create", "geometry_field_create_analytic", "geometry_field_destroy", "geometry_map_step",
     "psm_stream_collide", "body_force_torque", "psm_mass_fp64", "psm_macroscopic", "psm_error_flags",
     "psm_set_option", "psm_stream_copy", "psm_set_fraction_offset", "psm_adjoint_step", "psm_adjoint_omega",
-    "psm_step", "lbm_set_obstacle", "psm_rigid_body", "psm_rigid_advance", "psm_coupled_step", "psm_pdf_stride", "psm_adjoint_stride",
+    "psm_step", "lbm_set_obstacle", "psm_rigid_body", "psm_rigid_advance", "psm_coupled_step", "psm_pdf_stride", "psm_adjoint_gather",
     "pdf_field_create_noalloc", "psm_pdf_layout", "psm_pdf_gather", "psm_pdf_scatter",
 ]
 
@@ -104,7 +104,7 @@ def _load():
         "psm_rigid_advance": (C.c_int, [C.POINTER(psm_rigid), dp, C.c_double]),
         "psm_coupled_step": (C.c_int, [vp, C.POINTER(psm_rigid), C.POINTER(vp), C.c_int, i64, vp, dp, vp]),
         "psm_pdf_stride": (C.c_int, [C.POINTER(psm_config), C.POINTER(i64)]),
-        "psm_adjoint_stride": (C.c_int, [C.POINTER(psm_config), C.POINTER(i64)]),
+        "psm_adjoint_gather": (C.c_int, [vp, vp, vp, vp]),
         "psm_pdf_layout": (C.c_int, [C.POINTER(psm_config), i32p, C.POINTER(i64), C.POINTER(i64)]),
         "psm_pdf_gather": (C.c_int, [vp, vp, vp]),
         "psm_pdf_scatter": (C.c_int, [vp, vp, vp]),

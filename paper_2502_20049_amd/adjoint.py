@@ -50,9 +50,8 @@ class TorqueAdjoint:
             raise ValueError("one weight per step")
         self.field = sim.Field(wl, storage=storage, slots=1, device=device)
         self.q, self.N = wl.q, wl.n_cells
-        st = C.c_int64()
-        check(lib.psm_adjoint_stride(C.byref(self.field.cfg), C.byref(st)), "psm_adjoint_stride")
-        self.astride = st.value  # elements between the adjoint buffers' direction arrays
+        # adjoint buffers: the PDF buffer's layout, adjoint-precision elements
+        self.aelems = self.field.pdf.numel()
         L = segment or int(math.ceil(math.sqrt(self.steps)))
         self.L = max(2, L + (L & 1))
         self.adt = torch.float64 if self.field.storage == "f64" else torch.float32
@@ -128,15 +127,14 @@ class TorqueAdjoint:
         return float((w * (self.ft[:, 3:] @ a)).sum().item())
 
     def backward(self):
-        """(dJ/d dB (N,), dJ/dOmega, dJ/d f0 (q, N), a strided view) for the
-        last forward."""
+        """(dJ/d dB (N,), dJ/dOmega, dJ/d f0 (q, N)) for the last forward."""
         q, N = self.q, self.N
         f = self.field
         if not self.store_all and (self._store is None or len(self._store) < self.L):
             self._store = [torch.empty_like(f.pdf) for _ in range(self.L)]
             self._bstore = [torch.empty_like(f.bbuf) for _ in range(self.L)]
-        ahat = [torch.zeros((q, self.astride), dtype=self.adt, device=self.device),
-                torch.empty((q, self.astride), dtype=self.adt, device=self.device)]
+        ahat = [torch.zeros(self.aelems, dtype=self.adt, device=self.device),
+                torch.empty(self.aelems, dtype=self.adt, device=self.device)]
         gB = torch.zeros(N, dtype=self.adt, device=self.device)
         gW = torch.zeros(1, dtype=torch.float64, device=self.device)
         stream = sim._stream()
@@ -165,7 +163,10 @@ class TorqueAdjoint:
                 sim.stream_copy(f.bbuf, self._bstore[t - s0])
             for t in range(s1 - 1, s0 - 1, -1):
                 adjoint_step(t, self._store[t - s0], self._bstore[t - s0])
-        return gB, float(gW.item()), ahat[0][:, :N]
+        gF = torch.empty((q, N), dtype=self.adt, device=self.device)
+        check(lib.psm_adjoint_gather(f.handle, C.c_void_p(ahat[0].data_ptr()), C.c_void_p(gF.data_ptr()), stream),
+              "psm_adjoint_gather")
+        return gB, float(gW.item()), gF
 
 
 class PSMTorque(torch.autograd.Function):

@@ -13,8 +13,9 @@
 //   sum_i b_i dfeq_i/df_j = G_rho + G_u . (c_j - u)/rho,
 //   dfeq_i/drho = feq_i/rho,  dfeq_i/du = w_i rho [3 c_i + 9 (c_i.u) c_i - 3 u],
 //   dS_i/du = w_i [-3 F + 9 (c_i.F) c_i].
-// The forward state is read in the field's own PDF layout (a copy of the PDF
-// buffer); the adjoint PDFs are q arrays of N values a padded stride apart.
+// The forward state (a copy of the PDF buffer) and both adjoint buffers are
+// in the PDF buffer's layout: for a cell, one offset in elements serves all
+// three (the adjoint buffers in the adjoint precision).
 #include "k_stream_collide.hpp"
 
 namespace psm {
@@ -91,15 +92,17 @@ __device__ __forceinline__ double adjoint_cell(const AdjArgs &A, uint32_t row, u
   // Element offsets in 32 bits when every array spans fewer than 2^32 bytes
   // (a uniform base plus a 32-bit lane offset per access), else 64.
   using Off = typename std::conditional<O32, uint32_t, uint64_t>::type;
-  const Off AS = (Off)A.as, DS = (Off)a.dS, NX = (Off)nx;
-  auto frow = [&](uint32_t r) -> Off { return (Off)(r >> a.lrb) * (Off)a.bst + (Off)(r & a.rbm) * NX; };
+  const Off DS = (Off)a.dS, NX = (Off)nx;
+  auto el = [&](int k, uint32_t r, uint32_t xe) -> Off {
+    return (Off)(r >> a.lrb) * (Off)a.bst + (Off)(r & a.rbm) * NX + (Off)k * DS + (Off)xe;
+  };
   auto F = [&](int k, uint32_t r, uint32_t xe) -> const T * {
-    return (const T *)((const char *)A.fwd + (uint64_t)((frow(r) + (Off)k * DS + (Off)xe) * (Off)sizeof(T)));
+    return (const T *)((const char *)A.fwd + (uint64_t)(el(k, r, xe) * (Off)sizeof(T)));
   };
   auto G = [&](int k, uint32_t r, uint32_t xe) -> R {
-    return *(const R *)((const char *)A.ain + (uint64_t)(((Off)k * AS + (Off)r * NX + (Off)xe) * (Off)sizeof(R)));
+    return *(const R *)((const char *)A.ain + (uint64_t)(el(k, r, xe) * (Off)sizeof(R)));
   };
-  auto O = [&](int k) -> R * { return (R *)((char *)A.aout + (uint64_t)(((Off)k * AS + (Off)n) * (Off)sizeof(R))); };
+  auto O = [&](int k) -> R * { return (R *)((char *)A.aout + (uint64_t)(el(k, row, xx) * (Off)sizeof(R))); };
   R d[Q], gh[Q];
   if (bcm == 0) {  // no face direction: plain pulls / pushes with periodic wrap
     sfor<Q>([&](auto K) {

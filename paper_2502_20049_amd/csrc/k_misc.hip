@@ -172,13 +172,12 @@ static hipError_t convert_slab(const SCArgs &a, int q, uint64_t nr, T *d, const 
   return hipGetLastError();
 }
 
-hipError_t launch_pdf_gather(const psm_field &f, void *dst, const void *src, int to_std, hipStream_t st) {
+hipError_t launch_pdf_gather(const psm_field &f, void *dst, const void *src, int to_std, size_t sz, hipStream_t st) {
   const SCArgs a = make_sc_args(f);
   const uint64_t rows = (uint64_t)f.cfg.ny * (uint64_t)f.cfg.nz;
   // slabs of rows whose thread count fits 32 bits, starting on block boundaries
   uint64_t per = ((1ull << 31) - 1) / (uint64_t)f.cfg.nx;
   if (a.bst != 0) per &= ~((1ull << a.lrb) - 1ull);
-  const size_t sz = f.cfg.storage == PSM_F64 ? 8 : (f.cfg.storage == PSM_F32 ? 4 : 2);
   for (uint64_t r0 = 0; r0 < rows; r0 += per) {
     const uint64_t nr = rows - r0 < per ? rows - r0 : per;
     // rows r0 .. r0 + nr - 1: shift the pointers so the kernel's row index starts at 0
@@ -187,9 +186,9 @@ hipError_t launch_pdf_gather(const psm_field &f, void *dst, const void *src, int
     const char *s = (const char *)src + (to_std ? lay_off : std_off) * sz;
     char *d = (char *)dst + (to_std ? std_off : lay_off) * sz;
     hipError_t e;
-    switch (f.cfg.storage) {
-      case PSM_F64: e = convert_slab<double>(a, f.cfg.q, nr, (double *)d, (const double *)s, to_std, st); break;
-      case PSM_F32: e = convert_slab<float>(a, f.cfg.q, nr, (float *)d, (const float *)s, to_std, st); break;
+    switch (sz) {
+      case 8: e = convert_slab<double>(a, f.cfg.q, nr, (double *)d, (const double *)s, to_std, st); break;
+      case 4: e = convert_slab<float>(a, f.cfg.q, nr, (float *)d, (const float *)s, to_std, st); break;
       default: e = convert_slab<_Float16>(a, f.cfg.q, nr, (_Float16 *)d, (const _Float16 *)s, to_std, st);
     }
     if (e != hipSuccess) return e;

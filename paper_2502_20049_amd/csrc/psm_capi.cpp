@@ -24,9 +24,9 @@ int hip_fail(hipError_t e, const char *what) {
 }
 
 hipError_t launch_adjoint(const psm_field &f, const AdjArgs &A, hipStream_t st);
-hipError_t launch_sc_f64(const psm_config &, const SCArgs &, int, hipStream_t, int *, int *);
-hipError_t launch_sc_f32(const psm_config &, const SCArgs &, int, hipStream_t, int *, int *);
-hipError_t launch_sc_f16(const psm_config &, const SCArgs &, int, hipStream_t, int *, int *);
+hipError_t launch_sc_f64(const psm_config &, const SCArgs &, int, hipStream_t, hipStream_t, int *, int *);
+hipError_t launch_sc_f32(const psm_config &, const SCArgs &, int, hipStream_t, hipStream_t, int *, int *);
+hipError_t launch_sc_f16(const psm_config &, const SCArgs &, int, hipStream_t, hipStream_t, int *, int *);
 
 static size_t storage_size(int st) { return st == PSM_F64 ? 8 : (st == PSM_F32 ? 4 : 2); }
 
@@ -106,13 +106,8 @@ static PdfLayout pdf_layout_of(const psm_config &c) {
 
 static int64_t pdf_stride_elems(const psm_config &c) { return pdf_layout_of(c).dstride; }
 
-// Adjoint arrays: N values per direction, the start of each rounded up to a
-// 4 KiB boundary plus 4 KiB (no common offset modulo a large power of two).
+// Adjoint arrays: the PDF buffer's layout (in elements) in the adjoint precision.
 static size_t adjoint_elem_size(const psm_config &c) { return c.storage == PSM_F64 ? 8 : 4; }
-static int64_t adjoint_stride_elems(const psm_config &c) {
-  const int64_t N = (int64_t)c.nx * c.ny * c.nz, sz = (int64_t)adjoint_elem_size(c);
-  return (((N * sz + 4095) / 4096) * 4096 + 4096) / sz;
-}
 
 static Layout layout_of(const psm_config &c) {
   Layout L{};
@@ -313,7 +308,7 @@ int psm_required_bytes(const psm_config *cfg, int which, size_t *out) {
       *out = L.work_bytes;
       return PSM_OK;
     case PSM_BUF_ADJOINT:
-      *out = (size_t)cfg->q * (size_t)adjoint_stride_elems(*cfg) * adjoint_elem_size(*cfg);
+      *out = (size_t)pdf_layout_of(*cfg).elems * adjoint_elem_size(*cfg);
       return PSM_OK;
     case PSM_BUF_GRAD_B:
       *out = (size_t)L.N * (cfg->storage == PSM_F64 ? 8 : 4);
@@ -330,14 +325,6 @@ int psm_pdf_stride(const psm_config *cfg, int64_t *elems) {
   if (r) return r;
   if (!elems) return set_error("null output"), PSM_EINVAL;
   *elems = pdf_stride_elems(*cfg);
-  return PSM_OK;
-}
-
-int psm_adjoint_stride(const psm_config *cfg, int64_t *elems) {
-  int r = check_config(cfg);
-  if (r) return r;
-  if (!elems) return set_error("null output"), PSM_EINVAL;
-  *elems = adjoint_stride_elems(*cfg);
   return PSM_OK;
 }
 
@@ -447,6 +434,23 @@ static int field_create(const psm_config *cfg, void *pdf, size_t pdf_bytes, void
   for (int i = 0; i < PSM_MAX_BODIES; ++i) f->active[i] = empty_box();
   f->opt_xcd_remap = 0;
   f->opt_solid_grid = SOLID_BLOCKS;
+  f->opt_concurrent = 1;
+  if (!static_work) {
+    // the second stream (default priority) and its fork / join events; the
+    // field runs sequentially on the caller's stream if they cannot be made
+    if (hipStreamCreateWithFlags(&f->side, hipStreamNonBlocking) == hipSuccess) {
+      if (hipEventCreateWithFlags(&f->ev_fork, hipEventDisableTiming) != hipSuccess ||
+          hipEventCreateWithFlags(&f->ev_join, hipEventDisableTiming) != hipSuccess) {
+        if (f->ev_fork) hipEventDestroy(f->ev_fork);
+        hipStreamDestroy(f->side);
+        f->side = nullptr;
+        f->ev_fork = nullptr;
+      }
+    } else {
+      f->side = nullptr;
+    }
+    (void)hipGetLastError();
+  }
   f->map_list_max = cfg->psm ? (int)list_cap : 0;
   f->map_list_cap = f->map_list_max;
   f->device = device;
@@ -503,6 +507,12 @@ int pdf_field_destroy(psm_field *f) {
   if (f->static_work && f->device >= 0 && f->device < MAX_DEVICES) {
     const psm_field *mine = f;
     g_scratch_owner[f->device].compare_exchange_strong(mine, nullptr);
+  }
+  if (f->side) {
+    hipStreamSynchronize(f->side);
+    hipEventDestroy(f->ev_fork);
+    hipEventDestroy(f->ev_join);
+    hipStreamDestroy(f->side);
   }
   delete f;
   return PSM_OK;
@@ -854,15 +864,16 @@ static int sc_plan(psm_field *f, const psm_body *bodies, int nb, int64_t step, c
 }
 
 // ft_done (may be null): set when the step's launches also summed the F/T
-// into a.ft_out
-static int sc_launch(psm_field *f, const SCArgs &a, int64_t step, hipStream_t st, int *ft_done = nullptr) {
+// into a.ft_out.  ss: stream of the solid-cell and face-row launches.
+static int sc_launch(psm_field *f, const SCArgs &a, int64_t step, hipStream_t st, hipStream_t ss,
+                     int *ft_done = nullptr) {
   const int parity = (int)(step & 1);
   hipError_t e;
   int sb = 0, fd = 0;
   switch (f->cfg.storage) {
-    case PSM_F64: e = launch_sc_f64(f->cfg, a, parity, st, &sb, &fd); break;
-    case PSM_F32: e = launch_sc_f32(f->cfg, a, parity, st, &sb, &fd); break;
-    default: e = launch_sc_f16(f->cfg, a, parity, st, &sb, &fd); break;
+    case PSM_F64: e = launch_sc_f64(f->cfg, a, parity, st, ss, &sb, &fd); break;
+    case PSM_F32: e = launch_sc_f32(f->cfg, a, parity, st, ss, &sb, &fd); break;
+    default: e = launch_sc_f16(f->cfg, a, parity, st, ss, &sb, &fd); break;
   }
   if (e != hipSuccess) return hip_fail(e, "psm_stream_collide launch");
   f->solid_blocks = sb;
@@ -881,7 +892,10 @@ int geometry_map_step(psm_field *f, const psm_body *bodies, const psm_geom *cons
 }
 
 // ft_dev (may be null): the F/T of the step too, summed by an extra workgroup
-// of the interior launch, else by the separate reduction kernel
+// of the interior launch, else by the separate reduction kernel.  With the
+// field's second stream (PSM_OPT_CONCURRENT, steps with a face-row launch)
+// the solid-cell launch, the F/T sum and the face-row launch run there, beside
+// the interior launch on the caller's stream, which then waits for them.
 static int stream_collide(psm_field *f, const psm_body *bodies, int nb, int64_t step, void *stream,
                           double *ft_dev) {
   if (!f) return set_error("null handle"), PSM_EINVAL;
@@ -890,10 +904,29 @@ static int stream_collide(psm_field *f, const psm_body *bodies, int nb, int64_t 
   SCArgs a;
   int r = sc_plan(f, bodies, nb, step, f->active, a);
   if (r) return r;
-  a.ft_out = (ft_dev && a.nb > 0) ? ft_dev : nullptr;
+  hipStream_t st = (hipStream_t)stream;
+  // the second stream pays for its two cross-stream waits only where the step
+  // has a face-row launch to move off the critical path (odd steps, D3Q27);
+  // even D3Q19 steps take their face rows as extra blocks of the interior launch
+  const bool edge_launch = a.ntiles_e > 0 && !((step & 1) == 0 && f->cfg.q == 19);
+  const bool conc = f->side && f->opt_concurrent && !a.general && edge_launch;
+  if (conc) {
+    hipError_t e = hipEventRecord(f->ev_fork, st);
+    if (e == hipSuccess) e = hipStreamWaitEvent(f->side, f->ev_fork, 0);
+    if (e != hipSuccess) return hip_fail(e, "psm_stream_collide: fork");
+  }
+  a.ft_out = (!conc && ft_dev && a.nb > 0) ? ft_dev : nullptr;
   int done = 0;
-  r = sc_launch(f, a, step, (hipStream_t)stream, &done);
-  if (!r && ft_dev && !done) r = body_force_torque(f, nb, ft_dev, stream);
+  r = sc_launch(f, a, step, st, conc ? f->side : st, &done);
+  if (conc) {
+    if (!r && ft_dev) r = body_force_torque(f, nb, ft_dev, f->side);
+    // join even after a failed launch, so that no work stays behind on the side stream
+    hipError_t e = hipEventRecord(f->ev_join, f->side);
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, f->ev_join, 0);
+    if (!r && e != hipSuccess) r = hip_fail(e, "psm_stream_collide: join");
+  } else if (!r && ft_dev && !done) {
+    r = body_force_torque(f, nb, ft_dev, stream);
+  }
   return r;
 }
 
@@ -1018,6 +1051,7 @@ int psm_set_option(psm_field *f, int option, int value) {
   switch (option) {
     case PSM_OPT_GENERAL_PATH: f->opt_general_path = value ? 1 : 0; return PSM_OK;
     case PSM_OPT_XCD_REMAP: f->opt_xcd_remap = value ? 1 : 0; return PSM_OK;
+    case PSM_OPT_CONCURRENT: f->opt_concurrent = value ? 1 : 0; return PSM_OK;
     case PSM_OPT_SOLID_GRID:
       if (value < 0 || value > SOLID_BLOCKS) return set_error("PSM_OPT_SOLID_GRID takes 0 .. 2048"), PSM_EINVAL;
       f->opt_solid_grid = value ? value : SOLID_BLOCKS;
@@ -1112,7 +1146,6 @@ int psm_adjoint_step(psm_field *f, const void *fwd, int64_t step, const void *ai
   A.s = make_sc_args(*f);
   A.fwd = (const char *)fwd;
   A.parity = (int)(step & 1);
-  A.as = (uint64_t)adjoint_stride_elems(f->cfg);
   size_t pb = 0, ab = 0;
   psm_required_bytes(&f->cfg, PSM_BUF_PDF, &pb);
   psm_required_bytes(&f->cfg, PSM_BUF_ADJOINT, &ab);
@@ -1142,16 +1175,32 @@ int psm_adjoint_omega(psm_field *f, double *out, void *stream) {
   return PSM_OK;
 }
 
+// `lay` (a buffer in the PDF buffer's layout, `lay_bytes` long) to or from the
+// standard [q][N] array `std_arr`, elements of sz bytes
+static int layout_convert(psm_field *f, void *lay, size_t lay_bytes, void *std_arr, int to_std, size_t sz,
+                          void *stream) {
+  const size_t bytes = (size_t)f->cfg.q * (size_t)f->N * sz;
+  const char *p = (const char *)lay, *o = (const char *)std_arr;
+  if (o < p + lay_bytes && p < o + bytes) return set_error("the standard-layout array overlaps the buffer"), PSM_EINVAL;
+  hipError_t e = to_std ? launch_pdf_gather(*f, std_arr, lay, 1, sz, (hipStream_t)stream)
+                        : launch_pdf_gather(*f, lay, std_arr, 0, sz, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "layout conversion launch");
+  return PSM_OK;
+}
+
 static int pdf_convert(psm_field *f, void *dst, const void *src, int to_std, void *stream) {
   if (!f || !dst || !src) return set_error("null argument"), PSM_EINVAL;
-  const size_t bytes = (size_t)f->cfg.q * (size_t)f->N * storage_size(f->cfg.storage);
-  const char *p = (const char *)f->pdf, *o = (const char *)(to_std ? dst : src);
   size_t pb;
   psm_required_bytes(&f->cfg, PSM_BUF_PDF, &pb);
-  if (o < p + pb && p < o + bytes) return set_error("the standard-layout array overlaps the PDF buffer"), PSM_EINVAL;
-  hipError_t e = launch_pdf_gather(*f, dst, src, to_std, (hipStream_t)stream);
-  if (e != hipSuccess) return hip_fail(e, "psm_pdf_gather / psm_pdf_scatter launch");
-  return PSM_OK;
+  return layout_convert(f, f->pdf, pb, to_std ? dst : const_cast<void *>(src), to_std, storage_size(f->cfg.storage),
+                        stream);
+}
+
+int psm_adjoint_gather(psm_field *f, const void *adj, void *dst, void *stream) {
+  if (!f || !adj || !dst) return set_error("null argument"), PSM_EINVAL;
+  size_t ab;
+  psm_required_bytes(&f->cfg, PSM_BUF_ADJOINT, &ab);
+  return layout_convert(f, const_cast<void *>(adj), ab, dst, 1, adjoint_elem_size(f->cfg), stream);
 }
 
 int psm_pdf_gather(psm_field *f, void *dst, void *stream) {

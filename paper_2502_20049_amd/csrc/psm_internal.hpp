@@ -164,9 +164,8 @@ struct AdjArgs {
   SCArgs s;           // field geometry, faces, rates, B pointers
   const char *fwd;    // forward state before step t (storage type, parity t&1), the PDF buffer's layout
   int parity;
-  uint64_t as;        // elements between the direction arrays of ain / aout
   int o32;            // the PDF copy and both adjoint arrays each span < 2^32 bytes
-  const void *ain;    // fhat(t+1), q arrays of N values, adjoint precision
+  const void *ain;    // fhat(t+1): the PDF buffer's layout, adjoint precision
   void *aout;         // fhat(t)
   void *dJdB;         // accumulated, [N], adjoint precision
   double X[3], V[3], W[3], axis[3];
@@ -252,6 +251,12 @@ struct psm_field {
   int opt_xcd_remap;
   int opt_solid_grid;
   int opt_whole_domain;  // B may be nonzero anywhere (offset field set)
+  int opt_concurrent;    // PSM_OPT_CONCURRENT
+  // second stream of the field (null for fields on the static work area): the
+  // solid-cell and face-row launches of a step run on it beside the interior
+  // launch, forked from and joined back into the caller's stream by events
+  hipStream_t side;
+  hipEvent_t ev_fork, ev_join;
   const float *dB;       // caller-owned offset added to the slot-0 fraction
   // static obstacle (plain-LBM fields; null: none)
   uint8_t *ocls;
@@ -286,7 +291,8 @@ hipError_t launch_macro(const psm_field &f, int parity, double *rho, double *u, 
 hipError_t launch_mass_final(const double *partials, uint32_t n, double *out, hipStream_t st);
 hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t st);
 hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t st);
-hipError_t launch_pdf_gather(const psm_field &f, void *dst, const void *src, int to_std, hipStream_t st);
+// a buffer in the PDF buffer's layout to (to_std) or from [q][N], elements of sz bytes
+hipError_t launch_pdf_gather(const psm_field &f, void *dst, const void *src, int to_std, size_t sz, hipStream_t st);
 hipError_t launch_flags_copy(const int32_t *src, int32_t *dst, hipStream_t st);
 uint32_t macro_blocks(const psm_field &f);
 hipError_t launch_sum_accumulate(const double *p, uint32_t n, double *out, hipStream_t st);

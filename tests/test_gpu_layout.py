@@ -249,3 +249,46 @@ def test_blocked_channel_256_full_size_equals_soa(sim, gc):
         _assert_same(a, b)
         del a, b
         torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("case", ["channel_q19_f32", "channel_q19_f16_h2", "zpipe_q27_f32", "periodic_q19_f32_two_sc2",
+                                  "cumulant_q27_f16"])
+def test_second_stream_bitwise_equals_one_stream(sim, gc, case):
+    """The solid-cell, F/T and face-row launches on the field's second stream
+    (the default) against every launch on the caller's stream: the same PDFs,
+    F/T, B and mass bit for bit, over whole psm_step calls."""
+    from paper_2502_20049_amd import _capi as capi
+
+    build, steps = CASES[case]
+    wl = _blocked(build())
+    _say(f"[second stream] {case}: {steps} steps")
+    a, b = _run_pair_option(sim, gc, wl, steps, capi.PSM_OPT_CONCURRENT)
+    _assert_same(a, b)
+
+
+def _run_pair_option(sim, gc, wl, steps, opt, seed=5):
+    """The same steps with option `opt` at 1 and at 0, from one seeded state."""
+    import torch
+
+    out = []
+    for v in (1, 0):
+        f = sim.Field(wl)
+        f.set_option(opt, v)
+        gc.load_random_state(f, seed)
+        fts = []
+        ftb = torch.zeros((max(1, f.nb), 6), dtype=torch.float64, device="cuda")
+        for t in range(steps):
+            # the step's own F/T sum (psm_step), and body_force_torque after it
+            f.step(t, ft=ftb if f.nb else None)
+            if f.nb:
+                fts.append(ftb[: f.nb].clone())
+                fts.append(f.force_torque().clone())
+        torch.cuda.synchronize()
+        r = {"pdf": f.pdf_std().clone(), "ft": torch.stack(fts) if fts else None, "mass": f.mass(steps).item()}
+        if f.nb:
+            B, meta = f.b_view()
+            r["B"], r["meta"] = B.clone(), meta.clone()
+        r["flags"] = f.error_flags().cpu().numpy()[0]
+        out.append(r)
+        del f
+    return out
