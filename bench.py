@@ -512,10 +512,11 @@ def main():
 
     import torch
 
-    from paper_2502_20049_amd import _capi as capi
     from paper_2502_20049_amd import sim
 
     torch.cuda.set_device(0)
+    if args.sequential:
+        sim.CONCURRENT_DEFAULT = False
     if args.adjoint_only:
         print(json.dumps(adjoint_rate()), flush=True)
         return
@@ -541,8 +542,6 @@ def main():
         wl.storage = args.storage
     storage = wl.storage
     f = sim.Field(wl)
-    if args.sequential:
-        f.set_option(capi.PSM_OPT_CONCURRENT, 0)
     wall, t_end = time_field(f, args.steps, args.warmup)
     sc_ms, map_ms = time_kernels(f, min(args.steps, 300), t_end)
     N = wl.n_cells

@@ -111,13 +111,18 @@ class Geometry:
             self.handle = _vp()
 
 
+# PSM_OPT_CONCURRENT of new fields (None: the library's default)
+CONCURRENT_DEFAULT = None
+
+
 class Field:
     """One lattice on the current device; ``wl`` is a psm_inputs.Workload."""
 
     def __init__(self, wl, storage=None, psm=True, slots=None, max_bodies=None, device="cuda", remap_every_step=True,
-                 fused=True, noalloc=False):
+                 fused=True, noalloc=False, concurrent=None):
         """``noalloc``: create the handle with pdf_field_create_noalloc (the
-        library's static work area instead of a caller work buffer)."""
+        library's static work area instead of a caller work buffer).
+        ``concurrent``: PSM_OPT_CONCURRENT (None: CONCURRENT_DEFAULT)."""
         self.wl = wl
         self.storage = storage or wl.storage
         self.cfg = make_config(wl, self.storage, psm, slots, max_bodies)
@@ -144,6 +149,9 @@ class Field:
                                        C.c_void_p(self.bbuf.data_ptr()) if bb else None, bb,
                                        C.c_void_p(self.work.data_ptr()), wb, _stream(), C.byref(self.handle)),
                   "pdf_field_create")
+        conc = CONCURRENT_DEFAULT if concurrent is None else concurrent
+        if conc is not None:
+            check(lib.psm_set_option(self.handle, capi.PSM_OPT_CONCURRENT, int(bool(conc))), "psm_set_option")
         self.psm = bool(psm)
         self.bodies = list(wl.bodies) if psm else []
         self.geoms = [Geometry(b.shape, b.s, device) for b in self.bodies]
