@@ -161,7 +161,7 @@ const char *psm_last_error(void);
  *        elements (psm_pdf_layout)
  *   B    psm ? N*4*slots + N (FP32 fraction per slot + one body-id byte) : 0
  *   WORK flags + force/torque partials (max_bodies*6 doubles per solid-kernel
- *        workgroup, 2048 of them) + reduction scratch + the mapping's lists
+ *        workgroup, 4096 of them) + reduction scratch + the mapping's lists
  *        of surface cells (psm ? max_bodies * 2^21 * 4 bytes : 0)
  *   ADJOINT  one adjoint PDF buffer of psm_adjoint_step: the PDF buffer's
  *        layout (psm_pdf_layout, in elements) with adjoint-precision
@@ -449,8 +449,8 @@ int psm_error_flags(psm_field *f, int32_t *out_dev, void *stream);
  *                             a second kernel (three cells per wave); cells beyond it,
  *                             and every cell with 0, are sampled in the
  *                             classification kernel.  Results are identical.
- *   PSM_OPT_SOLID_GRID [2048] most workgroups of the solid-cell kernel (1 ..
- *                             2048, 0 = default); fewer make each workgroup walk
+ *   PSM_OPT_SOLID_GRID [4096] most workgroups of the solid-cell kernel (1 ..
+ *                             4096, 0 = default); fewer make each workgroup walk
  *                             more groups of chunks.  PDFs are identical; the
  *                             F/T partials are grouped differently (FP64
  *                             rounding only).  Meant for tests.

@@ -1053,7 +1053,7 @@ int psm_set_option(psm_field *f, int option, int value) {
     case PSM_OPT_XCD_REMAP: f->opt_xcd_remap = value ? 1 : 0; return PSM_OK;
     case PSM_OPT_CONCURRENT: f->opt_concurrent = value ? 1 : 0; return PSM_OK;
     case PSM_OPT_SOLID_GRID:
-      if (value < 0 || value > SOLID_BLOCKS) return set_error("PSM_OPT_SOLID_GRID takes 0 .. 2048"), PSM_EINVAL;
+      if (value < 0 || value > SOLID_BLOCKS) return set_error("PSM_OPT_SOLID_GRID takes 0 .. 4096"), PSM_EINVAL;
       f->opt_solid_grid = value ? value : SOLID_BLOCKS;
       return PSM_OK;
     case PSM_OPT_MAP_LIST:

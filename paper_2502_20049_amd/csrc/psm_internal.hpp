@@ -86,7 +86,7 @@ struct BodyK {
 
 // workgroups of the solid-cell kernel (fixed: its per-body partial sums are
 // independent of the grid size)
-constexpr int SOLID_BLOCKS = 2048;
+constexpr int SOLID_BLOCKS = 4096;
 // at most this many 256-cell chunks per workgroup group of the solid kernel
 constexpr int SOLID_MAX_CPW = 8;
 

@@ -166,7 +166,7 @@ def test_solid_grid_option_pdfs_bitwise(sim, gc):
     d = (res[0][1] - res[1][1]).abs().max().item() / res[0][1].abs().max().item()
     _say(f"[solid_grid 192] F/T rel diff {d:.1e}")
     assert d < 1e-12
-    for bad in (-1, 2049):
+    for bad in (-1, 4097):
         assert capi.lib.psm_set_option(f.handle, 8, bad) == capi.PSM_EINVAL
 
 
