@@ -77,7 +77,7 @@ def run_steps(field, t0, n, events=None, map_events=None, fused=True):
         t = t0 + i
         poses = field.poses(t) if field.nb else None
         if fused:
-            field.step(t, poses, ft=field.ft if field.nb else None)
+            field.step(t, ft=field.ft if field.nb else None)
             continue
         if field.nb and (field.remap_every_step or not field._mapped_once):
             if map_events is not None:

@@ -107,6 +107,9 @@ enum { PSM_LAYOUT_SOA = 0, PSM_LAYOUT_BLOCKED = 1 };            /* PDF buffer la
  *   block_rows  rows per block of the blocked layout: a power of two, or 0
  *            for the library's choice (the largest RB with RB*nx*sizeof
  *            (storage) <= 16 KiB, at least one row); 0 for PSM_LAYOUT_SOA
+ *   map_ahead  1: the field keeps two sets of solid fractions, so that
+ *            psm_step_ahead can map the next step into one while this step
+ *            reads the other (PSM_BUF_B twice as large); 0: one set.  psm = 1
  */
 typedef struct psm_config {
   int32_t nx, ny, nz;
@@ -126,6 +129,7 @@ typedef struct psm_config {
   int32_t map_reading;
   int32_t layout;
   int32_t block_rows;
+  int32_t map_ahead;
 } psm_config;
 
 /* Pose and velocity of one rigid body at one step: a body-frame point p is at
@@ -159,7 +163,9 @@ const char *psm_last_error(void);
  *        [k*S, k*S + N) with S = psm_pdf_stride(cfg) >= N (cell n = x +
  *        nx*(y + ny*z)); blocked: ceil(ny*nz / RB) blocks of q*RB*nx
  *        elements (psm_pdf_layout)
- *   B    psm ? N*4*slots + N (FP32 fraction per slot + one body-id byte) : 0
+ *   B    psm ? N*4*slots + N (FP32 fraction per slot + one body-id byte) : 0;
+ *        map_ahead: two such sets, the second at the first's size rounded up
+ *        to 256 bytes
  *   WORK flags + force/torque partials (max_bodies*6 doubles per solid-kernel
  *        workgroup, 4096 of them) + reduction scratch + the mapping's lists
  *        of surface cells (psm ? max_bodies * 2^21 * 4 bytes : 0)
@@ -311,6 +317,29 @@ int body_force_torque(psm_field *f, int n_bodies, double *ft_dev, void *stream);
  * readable by a later body_force_torque. */
 int psm_step(psm_field *f, const psm_body *map_poses, const psm_body *bodies, const psm_geom *const *geoms,
              int n_bodies, int64_t step, double *ft_dev, void *stream);
+
+/* psm_step with the mapping one step ahead (section III's per-step mapping,
+ * overlapped with the update), for fields made with map_ahead = 1 and motion
+ * known a step in advance.  Step `step` uses the fractions that the previous
+ * call mapped from its next_map_poses when that call was for step - 1 with the
+ * same n_bodies, else (the first call, or after geometry_map_step,
+ * psm_field_reset or another step) it maps them from map_poses (NULL =
+ * bodies) first.  It then runs psm_stream_collide(bodies, step) (+ the F/T
+ * sum into ft_dev) and maps step + 1 from next_map_poses into the field's
+ * other set of fractions on a mapping stream of the field (made at
+ * pdf_field_create, default priority), forked from `stream` at the start of
+ * the step and joined back into it before the call's later work: the mapping
+ * overlaps the step's launches.
+ * The results equal psm_step(map_poses, bodies, step) bit for bit, provided
+ * next_map_poses are the map poses of the next call.  PSM_EUNSUP without
+ * map_ahead; fields from pdf_field_create_noalloc map on `stream`. */
+int psm_step_ahead(psm_field *f, const psm_body *map_poses, const psm_body *bodies, const psm_body *next_map_poses,
+                   const psm_geom *const *geoms, int n_bodies, int64_t step, double *ft_dev, void *stream);
+
+/* Device pointers of the fractions the last step used (map_ahead fields swap
+ * between two sets): slot 0, slot 1 (NULL with one slot) and the body-id
+ * bytes.  Any output pointer may be NULL. */
+int psm_fractions(psm_field *f, const float **b0, const float **b1, const uint8_t **meta);
 
 /* ---- sensitivities (adjoint) ------------------------------------------------ */
 /* Optional time-invariant offset field dB (device, N floats, caller-owned,

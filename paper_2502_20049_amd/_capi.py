@@ -31,7 +31,7 @@ EXPORTS = [
     "geometry_field_create", "geometry_field_create_analytic", "geometry_field_destroy", "geometry_map_step",
     "psm_stream_collide", "body_force_torque", "psm_mass_fp64", "psm_macroscopic", "psm_error_flags",
     "psm_set_option", "psm_stream_copy", "psm_set_fraction_offset", "psm_adjoint_step", "psm_adjoint_omega",
-    "psm_step", "lbm_set_obstacle", "psm_rigid_body", "psm_rigid_advance", "psm_coupled_step", "psm_pdf_stride", "psm_adjoint_gather",
+    "psm_step", "lbm_set_obstacle", "psm_rigid_body", "psm_rigid_advance", "psm_coupled_step", "psm_pdf_stride", "psm_adjoint_gather", "psm_step_ahead", "psm_fractions",
     "pdf_field_create_noalloc", "psm_pdf_layout", "psm_pdf_gather", "psm_pdf_scatter",
 ]
 
@@ -48,7 +48,7 @@ class psm_config(C.Structure):
                 ("slots", C.c_int32), ("max_bodies", C.c_int32), ("bc", C.c_int32 * 6),
                 ("tau", C.c_double), ("magic", C.c_double), ("force", C.c_double * 3),
                 ("u_in", C.c_double * 3), ("collision", C.c_int32), ("map_reading", C.c_int32),
-                ("layout", C.c_int32), ("block_rows", C.c_int32)]
+                ("layout", C.c_int32), ("block_rows", C.c_int32), ("map_ahead", C.c_int32)]
 
 
 class psm_body(C.Structure):
@@ -90,6 +90,9 @@ def _load():
         "geometry_map_step": (C.c_int, [vp, C.POINTER(psm_body), C.POINTER(vp), C.c_int, vp]),
         "psm_stream_collide": (C.c_int, [vp, C.POINTER(psm_body), C.c_int, i64, vp]),
         "psm_step": (C.c_int, [vp, C.POINTER(psm_body), C.POINTER(psm_body), C.POINTER(vp), C.c_int, i64, vp, vp]),
+        "psm_step_ahead": (C.c_int, [vp, C.POINTER(psm_body), C.POINTER(psm_body), C.POINTER(psm_body), C.POINTER(vp),
+                                     C.c_int, i64, vp, vp]),
+        "psm_fractions": (C.c_int, [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp)]),
         "body_force_torque": (C.c_int, [vp, C.c_int, vp, vp]),
         "psm_mass_fp64": (C.c_int, [vp, i64, vp, vp]),
         "psm_macroscopic": (C.c_int, [vp, i64, vp, vp, vp]),

@@ -48,7 +48,7 @@ class TorqueAdjoint:
         self.weights = [float(w) for w in weights]
         if len(self.weights) != self.steps:
             raise ValueError("one weight per step")
-        self.field = sim.Field(wl, storage=storage, slots=1, device=device)
+        self.field = sim.Field(wl, storage=storage, slots=1, device=device, map_ahead=False)
         self.q, self.N = wl.q, wl.n_cells
         # adjoint buffers: the PDF buffer's layout, adjoint-precision elements
         self.aelems = self.field.pdf.numel()

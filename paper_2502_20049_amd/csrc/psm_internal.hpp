@@ -257,6 +257,19 @@ struct psm_field {
   // launch, forked from and joined back into the caller's stream by events
   hipStream_t side;
   hipEvent_t ev_fork, ev_join;
+  // map_ahead: the other set of fractions and its mapping state (swapped with
+  // the current one by psm_step_ahead), the stream that maps into it, and
+  // the step it holds when ahead_valid
+  float *B0x, *B1x;
+  uint8_t *metax;
+  psm::IBox activex[PSM_MAX_BODIES];
+  bool have_prevx[PSM_MAX_BODIES];
+  int nb_mappedx;
+  bool ahead_valid;
+  int64_t ahead_step;
+  int ahead_nb;
+  hipStream_t mstream;
+  hipEvent_t ev_mfork, ev_mjoin;
   const float *dB;       // caller-owned offset added to the slot-0 fraction
   // static obstacle (plain-LBM fields; null: none)
   uint8_t *ocls;

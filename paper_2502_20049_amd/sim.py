@@ -33,7 +33,7 @@ def lattice(q: int):
     return c.reshape(q, 3), w, o
 
 
-def make_config(wl, storage=None, psm=True, slots=None, max_bodies=None) -> capi.psm_config:
+def make_config(wl, storage=None, psm=True, slots=None, max_bodies=None, map_ahead=False) -> capi.psm_config:
     cfg = capi.psm_config()
     cfg.nx, cfg.ny, cfg.nz, cfg.q = wl.nx, wl.ny, wl.nz, wl.q
     cfg.storage = STORAGE[storage or wl.storage][0]
@@ -51,6 +51,7 @@ def make_config(wl, storage=None, psm=True, slots=None, max_bodies=None) -> capi
     cfg.map_reading = getattr(wl, "map_reading", 0)
     cfg.layout = {"soa": capi.PSM_LAYOUT_SOA, "blocked": capi.PSM_LAYOUT_BLOCKED}[getattr(wl, "layout", "soa")]
     cfg.block_rows = getattr(wl, "block_rows", 0)
+    cfg.map_ahead = 1 if (map_ahead and psm) else 0
     return cfg
 
 
@@ -113,19 +114,25 @@ class Geometry:
 
 # PSM_OPT_CONCURRENT of new fields (None: the library's default)
 CONCURRENT_DEFAULT = None
+# map_ahead of new PSM fields when not given: Field.step then maps the next
+# step on the field's mapping stream during this one (prescribed motion)
+MAP_AHEAD_DEFAULT = True
 
 
 class Field:
     """One lattice on the current device; ``wl`` is a psm_inputs.Workload."""
 
     def __init__(self, wl, storage=None, psm=True, slots=None, max_bodies=None, device="cuda", remap_every_step=True,
-                 fused=True, noalloc=False, concurrent=None):
+                 fused=True, noalloc=False, concurrent=None, map_ahead=None):
         """``noalloc``: create the handle with pdf_field_create_noalloc (the
         library's static work area instead of a caller work buffer).
-        ``concurrent``: PSM_OPT_CONCURRENT (None: CONCURRENT_DEFAULT)."""
+        ``concurrent``: PSM_OPT_CONCURRENT (None: CONCURRENT_DEFAULT).
+        ``map_ahead``: two sets of fractions and psm_step_ahead in step()
+        (None: MAP_AHEAD_DEFAULT)."""
         self.wl = wl
         self.storage = storage or wl.storage
-        self.cfg = make_config(wl, self.storage, psm, slots, max_bodies)
+        self.map_ahead = bool(psm) and bool(MAP_AHEAD_DEFAULT if map_ahead is None else map_ahead)
+        self.cfg = make_config(wl, self.storage, psm, slots, max_bodies, self.map_ahead)
         self.q = wl.q
         self.N = wl.n_cells
         self.dtype = STORAGE[self.storage][1]
@@ -192,8 +199,12 @@ class Field:
         """(slots, N) float32 solid fractions and (N,) uint8 body ids."""
         n = self.N
         s = self.cfg.slots
-        B = self.bbuf[: 4 * n * s].view(torch.float32).view(s, n)
-        meta = self.bbuf[4 * n * s: 4 * n * s + n]
+        b0, meta_p = C.c_void_p(), C.c_void_p()
+        check(lib.psm_fractions(self.handle, C.byref(b0), None, C.byref(meta_p)), "psm_fractions")
+        o = b0.value - self.bbuf.data_ptr()  # the set the last step used (map_ahead: one of two)
+        B = self.bbuf[o: o + 4 * n * s].view(torch.float32).view(s, n)
+        m = meta_p.value - self.bbuf.data_ptr()
+        meta = self.bbuf[m: m + n]
         return B, meta
 
     def reset(self):
@@ -222,6 +233,13 @@ class Field:
         """Map B(t) (every step, or once for static scenes) and advance from t
         to t+1; with ``ft`` (a (n_bodies, 6) float64 device tensor) also sum the
         force/torque of the step into it."""
+        if self.nb and self.fused and self.map_ahead and self.remap_every_step and poses is None:
+            poses, nxt = self.poses(t), self.poses(t + 1)
+            check(lib.psm_step_ahead(self.handle, poses, poses, nxt, self._geom_ptrs, self.nb, int(t),
+                                     C.c_void_p(ft.data_ptr()) if ft is not None else None, _stream()),
+                  "psm_step_ahead")
+            self._mapped_once = True
+            return
         poses = poses if poses is not None else (self.poses(t) if self.nb else None)
         if self.nb and self.fused and (self.remap_every_step or not self._mapped_once):
             check(lib.psm_step(self.handle, poses, poses, self._geom_ptrs, self.nb, int(t),

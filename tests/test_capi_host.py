@@ -61,6 +61,10 @@ def test_required_bytes(capi, sim):
     assert sim.required_bytes(cfg, capi.PSM_BUF_B) == N * 4 + N
     cfg.slots = 2
     assert sim.required_bytes(cfg, capi.PSM_BUF_B) == 2 * N * 4 + N
+    # two sets of fractions, the second 256-byte aligned
+    cfg.map_ahead = 1
+    assert sim.required_bytes(cfg, capi.PSM_BUF_B) == 2 * ((2 * N * 4 + N + 255) // 256 * 256)
+    cfg.map_ahead = 0
     cfg.q, cfg.storage = 27, capi.PSM_F16
     assert sim.required_bytes(cfg, capi.PSM_BUF_PDF) == 27 * stride(2) * 2
     assert sim.required_bytes(cfg, capi.PSM_BUF_OBSTACLE) == 0
@@ -84,7 +88,7 @@ def test_noalloc_rejects_lattices_beyond_the_static_area(capi, sim):
 @pytest.mark.parametrize("field,value,code", [
     ("q", 15, -1), ("storage", 7, -1), ("sc", 4, -1), ("slots", 3, -1), ("tau", 0.5, -1),
     ("b_form", 2, -1), ("max_bodies", 9, -1), ("nx", 0, -1), ("map_reading", 2, -1), ("map_reading", -1, -1),
-    ("layout", 2, -1), ("block_rows", 4, -1),
+    ("layout", 2, -1), ("block_rows", 4, -1), ("map_ahead", 2, -1), ("map_ahead", -1, -1),
 ])
 def test_config_validation(capi, sim, field, value, code):
     cfg = _cfg(sim)
@@ -273,6 +277,13 @@ def test_new_entry_points_reject_null_arguments(capi, sim):
     assert capi.lib.psm_rigid_body(None, None) == capi.PSM_EINVAL
     s = capi.psm_rigid()
     assert capi.lib.psm_rigid_advance(C.byref(s), None, 1.0) == capi.PSM_EINVAL
+    assert capi.lib.psm_step_ahead(None, None, None, None, None, 1, 0, None, None) == capi.PSM_EINVAL
+    assert capi.lib.psm_fractions(None, None, None, None) == capi.PSM_EINVAL
+    # map_ahead needs a PSM field
+    cfg.psm, cfg.map_ahead = 0, 1
+    n = C.c_size_t()
+    assert capi.lib.psm_required_bytes(C.byref(cfg), 0, C.byref(n)) == capi.PSM_EINVAL
+    assert "map_ahead" in capi.last_error()
 
 
 @pytest.mark.parametrize("shape,storage,rows", [((70, 22, 13), 1, 0), ((256, 256, 256), 1, 0), ((256, 8, 8), 2, 0),

@@ -292,3 +292,60 @@ def _run_pair_option(sim, gc, wl, steps, opt, seed=5):
         out.append(r)
         del f
     return out
+
+
+def _run_steps_ahead(sim, gc, wl, steps, ahead, seed=9, plain_steps=()):
+    """Steps 0..steps-1 through Field.step on a field with or without
+    map_ahead (psm_step_ahead / psm_step), from one seeded state; the steps in
+    `plain_steps` go through psm_step (explicit poses) on either field."""
+    import torch
+
+    f = sim.Field(wl, map_ahead=ahead)
+    gc.load_random_state(f, seed)
+    fts = []
+    ftb = torch.zeros((max(1, f.nb), 6), dtype=torch.float64, device="cuda")
+    for t in range(steps):
+        if t in plain_steps:
+            f.step(t, poses=f.poses(t), ft=ftb)
+        else:
+            f.step(t, ft=ftb)
+        fts.append(ftb[: f.nb].clone())
+    torch.cuda.synchronize()
+    B, meta = f.b_view()
+    r = {"pdf": f.pdf_std().clone(), "ft": torch.stack(fts), "mass": f.mass(steps).item(), "B": B.clone(),
+         "meta": meta.clone(), "flags": f.error_flags().cpu().numpy()[0]}
+    del f
+    return r
+
+
+@pytest.mark.parametrize("case", ["channel_q19_f32", "channel_q19_f16_h2", "zpipe_q27_f32", "periodic_q19_f32_two_sc2",
+                                  "periodic_q27_f32_two_sc3", "cumulant_q27_f16", "wide_300_q19_f16"])
+def test_map_ahead_bitwise_equals_psm_step(sim, gc, case):
+    """psm_step_ahead (the next step mapped into the second set of fractions
+    on the mapping stream during this step) against psm_step on a one-set
+    field: PDFs, the step's F/T, the last step's B and body ids, mass and
+    error flags bit for bit, including a psm_step in the middle of the run
+    (the next psm_step_ahead maps its own step first)."""
+    build, steps = CASES[case]
+    wl = _blocked(build())
+    steps = max(steps, 6)
+    _say(f"[map ahead] {case}: {steps} steps")
+    ref = _run_steps_ahead(sim, gc, wl, steps, False)
+    a = _run_steps_ahead(sim, gc, wl, steps, True)
+    _assert_same(ref, a)
+    b = _run_steps_ahead(sim, gc, wl, steps, True, plain_steps=(3,))
+    _assert_same(ref, b)
+
+
+def test_map_ahead_refused_without_second_set(sim):
+    """psm_step_ahead on a field with one set of fractions: PSM_EUNSUP."""
+    from paper_2502_20049_amd import _capi as capi
+
+    wl = _small(19, "f32", ("periodic",) * 6)
+    f = sim.Field(wl, map_ahead=False)
+    p0, p1 = f.poses(0), f.poses(1)
+    r = capi.lib.psm_step_ahead(f.handle, p0, p0, p1, f._geom_ptrs, f.nb, 0, None, None)
+    assert r == capi.PSM_EUNSUP and "map_ahead" in capi.last_error()
+    g = sim.Field(wl, map_ahead=True)
+    assert capi.lib.psm_step_ahead(g.handle, p0, p0, None, g._geom_ptrs, g.nb, 0, None, None) == capi.PSM_EINVAL
+    assert g.bbuf.numel() >= 2 * (wl.n_cells * 5)
