@@ -1082,8 +1082,12 @@ __global__ __launch_bounds__(256) void k_obstacle(const SCArgs a) {
 // workgroup (fixed order: deterministic).  A cell inside several boxes is
 // taken by the lowest-index box.
 // ---------------------------------------------------------------------------
+// D3Q19 even steps with one fraction slot and FP32 or FP16 storage fit four
+// waves per SIMD without spills (128 VGPRs; rotor box +1.1%); the other
+// instantiations keep the compiler's choice (four waves there spill).
 template <int Q, typename T, int PAR, int SC, int CM, int NS>
-__global__ __launch_bounds__(256) void k_solid(const SCArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
+    (PAR == 0 && NS == 1 && Q == 19 && sizeof(T) <= 4) ? 4 : 1, 8))) void k_solid(const SCArgs a) {
   using R = typename Comp<T>::type;
   __shared__ double wacc[4][PSM_MAX_BODIES][6];  // per-wave F/T sums (each wave writes only its own)
   // listed cells: fewer than 256 left over from earlier groups, then this group's
