@@ -557,6 +557,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl.name, "cells": N, "q": wl.q, "storage": storage, "layout": wl.layout,
                    "launches": "one stream" if args.sequential else "solid and face rows on a second stream",
+                   "mapping": "next step mapped during this one (psm_step_ahead)" if f.map_ahead else "psm_step",
                    "bodies": len(wl.bodies),
                    "supersampling_s": [b.s for b in wl.bodies], "bc": list(wl.bc), "parallelism": "1 GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
@@ -566,7 +567,7 @@ def main():
                      "avg_launch_ms": round(sc_ms, 5)},
         "kernels_ms": {"psm_stream_collide": round(sc_ms, 5), "geometry_map_step": round(map_ms, 5),
                        "note": "HIP events around back-to-back calls of each after the timed steps (which "
-                               "run psm_step)"},
+                               "run whole steps)"},
     }
     del f
     torch.cuda.empty_cache()
