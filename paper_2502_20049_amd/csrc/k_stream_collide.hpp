@@ -944,9 +944,13 @@ __device__ __forceinline__ void fluid_seg_h2(const SCArgs &a, int x0, int y, int
 
 // Odd steps with 16-bit storage and rows of a multiple of 128 cells:
 // interior rows in segments of 128 cells, one segment per wave
-// (fluid_seg_h2).  Other row lengths take k_fluid.
+// (fluid_seg_h2).  Other row lengths take k_fluid.  The D3Q27 PSM
+// instantiation is held to four waves per SIMD (130 -> 128 VGPRs, 12 bytes
+// of spills per lane: rotor pair 3.28 -> 3.02 ms per call); five for D3Q19
+// spills more and is slower.
 template <int Q, bool PSM, int CM = 0>
-__global__ __launch_bounds__(256) void k_fluid_h2odd(const SCArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((Q == 27 && PSM) ? 4 : 1, 8))) void k_fluid_h2odd(
+    const SCArgs a) {
   const int nsx = a.nx / 128;
   // wave-uniform (one segment per wave): the row arithmetic stays scalar
   const uint32_t seg = (uint32_t)__builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4u + (threadIdx.x >> 6)));
