@@ -420,6 +420,7 @@ static int field_create(const psm_config *cfg, void *pdf, size_t pdf_bytes, void
     f->bstride = PL.bstride;
   }
   if (cfg->psm) {
+    f->bbase = b;
     f->B0 = (float *)b;
     f->B1 = cfg->slots == 2 ? (float *)b + L.N : nullptr;
     f->meta = (uint8_t *)((float *)b + L.N * cfg->slots);
@@ -560,8 +561,9 @@ int psm_field_reset(psm_field *f, void *stream) {
   psm_required_bytes(&f->cfg, PSM_BUF_PDF, &need);
   hipError_t e = launch_fill_zero(f->pdf, need, st);
   if (e == hipSuccess && f->cfg.psm) {
+    // the whole buffer from its start: with map_ahead, B0 may be the second set
     psm_required_bytes(&f->cfg, PSM_BUF_B, &need);
-    e = launch_fill_zero(f->B0, need, st);
+    e = launch_fill_zero(f->bbase, need, st);
   }
   if (e == hipSuccess) e = launch_fill_zero(f->work, 256, st);
   if (e != hipSuccess) return hip_fail(e, "psm_field_reset");
@@ -569,6 +571,11 @@ int psm_field_reset(psm_field *f, void *stream) {
   f->nb_mapped = f->nb_mappedx = 0;
   f->map_parity = 0;
   f->ahead_valid = false;
+  if (f->cfg.map_ahead && (void *)f->B0 != f->bbase) {  // back to the first set as the current one
+    std::swap(f->B0, f->B0x);
+    std::swap(f->B1, f->B1x);
+    std::swap(f->meta, f->metax);
+  }
   for (int i = 0; i < PSM_MAX_BODIES; ++i) {
     f->have_prev[i] = f->have_prevx[i] = false;
     f->active[i] = f->activex[i] = empty_box();

@@ -257,6 +257,7 @@ struct psm_field {
   // launch, forked from and joined back into the caller's stream by events
   hipStream_t side;
   hipEvent_t ev_fork, ev_join;
+  void *bbase;  // start of the fractions buffer (both sets with map_ahead)
   // map_ahead: the other set of fractions and its mapping state (swapped with
   // the current one by psm_step_ahead), the stream that maps into it, and
   // the step it holds when ahead_valid

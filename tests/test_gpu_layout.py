@@ -349,3 +349,32 @@ def test_map_ahead_refused_without_second_set(sim):
     g = sim.Field(wl, map_ahead=True)
     assert capi.lib.psm_step_ahead(g.handle, p0, p0, None, g._geom_ptrs, g.nb, 0, None, None) == capi.PSM_EINVAL
     assert g.bbuf.numel() >= 2 * (wl.n_cells * 5)
+
+
+def test_map_ahead_reset_clears_both_sets(sim, gc):
+    """After an even number of psm_step_ahead calls the second set of
+    fractions is the current one; psm_field_reset clears the whole fractions
+    buffer (both sets) and makes the first set current again; the next run
+    equals a fresh field's bit for bit."""
+    import torch
+
+    wl = _blocked(_small(19, "f32", ("periodic",) * 6, two=True, sc=2))
+    f = sim.Field(wl, map_ahead=True)
+    for t in range(2):
+        f.step(t)
+    f.reset()
+    torch.cuda.synchronize()
+    assert int(f.bbuf.count_nonzero().item()) == 0
+    B, _ = f.b_view()
+    assert B.data_ptr() == f.bbuf.data_ptr()
+    gc.load_random_state(f, 4)
+    for t in range(3):
+        f.step(t)
+    torch.cuda.synchronize()
+    g = sim.Field(wl, map_ahead=True)
+    gc.load_random_state(g, 4)
+    for t in range(3):
+        g.step(t)
+    torch.cuda.synchronize()
+    assert torch.equal(f.pdf_std(), g.pdf_std())
+    assert torch.equal(f.b_view()[0], g.b_view()[0])
