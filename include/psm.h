@@ -208,7 +208,12 @@ int psm_body_pose(const psm_motion *m, int64_t step, psm_body *out);
 /* Validates cfg and the caller buffers (sizes from psm_required_bytes; the
  * B buffer may be NULL when cfg->psm == 0) and records them.  Clears the
  * first 256 bytes of the work buffer (flags, counters) on `stream`; the PDFs
- * and B are not touched: call psm_field_reset before the first step. */
+ * and B are not touched: call psm_field_reset before the first step.  Also
+ * makes the field's own streams (default priority, non-blocking; they are
+ * synchronised and destroyed by pdf_field_destroy): one for the solid-cell
+ * and face-row launches (PSM_OPT_CONCURRENT) and, with map_ahead, one for
+ * the mapping; if they cannot be made the field runs on the caller's
+ * stream. */
 int pdf_field_create(const psm_config *cfg, void *pdf_dev, size_t pdf_bytes, void *b_dev,
                      size_t b_bytes, void *work_dev, size_t work_bytes, void *stream,
                      psm_field **out);
@@ -490,7 +495,7 @@ int psm_error_flags(psm_field *f, int32_t *out_dev, void *stream);
  *                             second stream of the field (default priority,
  *                             made at pdf_field_create), beside the interior
  *                             launch on the caller's stream, which waits for
- *                             them before the call returns its later work;
+ *                             them before any later work on it;
  *                             0: all on the caller's stream.  Results are
  *                             bitwise identical.  Fields made by
  *                             pdf_field_create_noalloc have no second stream
