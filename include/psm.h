@@ -337,7 +337,9 @@ int psm_step(psm_field *f, const psm_body *map_poses, const psm_body *bodies, co
  * overlaps the step's launches.
  * The results equal psm_step(map_poses, bodies, step) bit for bit, provided
  * next_map_poses are the map poses of the next call.  PSM_EUNSUP without
- * map_ahead; fields from pdf_field_create_noalloc map on `stream`. */
+ * map_ahead; fields from pdf_field_create_noalloc map on `stream`.  Which set
+ * a call reads is host state, so a captured graph would replay one call's
+ * choice every time: capture psm_step instead. */
 int psm_step_ahead(psm_field *f, const psm_body *map_poses, const psm_body *bodies, const psm_body *next_map_poses,
                    const psm_geom *const *geoms, int n_bodies, int64_t step, double *ft_dev, void *stream);
 
