@@ -278,6 +278,7 @@ def test_new_entry_points_reject_null_arguments(capi, sim):
     s = capi.psm_rigid()
     assert capi.lib.psm_rigid_advance(C.byref(s), None, 1.0) == capi.PSM_EINVAL
     assert capi.lib.psm_step_ahead(None, None, None, None, None, 1, 0, None, None) == capi.PSM_EINVAL
+    assert capi.lib.psm_adjoint_gather(None, None, None, None) == capi.PSM_EINVAL
     assert capi.lib.psm_fractions(None, None, None, None) == capi.PSM_EINVAL
     # map_ahead needs a PSM field
     cfg.psm, cfg.map_ahead = 0, 1
