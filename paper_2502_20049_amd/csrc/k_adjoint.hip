@@ -67,7 +67,7 @@ __device__ __forceinline__ void cacc(R &vx, R &vy, R &vz, R k) {
 //
 // One cell: x per lane, the row (y, z) shared by the wave.  Returns the
 // cell's dJ/dOmega term.
-template <int Q, typename T, int PAR, bool O32>
+template <int Q, typename T, int PAR, bool O32, bool FRC>
 __device__ __forceinline__ double adjoint_cell(const AdjArgs &A, uint32_t row, uint32_t yy, uint32_t zz,
                                                uint32_t xx) {
   using R = typename Comp<T>::type;
@@ -153,10 +153,12 @@ __device__ __forceinline__ double adjoint_cell(const AdjArgs &A, uint32_t row, u
     cacc<cx<Q>(i), cy<Q>(i), cz<Q>(i)>(jx, jy, jz, d[i] - d[ib]);
   });
   const R rho = R(1) + drho, ir = R(1) / rho;
-  const R Fx = (R)a.force[0], Fy = (R)a.force[1], Fz = (R)a.force[2];
-  const R ux = (jx + R(0.5) * Fx) * ir, uy = (jy + R(0.5) * Fy) * ir, uz = (jz + R(0.5) * Fz) * ir;
+  // FRC = false: no body force, its terms dropped at compile time
+  const R Fx = FRC ? (R)a.force[0] : R(0), Fy = FRC ? (R)a.force[1] : R(0), Fz = FRC ? (R)a.force[2] : R(0);
+  const R ux = FRC ? (jx + R(0.5) * Fx) * ir : jx * ir, uy = FRC ? (jy + R(0.5) * Fy) * ir : jy * ir,
+          uz = FRC ? (jz + R(0.5) * Fz) * ir : jz * ir;
   const R Frx = Fx * ir, Fry = Fy * ir, Frz = Fz * ir;
-  const R usq = ux * ux + uy * uy + uz * uz, uF = ux * Fx + uy * Fy + uz * Fz;
+  const R usq = ux * ux + uy * uy + uz * uz, uF = FRC ? ux * Fx + uy * Fy + uz * Fz : R(0);
   const R B = solid_fraction<R>(a, n), fl = R(1) - B;
   const double rx = x + 0.5 - A.X[0], ry = y + 0.5 - A.X[1], rz = z + 0.5 - A.X[2];
   const R usx = (R)(A.V[0] + (A.W[1] * rz - A.W[2] * ry));
@@ -175,7 +177,7 @@ __device__ __forceinline__ double adjoint_cell(const AdjArgs &A, uint32_t row, u
   {
     const R w0 = (R)wt<Q>(0);
     const R fe = d[0] - w0 * (drho - rho * R(1.5) * usq);
-    const R OF = -le * fe - ge * R(3) * w0 * uF;
+    const R OF = FRC ? -le * fe - ge * R(3) * w0 * uF : -le * fe;
     const R OS = -w0 * rho * dus;
     Wg = w0 * gh[0];
     dJ = R(0.5) * gh[0] * (OS - OF);
@@ -188,32 +190,41 @@ __device__ __forceinline__ double adjoint_cell(const AdjArgs &A, uint32_t row, u
     const R gp = R(0.5) * (gh[i] + gh[ib]), gm = R(0.5) * (gh[i] - gh[ib]);
     const R dp = R(0.5) * (d[i] + d[ib]), dm = R(0.5) * (d[i] - d[ib]);
     const R cu = cdot<ex, ey, ez>(ux, uy, uz), cs = cdot<ex, ey, ez>(usx, usy, usz);
-    const R cF = cdot<ex, ey, ez>(Fx, Fy, Fz), cFr = cdot<ex, ey, ez>(Frx, Fry, Frz);
+    const R cF = FRC ? cdot<ex, ey, ez>(Fx, Fy, Fz) : R(0), cFr = FRC ? cdot<ex, ey, ez>(Frx, Fry, Frz) : R(0);
     const R m = cdot<ex, ey, ez>(arx, ary, arz);
     const R cu2 = cu * cu, cs2 = cs * cs;
     // TRT + Guo (even / odd parts) and SC1 collision of the pair
     const R fpe = dp - wi * (drho + rho * (R(4.5) * cu2 - R(1.5) * usq));
     const R fme = dm - R(3) * wi * rho * cu;
-    const R OFp = -le * fpe + ge * wi * (R(9) * cu * cF - R(3) * uF);
-    const R OFm = -lo * fme + go * R(3) * wi * cF;
+    const R OFp = FRC ? -le * fpe + ge * wi * (R(9) * cu * cF - R(3) * uF) : -le * fpe;
+    const R OFm = FRC ? -lo * fme + go * R(3) * wi * cF : -lo * fme;
     const R OSp = wi * rho * (R(4.5) * (cs2 - cu2) - dus);
     const R OSm = R(-2) * dm + R(3) * wi * rho * (cu + cs);
     const R qm = gm - wtt * m;
     dJ += gp * (OSp - OFp) + qm * OSm - gm * OFm;
     const R shp = B * gp, shm = B * qm;
-    const R kap = wi * (fl * (R(6) * lo * gm + R(18) * gp * (le * cu + ge * cFr)) + R(6) * shm - R(18) * shp * cu);
+    const R kap = wi * (fl * (R(6) * lo * gm + R(18) * gp * (FRC ? le * cu + ge * cFr : le * cu)) + R(6) * shm -
+                        R(18) * shp * cu);
     cacc<ex, ey, ez>(Vx, Vy, Vz, kap);
-    C0 += wi * (R(9) * shp * (cu2 + cs2) + R(6) * shm * cs - fl * gp * cu * (R(9) * le * cu + R(18) * ge * cFr));
+    C0 += wi * (R(9) * shp * (cu2 + cs2) + R(6) * shm * cs -
+                fl * gp * cu * (FRC ? R(9) * le * cu + R(18) * ge * cFr : R(9) * le * cu));
     dS += wi * (R(6) * shm + R(18) * shp * cs) * m;
     Wg2 += wi * gp;
   });
   Wg += R(2) * Wg2;
   const R Ws = B * Wg;
-  C0 += fl * Wg * (le * (R(1) + R(1.5) * usq) + R(3) * ge * (Frx * ux + Fry * uy + Frz * uz)) -
-        R(1.5) * (usq + uss) * Ws;
-  Vx -= R(3) * (fl * Wg * (le * ux + ge * Frx) - ux * Ws);
-  Vy -= R(3) * (fl * Wg * (le * uy + ge * Fry) - uy * Ws);
-  Vz -= R(3) * (fl * Wg * (le * uz + ge * Frz) - uz * Ws);
+  if constexpr (FRC) {
+    C0 += fl * Wg * (le * (R(1) + R(1.5) * usq) + R(3) * ge * (Frx * ux + Fry * uy + Frz * uz)) -
+          R(1.5) * (usq + uss) * Ws;
+    Vx -= R(3) * (fl * Wg * (le * ux + ge * Frx) - ux * Ws);
+    Vy -= R(3) * (fl * Wg * (le * uy + ge * Fry) - uy * Ws);
+    Vz -= R(3) * (fl * Wg * (le * uz + ge * Frz) - uz * Ws);
+  } else {
+    C0 += fl * Wg * (le * (R(1) + R(1.5) * usq)) - R(1.5) * (usq + uss) * Ws;
+    Vx -= R(3) * (fl * Wg * (le * ux) - ux * Ws);
+    Vy -= R(3) * (fl * Wg * (le * uy) - uy * Ws);
+    Vz -= R(3) * (fl * Wg * (le * uz) - uz * Ws);
+  }
   *O(0) = gh[0] - fl * le * gh[0] + C0;
   sfor<H>([&](auto P) {
     constexpr int i = P + 1, ib = opp<Q>(i);
@@ -232,8 +243,12 @@ __device__ __forceinline__ double adjoint_cell(const AdjArgs &A, uint32_t row, u
 
 // One wave per work unit of up to 64 cells of one row (ceil(nx / 64) units
 // per row); one FP64 dJ/dOmega partial per workgroup.
-template <int Q, typename T, int PAR, bool O32>
-__global__ __launch_bounds__(256) void k_adjoint(const AdjArgs A) {
+// Without body force the FP32-arithmetic D3Q19 kernels fit five waves per
+// SIMD (100 -> 96 VGPRs, 8-12 bytes of spills per lane; 128^3 rotor backward
+// 0.130 -> 0.120 s); the others keep the compiler's choice.
+template <int Q, typename T, int PAR, bool O32, bool FRC>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((Q == 19 && !FRC && sizeof(T) <= 4) ? 5 : 1, 8))) void
+k_adjoint(const AdjArgs A) {
   const SCArgs &a = A.s;
   const uint32_t nx = (uint32_t)a.nx, ny = (uint32_t)a.ny;
   const uint32_t segs = (nx + 63u) >> 6, units = ny * (uint32_t)a.nz * segs;
@@ -242,7 +257,7 @@ __global__ __launch_bounds__(256) void k_adjoint(const AdjArgs A) {
   if (u < units) {
     const uint32_t row = u / segs, xx = (u - row * segs) * 64u + (threadIdx.x & 63u);
     const uint32_t zz = row / ny, yy = row - zz * ny;
-    if (xx < nx) dom = adjoint_cell<Q, T, PAR, O32>(A, row, yy, zz, xx);
+    if (xx < nx) dom = adjoint_cell<Q, T, PAR, O32, FRC>(A, row, yy, zz, xx);
   }
   __shared__ double sh4[4];
   double v = wave_sum(dom);
@@ -251,16 +266,19 @@ __global__ __launch_bounds__(256) void k_adjoint(const AdjArgs A) {
   if (threadIdx.x == 0) A.part[blockIdx.x] = ((sh4[0] + sh4[1]) + sh4[2]) + sh4[3];
 }
 
-template <int Q, typename T, bool O32>
+template <int Q, typename T, bool O32, bool FRC>
 static void go_adjoint(const AdjArgs &A, dim3 g, hipStream_t st) {
-  if (A.parity == 0) hipLaunchKernelGGL((k_adjoint<Q, T, 0, O32>), g, dim3(256), 0, st, A);
-  else hipLaunchKernelGGL((k_adjoint<Q, T, 1, O32>), g, dim3(256), 0, st, A);
+  if (A.parity == 0) hipLaunchKernelGGL((k_adjoint<Q, T, 0, O32, FRC>), g, dim3(256), 0, st, A);
+  else hipLaunchKernelGGL((k_adjoint<Q, T, 1, O32, FRC>), g, dim3(256), 0, st, A);
 }
 
 template <int Q, typename T>
 static void go_adjoint(const AdjArgs &A, dim3 g, hipStream_t st) {
-  if (A.o32) go_adjoint<Q, T, true>(A, g, st);
-  else go_adjoint<Q, T, false>(A, g, st);
+  const bool frc = A.s.force[0] != 0.0 || A.s.force[1] != 0.0 || A.s.force[2] != 0.0;
+  if (A.o32 && frc) go_adjoint<Q, T, true, true>(A, g, st);
+  else if (A.o32) go_adjoint<Q, T, true, false>(A, g, st);
+  else if (frc) go_adjoint<Q, T, false, true>(A, g, st);
+  else go_adjoint<Q, T, false, false>(A, g, st);
 }
 
 hipError_t launch_adjoint(const psm_field &f, const AdjArgs &A, hipStream_t st) {
